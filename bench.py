@@ -1,0 +1,185 @@
+#!/usr/bin/env python
+"""Throughput of the particle hot path on one MI355X.
+
+Workload (default): the 3D3V shearing box, 256^3 Yee cells, 8 particles per cell per species
+(e+ and e-, 268,435,456 particles), Maxwell-Juttner theta = 0.3, skin depth 4 cells, weak
+B0 along z with sigma = 0.05, Keplerian shear q = 1.5, Omega0/omega_c = 0.05, dt = 0.45,
+FP32 particles (int32 cell + FP32 offset) with FP64 shear offset.  Synthetic seeded inputs.
+
+One step = tile sort + fused gather/push/deposit + current fold with the J' transport +
+implicit-midpoint Maxwell (fixed-point sweeps) + guard fills, i.e. the whole hot path.
+value = particles x steps / wall time of the timed steps (particle-steps/s).
+The fused push kernel is timed with HIP events on the box stream for the roofline line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def workload_shear3d(n=256, ppc=8):
+    from paper_2602_15939_amd import synth
+
+    wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.05)
+    return dict(name=f"shear3d_{n}^3_ppc{ppc}", dim=3, n=(n, n, n), ppc=ppc, theta=0.3, q=q,
+                B0=B0, shear_s=1.5, omega0=0.05 * B0, dt=0.45, maxwell_iters=8)
+
+
+def make_box(w, seed, device="cuda"):
+    import torch
+
+    from paper_2602_15939_amd import _lib as L
+    from paper_2602_15939_amd import synth
+    from paper_2602_15939_amd.box import Box
+
+    count = w["ppc"] * math.prod(w["n"])
+    box = Box(w["dim"], w["n"], dt=w["dt"], frame=L.FRAME_SHEAR,
+              species=[(-1.0, -w["q"], count), (1.0, w["q"], count)], shear_s=w["shear_s"],
+              shear_omega0=w["omega0"], seed=seed, maxwell_iters=w["maxwell_iters"])
+    E, B = synth.uniform_field(w["n"], 2, w["B0"])
+    box.set_fields(torch.from_numpy(E).float(), torch.from_numpy(B).float())
+    parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], seed, device=device)
+    for s, p in enumerate(parts):
+        box.set_particles(s, p["cell"], p["off"], p["u"])
+    del parts
+    torch.cuda.synchronize()
+    return box, 2 * count
+
+
+def algorithmic_bytes(w, nparticles):
+    """Bytes the fused gather/push/deposit must move per launch: particle state read + write
+    (int32 cell + 3 FP32 offsets + 3 FP32 momenta = 28 B each way), the sort permutation
+    (4 B), the six field components read once (24 B/cell) and the current read-modify-write
+    (24 B/cell)."""
+    ncell = math.prod(w["n"])
+    return nparticles * (28 + 28 + 4) + ncell * (24 + 24)
+
+
+def cpu_baseline(seconds=12.0):
+    """The FP64 oracle, unchanged, on the host cores: a 32^3 sample of the same workload
+    (same ppc, theta, sigma, shear), stepped until ~seconds have elapsed."""
+    import numpy as np
+
+    import oracle
+    from paper_2602_15939_amd import synth
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    w = workload_shear3d(n=32)
+    parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], 99, device="cpu")
+    box = oracle.make_box(3, w["n"], dt=w["dt"], frame=oracle.SHEAR, shear_s=w["shear_s"],
+                          omega0=w["omega0"], maxwell_iters=w["maxwell_iters"])
+    E, B = synth.uniform_field(w["n"], 2, w["B0"])
+    J = np.zeros_like(E)
+    sp = []
+    for s, p in enumerate(parts):
+        c = p["cell"].numpy().astype(np.int64)
+        off = p["off"].numpy().astype(np.float64)
+        n = w["n"]
+        x = c % n[0] + off[0]
+        y = (c // n[0]) % n[1] + off[1]
+        z = c // (n[0] * n[1]) + off[2]
+        u = p["u"].numpy().astype(np.float64)
+        qm = (-1.0, 1.0)[s]
+        sp.append(oracle.SpeciesState(x, y, z, u[0], u[1], u[2], qm, qm * w["q"]))
+    npart = sum(len(s.x) for s in sp)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.step(box, E, B, J, sp, nthreads=cores)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds or steps >= 200:
+            break
+    return dict(value=npart * steps / el, unit="particle-steps/s", cores=cores, kind="oracle",
+                sample=f"32^3 shearing box, 8 ppc/species ({npart} particles), {steps} full "
+                       f"steps in {el:.1f} s, OpenMP over particles")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=20260216)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: every box of this build lives on a single MI355X; "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2602_15939_amd import _lib as L
+
+    w = workload_shear3d(n=args.n)
+    print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
+    box, npart = make_box(w, args.seed)
+    h = [box.h]
+    st = torch.cuda.current_stream()
+
+    def one_step(ev=None):
+        L.pic_tile_sort(h)
+        if ev is not None:
+            ev[0].record(st)
+        L.pic_gather_push(h, L.FUSE_DEPOSIT)
+        if ev is not None:
+            ev[1].record(st)
+        L.pic_shear_remap(h, L.REMAP_CURRENT)
+        L.pic_maxwell_step(h)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step(evs[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpd_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    info = box.info()
+    assert info.errors & ~L.DERR_ORDER == 0, f"device error bits {info.errors}"
+    value = npart * args.steps / el
+    nbytes = algorithmic_bytes(w, npart)
+    achieved = nbytes / (gpd_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s (gather+push+deposit) & HBM %peak",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "particles": npart, "frame": "shearing box",
+                   "theta": w["theta"], "sigma": 0.05, "q": 1.5, "omega0_over_wc": 0.05,
+                   "dt": w["dt"], "maxwell_iters": w["maxwell_iters"],
+                   "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": npart / (gpd_ms * 1e-3)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    box.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * pic.h — C ABI of the MI355X particle hot path for the extended particle-in-cell
+ * methods of Bacchini et al., "Particle-in-Cell Methods for Simulations of Sheared,
+ * Expanding, or Escaping Astrophysical Plasma" (arXiv 2602.15939):
+ *   the shearing box with orbital advection (Sec. 2), the expanding box (Sec. 3)
+ *   and the leaky box (Sec. 4), on a Yee grid with charge-conserving deposition.
+ *
+ * Conventions (every call):
+ *   - code units: c = 1, cell size dx = 1, Gaussian units with an explicit 4*pi;
+ *   - return value: PIC_OK (0) or a negative pic_status; nothing throws or aborts;
+ *   - all device work is asynchronous on the box stream (desc.stream, a hipStream_t;
+ *     NULL = the null stream) unless the call says it synchronises;
+ *   - a box owns its device memory (allocated in pic_box_create, freed in
+ *     pic_box_destroy).  Pointers passed in or out are caller-owned; a pointer argument
+ *     named *_dev must be device memory, *_host host memory;
+ *   - handles are not thread-safe; calls on one box must not overlap;
+ *   - fields are stored as the frame's evolved variables: E' and B for the shearing box
+ *     (Sec. 2.1), lab-frame E and B at the primed coordinates for the expanding box
+ *     (Sec. 3.2), E and B otherwise;
+ *   - grid layout at the boundary: one component array holds n[0]*n[1]*n[2] floats,
+ *     x fastest; the Yee offsets (cells) are Ex(1/2,0,0) Ey(0,1/2,0) Ez(0,0,1/2),
+ *     Bx(0,1/2,1/2) By(1/2,0,1/2) Bz(1/2,1/2,0), J as E; in 2D n[2] = 1;
+ *   - particle layout at the boundary (structure of arrays): cell[n] int32 linear cell
+ *     index i + n0*(j + n1*k); off[dim][n] float in-cell offsets in [0,1); u[3][n] float
+ *     spatial part of the four-velocity (u' in the shearing box, Sec. 2.1); id[n] uint32;
+ *     dr[3][n] float leaky-box displacement (Sec. 4.1).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pic_status {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,  /* invalid argument (unsupported combination, CFL, null pointer) */
+    PIC_ENOMEM = -2,  /* device allocation failed */
+    PIC_EDEVICE = -3, /* a HIP call failed */
+    PIC_ESTATE = -4,  /* call not valid in the box's current state */
+    PIC_ECAP = -5     /* particle count above the species capacity */
+} pic_status;
+
+enum pic_frame { PIC_FRAME_PLAIN = 0, PIC_FRAME_SHEAR = 1, PIC_FRAME_EXPAND = 2, PIC_FRAME_LEAKY = 3 };
+enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
+
+/* pic_gather_push flags */
+#define PIC_FUSE_DEPOSIT 1u /* deposit the current inside the push kernel (the hot path) */
+/* pic_shear_remap selection */
+#define PIC_REMAP_FIELDS 1u
+#define PIC_REMAP_CURRENT 2u
+/* pic_box_desc.flags */
+#define PIC_BOX_TRACK_IDS 1u /* carry particle ids through the sort (always on for LEAKY) */
+
+/* sticky device error bits (pic_box_info.errors) */
+#define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell */
+#define PIC_DERR_NAN 2u      /* non-finite momentum */
+#define PIC_DERR_ORDER 4u    /* a particle outside its tile: handled on the slow path */
+
+typedef struct pic_box_desc {
+    int32_t dim;         /* 2 or 3 */
+    int32_t n[3];        /* cells per axis (n[2] = 1 in 2D); n[0]*n[1]*n[2] < 2^31 */
+    double dt;           /* time step; requires dt*sqrt(dim) < 1 (Yee CFL) */
+    int32_t frame;       /* enum pic_frame */
+    /* shearing box (Sec. 2.1): v_s = -s*Omega0*x e_y, x = X - n[0]/2 */
+    double shear_s, shear_omega0;
+    /* expanding box (Sec. 3.1): l_d(t) = 1 + expand_adot*t on the axes in expand_axis_mask */
+    double expand_adot;
+    int32_t expand_axis_mask;
+    /* leaky box (Sec. 4.1) */
+    int32_t leaky_mode;      /* enum pic_leaky_mode */
+    double leaky_l_esc;      /* displacement mode: escape distance */
+    int32_t leaky_use_3vec;  /* displacement mode: test (dx, dy, dz) instead of (dx, dy) */
+    double leaky_theta_inj;  /* displacement mode: Maxwell-Juttner temperature of reinjection */
+    double leaky_t_esc;      /* probabilistic mode: escape probability dt/t_esc per step ... */
+    double leaky_gamma_thr;  /* ... for particles with gamma > gamma_thr */
+    /* species */
+    int32_t n_species;       /* 1 or 2 */
+    double q_over_m[2];      /* charge-to-mass ratio (sign included) */
+    double q_macro[2];       /* macro-particle charge (sign included) */
+    int64_t capacity[2];     /* maximum particle count per species */
+    uint64_t seed;           /* Philox4x32-10 key */
+    uint32_t box_id;         /* fourth Philox counter word */
+    int32_t tile[3];         /* tile shape in cells (0 = default: 8^3 in 3D, 16x16 in 2D) */
+    int32_t maxwell_iters;   /* shearing box: fixed-point iterations per step (0 = 8) */
+    uint32_t flags;          /* PIC_BOX_* */
+    void* stream;            /* hipStream_t */
+} pic_box_desc;
+
+typedef struct pic_box pic_box;
+
+typedef struct pic_box_info {
+    int64_t step;            /* steps taken */
+    double t;                /* t^n = step*dt */
+    double dys;              /* shearing box: Delta y_s(t) reduced mod n[1] (Sec. 2.1) */
+    double a;                /* expanding box: l(t) of the expanding axes */
+    int64_t n_particles[2];  /* live particles per species */
+    uint32_t errors;         /* sticky PIC_DERR_* bits */
+    int64_t n_slow;          /* particles handled outside their tile (counter) */
+    int64_t n_escaped;       /* probabilistic escapes (counter) */
+    /* FP64 reductions: sum E_c^2/8pi, sum B_c^2/8pi (c = x,y,z), kinetic energy
+       sum m(gamma-1), momentum sum m u */
+    double field_energy_E[3], field_energy_B[3];
+    double kinetic_energy;
+    double momentum[3];
+} pic_box_info;
+
+/* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard
+   cells, the ping-pong particle arrays of the given capacities and the sort workspace
+   (PIC_ENOMEM).  Fields start at zero and the box holds no particles.  *out is set only
+   on success. */
+int32_t pic_box_create(const pic_box_desc* desc, pic_box** out);
+
+/* Free the box and its device memory (synchronises the box stream).  NULL is accepted. */
+int32_t pic_box_destroy(pic_box* box);
+
+/* Copy fields in or out: E_dev/B_dev/J_dev hold 3 component arrays of n0*n1*n2 floats.
+   pic_set_fields also fills the guard cells at the current time. */
+int32_t pic_set_fields(pic_box* box, const float* E_dev, const float* B_dev);
+int32_t pic_get_fields(pic_box* box, float* E_dev, float* B_dev);
+/* the current of the last step (J' for the shearing box, l J' for the expanding box, Sec. 3.1),
+   after the guard fold and (shearing box) the J' transport of Sec. 2.2 */
+int32_t pic_get_current(pic_box* box, float* J_dev);
+
+/* Load n particles of one species (layout above; id_dev NULL -> ids 0..n-1, dr_dev NULL -> 0)
+   and tile-sort them.  PIC_ECAP if n exceeds the capacity, PIC_EINVAL on a bad species. */
+int32_t pic_set_particles(pic_box* box, int32_t species, int64_t n, const int32_t* cell_dev,
+                          const float* off_dev, const float* u_dev, const uint32_t* id_dev,
+                          const float* dr_dev);
+/* Copy the live particles of one species out in the box's current order (synchronises).
+   *n_out receives the count; the arrays must hold pic_box_info.n_particles values.
+   Any output pointer may be NULL. */
+int32_t pic_get_particles(pic_box* box, int32_t species, int64_t* n_out, int32_t* cell_dev,
+                          float* off_dev, float* u_dev, uint32_t* id_dev, float* dr_dev);
+/* The permutation of the last tile sort: perm_dev[i] = index, in the order before that sort,
+   of the particle in sorted position i (live particles only); offsets_dev receives the
+   n_tiles+1 tile offsets.  Synchronises. */
+int32_t pic_get_sort(pic_box* box, int32_t species, int32_t* perm_dev, int32_t* offsets_dev,
+                     int32_t* n_tiles_out);
+
+/* ---- the hot path (each call acts on nb boxes; nb = 1 is the single-box case) ---- */
+
+/* Tile counting sort (stable): key = tile of the particle's cell, dead particles go to a
+   dead bin and are dropped.  Produces the permutation used by the next pic_gather_push and
+   the per-tile offsets. */
+int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* Field gather at x^n, push u^{n-1/2} -> u^{n+1/2} with the frame's pusher (Boris;
+   the shearing-box operator of Sec. 2.2, eq. OAu_disc; the expanding-box operator of
+   Sec. 3.2, eq. EBu_disc), position update (Secs. 2.2, 3.2) with the boundary conditions
+   (shearing-periodic x, Sec. 2.1), leaky-box displacement and escape test (Sec. 4.1 or the
+   probabilistic rule).  With PIC_FUSE_DEPOSIT it also deposits the charge-conserving
+   current (Esirkepov) into the box current; without it the old positions are kept for
+   pic_deposit.  Requires a pic_tile_sort since the last push. */
+int32_t pic_gather_push(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* Charge-conserving current of the last unfused pic_gather_push (PIC_ESTATE otherwise). */
+int32_t pic_deposit(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* PIC_REMAP_CURRENT: fold the current guard cells (periodic, or shearing-periodic with
+   Delta y_s(t^{n+1/2})) after the J' transport of Sec. 2.2 along y by v_{s,y} dt/2.
+   PIC_REMAP_FIELDS: fill the field guard cells at the current time.  Plain periodic
+   folding/filling for non-shear frames. */
+int32_t pic_shear_remap(pic_box* const* boxes, int32_t nb, uint32_t what);
+
+/* One Maxwell step of the box frame: Yee leapfrog (plain, leaky), Yee with the scale
+   factors of Sec. 3.2 (expanding), implicit midpoint with upwinded advection solved by
+   fixed-point iteration (shearing box, Sec. 2.2).  Advances the box time by dt. */
+int32_t pic_maxwell_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* Escape compaction: the tile sort with the dead bin, which removes the particles marked
+   by the probabilistic escape, and the survivor count (read with pic_box_get). */
+int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* One whole step: sort, fused gather-push-deposit, current fold, Maxwell, field guards. */
+int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */
+int32_t pic_box_get(pic_box* box, pic_box_info* info);
+
+/* Static description of a pic_status. */
+const char* pic_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -184,6 +184,15 @@ def step(box: Box, E, B, J, species, nthreads: int = 1) -> None:
     assert rc == 0
 
 
+def particles_only(box: Box, E, B, species) -> None:
+    """gather + push + move (+ leaky escape) of the species, without deposit or Maxwell"""
+    J = np.zeros(field_shape(box))
+    f = _fields(E, B, J)
+    arr = (Species * len(species))(*[s.cstruct() for s in species])
+    rc = lib().ora_particles_only(C.byref(box), C.byref(f), arr, len(species))
+    assert rc == 0
+
+
 def gather(box: Box, E, B, x, y, z=None, dys=0.0):
     n = len(x)
     Eo, Bo = np.zeros((n, 3)), np.zeros((n, 3))

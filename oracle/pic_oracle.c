@@ -777,8 +777,8 @@ void ora_ksb_rhs(const ora_box* b, double* const E[3], double* const B[3], doubl
 /* Sec. 2.2: implicit midpoint in time, F^{n+1} = F^n + dt RHS((F^n + F^{n+1})/2, J'),
    solved by the fixed-point iteration F^{k+1} = F^n + dt RHS((F^n + F^k)/2) from F^0 = F^n.
    reading: a fixed number of iterations (maxwell_iters), or, with maxwell_tol > 0, until
-   max|F^{k+1} - F^k| <= tol max|F^{k+1}| (at most maxwell_iters).  The x guards of F^n use
-   Delta y_s(t^n) and those of the iterate Delta y_s(t^{n+1}). */
+   max|F^{k+1} - F^k| <= tol max|F^{k+1}| (at most maxwell_iters).  The x guards of F^n (and of
+   F^0 = F^n) use Delta y_s(t^n), those of every later iterate Delta y_s(t^{n+1}). */
 static void maxwell_ksb(ora_box* b, ora_fields* f)
 {
     const int64_t nc = ncells(b);
@@ -805,7 +805,8 @@ static void maxwell_ksb(ora_box* b, ora_fields* f)
             Ea[c].a = Fn + (3 + c) * nc;
             Ea[c].c = Fk + (3 + c) * nc;
             Ba[c].dys_a = Ea[c].dys_a = dys_n;
-            Ba[c].dys_c = Ea[c].dys_c = dys_1;
+            /* F^0 = F^n keeps its own boundary values; later iterates sit at t^{n+1} */
+            Ba[c].dys_c = Ea[c].dys_c = it == 0 ? dys_n : dys_1;
             Ba[c].wa = Ba[c].wc = Ea[c].wa = Ea[c].wc = 0.5;
         }
         ksb_rhs_acc(b, Ea, Ba, f->J, outp);
@@ -1056,33 +1057,139 @@ static inline double wrapd(double v, int n)
     return v;
 }
 
-/* Step orders: Sec. 2.2 (shearing box), Sec. 3.2 (expanding box), Sec. 4.1 (leaky box),
-   standard PIC otherwise:
-     gather at x^n -> push -> deposit displacement (x' - x^n for the shearing box, the
-     primed displacement for the expanding box) -> shear move and boundaries -> leaky-box
-     displacement update and escape -> current finalisation -> Maxwell. */
-int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
+/* Per-step scalars of the particle update. */
+typedef struct {
+    double dt, dys_n, dys_1, sO;
+    double lam[3], linv_h[3];
+    uint32_t esc_thr;
+    double g2thr;
+    uint32_t key[2];
+} step_scalars;
+
+static void make_scalars(const ora_box* b, step_scalars* S)
 {
-    const int nd = b->dim;
-    const int nx = b->n[0];
     const double dt = b->dt;
     const double tn = (double)b->step * dt, th = tn + 0.5 * dt, t1 = tn + dt;
-    const double dys_n = ora_shear_offset(b, tn), dys_1 = ora_shear_offset(b, t1);
-    const double sO = b->shear_s * b->omega0;
-    double lam[3], linv_h[3];
+    S->dt = dt;
+    S->dys_n = ora_shear_offset(b, tn);
+    S->dys_1 = ora_shear_offset(b, t1);
+    S->sO = b->shear_s * b->omega0;
     for (int d = 0; d < 3; d++) {
-        lam[d] = -0.5 * dt * scale_rate(b, d) / ora_scale(b, d, tn); /* Lambda at t^n */
-        linv_h[d] = 1.0 / ora_scale(b, d, th);                        /* (L^-1)^{n+1/2} */
+        S->lam[d] = -0.5 * dt * scale_rate(b, d) / ora_scale(b, d, tn); /* Lambda at t^n */
+        S->linv_h[d] = 1.0 / ora_scale(b, d, th);                      /* (L^-1)^{n+1/2} */
     }
-    uint32_t esc_thr = 0;
+    S->esc_thr = 0;
     if (b->frame == ORA_LEAKY && b->leaky_mode == ORA_LEAKY_PROBABILISTIC) {
         double p = b->t_esc > 0 ? dt / b->t_esc : 0.0;
         double th32 = floor(p * 4294967296.0);
-        esc_thr = th32 >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th32;
+        S->esc_thr = th32 >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th32;
     }
-    const double g2thr = b->gamma_thr * b->gamma_thr - 1.0;
-    const uint32_t key[2] = {(uint32_t)b->seed, (uint32_t)(b->seed >> 32)};
+    S->g2thr = b->gamma_thr * b->gamma_thr - 1.0;
+    S->key[0] = (uint32_t)b->seed;
+    S->key[1] = (uint32_t)(b->seed >> 32);
+}
 
+/* One particle of the step orders of Sec. 2.2 (shearing box), Sec. 3.2 (expanding box),
+   Sec. 4.1 (leaky box) and standard PIC: gather at x^n -> push -> deposit displacement
+   (x' - x^n for the shearing box, the primed displacement for the expanding box; deposited
+   when Jt is not NULL) -> shear move and boundaries -> leaky-box displacement and escape. */
+static void particle_update(const ora_box* b, const ora_fields* f, const step_scalars* C,
+                            ora_species* S, int64_t p, double* Jt)
+{
+    const int nd = b->dim;
+    const int nx = b->n[0];
+    const double dt = C->dt;
+    double X0[3] = {S->x[p], S->y[p], nd == 3 ? S->z[p] : 0.0};
+    double E[3], B[3];
+    for (int c = 0; c < 3; c++) {
+        E[c] = interp(b, f->E[c], STAG_E[c], X0[0], X0[1], X0[2], C->dys_n);
+        B[c] = interp(b, f->B[c], STAG_B[c], X0[0], X0[1], X0[2], C->dys_n);
+    }
+    double u[3] = {S->ux[p], S->uy[p], S->uz[p]};
+    if (b->frame == ORA_SHEAR) {
+        double xr = X0[0] - 0.5 * nx;
+        ora_push_shear(1, S->q_over_m, dt, b->shear_s, b->omega0, &xr, E, B, u, NULL);
+    } else if (b->frame == ORA_EXPAND) {
+        ora_push_expand(1, S->q_over_m, dt, C->lam, b->expand_push, E, B, u);
+    } else {
+        ora_push_boris(1, S->q_over_m, dt, E, B, u);
+    }
+    const double gam = sqrt(1.0 + dot(u, u));
+    double D[3];
+    for (int c = 0; c < 3; c++) {
+        D[c] = dt * u[c] / gam;
+        if (b->frame == ORA_EXPAND) D[c] *= C->linv_h[c];
+    }
+    double X1[3] = {X0[0] + D[0], X0[1] + D[1], nd == 3 ? X0[2] + D[2] : 0.0};
+    if (Jt) deposit_one(b, S->q, X0, X1, D[2], Jt);
+    if (b->frame == ORA_SHEAR) {
+        /* x^{n+1} = x' - s Omega0 (x' + x^n)/2 dt e_y (Sec. 2.2) */
+        double xp = X1[0] - 0.5 * nx, xn = X0[0] - 0.5 * nx;
+        X1[1] -= C->sO * (xp + xn) / 2.0 * dt;
+    }
+    if (X1[0] >= nx) {
+        X1[0] -= nx;
+        if (b->frame == ORA_SHEAR) X1[1] += C->dys_1;
+    } else if (X1[0] < 0.0) {
+        X1[0] += nx;
+        if (b->frame == ORA_SHEAR) X1[1] -= C->dys_1;
+    }
+    X1[0] = wrapd(X1[0], nx);
+    X1[1] = wrapd(X1[1], b->n[1]);
+    if (nd == 3) X1[2] = wrapd(X1[2], b->n[2]);
+    if (b->frame == ORA_LEAKY) {
+        if (b->leaky_mode == ORA_LEAKY_DISPLACEMENT) {
+            /* Sec. 4.1: Delta r^n = Delta r^{n-1} + (u/gamma) dt; escape when
+               max(|dx|,|dy|) >= l_esc (eq. escape); resample u, reset Delta r.
+               reading: u/gamma is the velocity of the push just made. */
+            S->drx[p] += D[0];
+            S->dry[p] += D[1];
+            if (S->drz) S->drz[p] += D[2];
+            double m = fmax(fabs(S->drx[p]), fabs(S->dry[p]));
+            if (b->use_3vec && S->drz) m = fmax(m, fabs(S->drz[p]));
+            if (m >= b->l_esc) {
+                uint32_t ctr[4] = {S->id[p], (uint32_t)b->step, 1u, b->box_id}, w[4];
+                ora_philox4x32_10(ctr, C->key, w);
+                ora_mj_sample(b->mj_table, b->mj_bins, b->mj_tail, w, u);
+                S->drx[p] = S->dry[p] = 0.0;
+                if (S->drz) S->drz[p] = 0.0;
+            }
+        } else {
+            /* escape with probability dt/t_esc per step above gamma_thr */
+            double g2m1 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+            if (g2m1 > C->g2thr) {
+                uint32_t ctr[4] = {S->id[p], (uint32_t)b->step, 0u, b->box_id}, w[4];
+                ora_philox4x32_10(ctr, C->key, w);
+                if (w[0] < C->esc_thr && S->alive) S->alive[p] = 0;
+            }
+        }
+    }
+    S->x[p] = X1[0];
+    S->y[p] = X1[1];
+    if (nd == 3) S->z[p] = X1[2];
+    S->ux[p] = u[0];
+    S->uy[p] = u[1];
+    S->uz[p] = u[2];
+}
+
+int ora_particles_only(ora_box* b, const ora_fields* f, ora_species* sp, int nsp)
+{
+    step_scalars C;
+    make_scalars(b, &C);
+    for (int s = 0; s < nsp; s++)
+        for (int64_t p = 0; p < sp[s].n; p++) {
+            if (sp[s].alive && !sp[s].alive[p]) continue;
+            particle_update(b, f, &C, &sp[s], p, NULL);
+        }
+    return 0;
+}
+
+/* One full step: the particle updates with deposit, the current finalisation, Maxwell. */
+int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
+{
+    step_scalars C;
+    make_scalars(b, &C);
+    const double th = ((double)b->step + 0.5) * b->dt;
     if (nthreads < 1) nthreads = 1;
 #ifdef _OPENMP
     omp_set_num_threads(nthreads);
@@ -1091,7 +1198,6 @@ int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
 #endif
     const int64_t ne = jext_cells(b);
     double* Jbuf = (double*)calloc((size_t)nthreads * 3 * ne, sizeof(double));
-
     for (int s = 0; s < nsp; s++) {
         ora_species* S = &sp[s];
 #pragma omp parallel num_threads(nthreads)
@@ -1104,77 +1210,7 @@ int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
 #pragma omp for schedule(static)
             for (int64_t p = 0; p < S->n; p++) {
                 if (S->alive && !S->alive[p]) continue;
-                double X0[3] = {S->x[p], S->y[p], nd == 3 ? S->z[p] : 0.0};
-                double E[3], B[3];
-                for (int c = 0; c < 3; c++) {
-                    E[c] = interp(b, f->E[c], STAG_E[c], X0[0], X0[1], X0[2], dys_n);
-                    B[c] = interp(b, f->B[c], STAG_B[c], X0[0], X0[1], X0[2], dys_n);
-                }
-                double u[3] = {S->ux[p], S->uy[p], S->uz[p]};
-                if (b->frame == ORA_SHEAR) {
-                    double xr = X0[0] - 0.5 * nx;
-                    ora_push_shear(1, S->q_over_m, dt, b->shear_s, b->omega0, &xr, E, B, u, NULL);
-                } else if (b->frame == ORA_EXPAND) {
-                    ora_push_expand(1, S->q_over_m, dt, lam, b->expand_push, E, B, u);
-                } else {
-                    ora_push_boris(1, S->q_over_m, dt, E, B, u);
-                }
-                const double gam = sqrt(1.0 + dot(u, u));
-                double D[3];
-                for (int c = 0; c < 3; c++) {
-                    D[c] = dt * u[c] / gam;
-                    if (b->frame == ORA_EXPAND) D[c] *= linv_h[c];
-                }
-                double X1[3] = {X0[0] + D[0], X0[1] + D[1], nd == 3 ? X0[2] + D[2] : 0.0};
-                deposit_one(b, S->q, X0, X1, D[2], Jt);
-                if (b->frame == ORA_SHEAR) {
-                    /* x^{n+1} = x' - s Omega0 (x' + x^n)/2 dt e_y (Sec. 2.2) */
-                    double xp = X1[0] - 0.5 * nx, xn = X0[0] - 0.5 * nx;
-                    X1[1] -= sO * (xp + xn) / 2.0 * dt;
-                }
-                if (X1[0] >= nx) {
-                    X1[0] -= nx;
-                    if (b->frame == ORA_SHEAR) X1[1] += dys_1;
-                } else if (X1[0] < 0.0) {
-                    X1[0] += nx;
-                    if (b->frame == ORA_SHEAR) X1[1] -= dys_1;
-                }
-                X1[0] = wrapd(X1[0], nx);
-                X1[1] = wrapd(X1[1], b->n[1]);
-                if (nd == 3) X1[2] = wrapd(X1[2], b->n[2]);
-                if (b->frame == ORA_LEAKY) {
-                    if (b->leaky_mode == ORA_LEAKY_DISPLACEMENT) {
-                        /* Sec. 4.1: Delta r^n = Delta r^{n-1} + (u/gamma) dt; escape when
-                           max(|dx|,|dy|) >= l_esc (eq. escape); resample u, reset Delta r.
-                           reading: u/gamma is the velocity of the push just made. */
-                        S->drx[p] += D[0];
-                        S->dry[p] += D[1];
-                        if (S->drz) S->drz[p] += D[2];
-                        double m = fmax(fabs(S->drx[p]), fabs(S->dry[p]));
-                        if (b->use_3vec && S->drz) m = fmax(m, fabs(S->drz[p]));
-                        if (m >= b->l_esc) {
-                            uint32_t ctr[4] = {S->id[p], (uint32_t)b->step, 1u, b->box_id}, w[4];
-                            ora_philox4x32_10(ctr, key, w);
-                            ora_mj_sample(b->mj_table, b->mj_bins, b->mj_tail, w, u);
-                            S->drx[p] = S->dry[p] = 0.0;
-                            if (S->drz) S->drz[p] = 0.0;
-                        }
-                    } else {
-                        /* escape with probability dt/t_esc per step above gamma_thr */
-                        double g2m1 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
-                        if (g2m1 > g2thr) {
-                            uint32_t ctr[4] = {S->id[p], (uint32_t)b->step, 0u, b->box_id}, w[4];
-                            ora_philox4x32_10(ctr, key, w);
-                            if (w[0] < esc_thr && S->alive) S->alive[p] = 0;
-                        }
-                    }
-                }
-                S->x[p] = X1[0];
-                S->y[p] = X1[1];
-                if (nd == 3) S->z[p] = X1[2];
-                S->ux[p] = u[0];
-                S->uy[p] = u[1];
-                S->uz[p] = u[2];
+                particle_update(b, f, &C, S, p, Jt);
             }
         }
     }

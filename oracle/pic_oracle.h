@@ -130,6 +130,9 @@ void ora_charge(const ora_box* b, int64_t n, double q, const double* x, const do
 
 /* one full step of the box frame for all species (step order of sections 2.2, 3.2, 4.1) */
 int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads);
+/* the particle part of a step only (gather, push, move, leaky escape): no deposit, no
+   Maxwell, b->step unchanged */
+int ora_particles_only(ora_box* b, const ora_fields* f, ora_species* sp, int nsp);
 
 /* FP64 diagnostics: out[0..2] = sum E_c^2/8pi, out[3..5] = sum B_c^2/8pi,
    out[6] = kinetic energy sum m(gamma-1), out[7..9] = momentum sum m u, out[10] = live count */

@@ -1,0 +1,162 @@
+"""ctypes binding of the C ABI in include/pic.h (argument marshalling only).
+
+The shared library is the in-tree ``libpic.so`` built by ``build.py``.  There is no
+fallback: a missing or unloadable library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ECAP = 0, -1, -2, -3, -4, -5
+FRAME_PLAIN, FRAME_SHEAR, FRAME_EXPAND, FRAME_LEAKY = 0, 1, 2, 3
+LEAKY_DISPLACEMENT, LEAKY_PROBABILISTIC = 0, 1
+FUSE_DEPOSIT = 1
+REMAP_FIELDS, REMAP_CURRENT = 1, 2
+BOX_TRACK_IDS = 1
+DERR_CFL, DERR_NAN, DERR_ORDER = 1, 2, 4
+
+
+class pic_box_desc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32 * 3), ("dt", C.c_double), ("frame", C.c_int32),
+        ("shear_s", C.c_double), ("shear_omega0", C.c_double),
+        ("expand_adot", C.c_double), ("expand_axis_mask", C.c_int32),
+        ("leaky_mode", C.c_int32), ("leaky_l_esc", C.c_double), ("leaky_use_3vec", C.c_int32),
+        ("leaky_theta_inj", C.c_double), ("leaky_t_esc", C.c_double),
+        ("leaky_gamma_thr", C.c_double),
+        ("n_species", C.c_int32), ("q_over_m", C.c_double * 2), ("q_macro", C.c_double * 2),
+        ("capacity", C.c_int64 * 2), ("seed", C.c_uint64), ("box_id", C.c_uint32),
+        ("tile", C.c_int32 * 3), ("maxwell_iters", C.c_int32), ("flags", C.c_uint32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class pic_box_info(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("t", C.c_double), ("dys", C.c_double), ("a", C.c_double),
+        ("n_particles", C.c_int64 * 2), ("errors", C.c_uint32), ("n_slow", C.c_int64),
+        ("n_escaped", C.c_int64), ("field_energy_E", C.c_double * 3),
+        ("field_energy_B", C.c_double * 3), ("kinetic_energy", C.c_double),
+        ("momentum", C.c_double * 3),
+    ]
+
+
+class PicError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libpic.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PicError(f"HIP library not built: {LIB_PATH} (run paper_2602_15939_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, i64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_int64
+        boxes = C.POINTER(C.c_void_p)
+        sig = {
+            "pic_box_create": ([C.POINTER(pic_box_desc), C.POINTER(C.c_void_p)], i32),
+            "pic_box_destroy": ([vp], i32),
+            "pic_set_fields": ([vp, vp, vp], i32),
+            "pic_get_fields": ([vp, vp, vp], i32),
+            "pic_get_current": ([vp, vp], i32),
+            "pic_set_particles": ([vp, i32, i64, vp, vp, vp, vp, vp], i32),
+            "pic_get_particles": ([vp, i32, C.POINTER(i64), vp, vp, vp, vp, vp], i32),
+            "pic_get_sort": ([vp, i32, vp, vp, C.POINTER(i32)], i32),
+            "pic_tile_sort": ([boxes, i32, u32], i32),
+            "pic_gather_push": ([boxes, i32, u32], i32),
+            "pic_deposit": ([boxes, i32, u32], i32),
+            "pic_shear_remap": ([boxes, i32, u32], i32),
+            "pic_maxwell_step": ([boxes, i32, u32], i32),
+            "pic_escape_compact": ([boxes, i32, u32], i32),
+            "pic_step": ([boxes, i32, u32], i32),
+            "pic_box_get": ([vp, C.POINTER(pic_box_info)], i32),
+            "pic_status_str": ([i32], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str = "") -> None:
+    if rc != PIC_OK:
+        msg = lib().pic_status_str(rc).decode()
+        raise PicError(f"{what}: {msg} ({rc})")
+
+
+def box_array(handles):
+    arr = (C.c_void_p * len(handles))(*handles)
+    return C.cast(arr, C.POINTER(C.c_void_p)), arr
+
+
+def pic_box_create(desc: pic_box_desc) -> int:
+    h = C.c_void_p()
+    check(lib().pic_box_create(C.byref(desc), C.byref(h)), "pic_box_create")
+    return h.value
+
+
+def pic_box_destroy(h) -> None:
+    check(lib().pic_box_destroy(h), "pic_box_destroy")
+
+
+def pic_set_fields(h, E_ptr, B_ptr):
+    check(lib().pic_set_fields(h, E_ptr, B_ptr), "pic_set_fields")
+
+
+def pic_get_fields(h, E_ptr, B_ptr):
+    check(lib().pic_get_fields(h, E_ptr, B_ptr), "pic_get_fields")
+
+
+def pic_get_current(h, J_ptr):
+    check(lib().pic_get_current(h, J_ptr), "pic_get_current")
+
+
+def pic_set_particles(h, species, n, cell, off, u, ids=None, dr=None):
+    check(lib().pic_set_particles(h, species, n, cell, off, u, ids, dr), "pic_set_particles")
+
+
+def pic_get_particles(h, species, cell, off, u, ids=None, dr=None) -> int:
+    n = C.c_int64()
+    check(lib().pic_get_particles(h, species, C.byref(n), cell, off, u, ids, dr),
+          "pic_get_particles")
+    return n.value
+
+
+def pic_get_sort(h, species, perm, offsets) -> int:
+    nt = C.c_int32()
+    check(lib().pic_get_sort(h, species, perm, offsets, C.byref(nt)), "pic_get_sort")
+    return nt.value
+
+
+def _batched(name):
+    def call(handles, flags=0):
+        p, keep = box_array(handles)
+        check(getattr(lib(), name)(p, len(handles), flags), name)
+        del keep
+    call.__name__ = name
+    return call
+
+
+pic_tile_sort = _batched("pic_tile_sort")
+pic_gather_push = _batched("pic_gather_push")
+pic_deposit = _batched("pic_deposit")
+pic_shear_remap = _batched("pic_shear_remap")
+pic_maxwell_step = _batched("pic_maxwell_step")
+pic_escape_compact = _batched("pic_escape_compact")
+pic_step = _batched("pic_step")
+
+
+def pic_box_get(h) -> pic_box_info:
+    info = pic_box_info()
+    check(lib().pic_box_get(h, C.byref(info)), "pic_box_get")
+    return info

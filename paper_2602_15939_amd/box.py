@@ -1,0 +1,146 @@
+"""A box of the particle hot path driven through the C ABI (include/pic.h).
+
+PyTorch supplies device buffers and the stream; every step of the path runs in the HIP
+library.  Field tensors are float32 of shape (3, nz, ny, nx) (x fastest); particle tensors
+follow the boundary layout of pic.h: cell int32 (n,), off float32 (dim, n), u float32 (3, n).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+class Box:
+    def __init__(self, dim, n, dt=0.45, frame=L.FRAME_PLAIN, species=((-1.0, -1e-3, 0),),
+                 shear_s=0.0, shear_omega0=0.0, expand_adot=0.0, expand_axis_mask=0,
+                 leaky_mode=L.LEAKY_DISPLACEMENT, leaky_l_esc=0.0, leaky_use_3vec=0,
+                 leaky_theta_inj=0.0, leaky_t_esc=0.0, leaky_gamma_thr=10.0, seed=0, box_id=0,
+                 tile=(0, 0, 0), maxwell_iters=8, track_ids=False, stream=None):
+        """species: sequence of (q_over_m, q_macro, capacity)."""
+        n = list(n) + [1] * (3 - len(n))
+        d = L.pic_box_desc()
+        d.dim = dim
+        for k in range(3):
+            d.n[k] = int(n[k])
+            d.tile[k] = int(tile[k]) if k < len(tile) else 0
+        d.dt, d.frame = dt, frame
+        d.shear_s, d.shear_omega0 = shear_s, shear_omega0
+        d.expand_adot, d.expand_axis_mask = expand_adot, expand_axis_mask
+        d.leaky_mode, d.leaky_l_esc, d.leaky_use_3vec = leaky_mode, leaky_l_esc, leaky_use_3vec
+        d.leaky_theta_inj, d.leaky_t_esc, d.leaky_gamma_thr = leaky_theta_inj, leaky_t_esc, leaky_gamma_thr
+        d.n_species = len(species)
+        for s, (qm, q, cap) in enumerate(species):
+            d.q_over_m[s], d.q_macro[s], d.capacity[s] = qm, q, int(cap)
+        d.seed, d.box_id = int(seed), int(box_id)
+        d.maxwell_iters = maxwell_iters
+        d.flags = L.BOX_TRACK_IDS if track_ids else 0
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        d.stream = stream.cuda_stream
+        self.desc = d
+        self.dim, self.n = dim, tuple(n)
+        self.ncell = n[0] * n[1] * n[2]
+        self.nsp = len(species)
+        self.h = L.pic_box_create(d)
+
+    # ---- lifetime
+    def close(self):
+        if getattr(self, "h", None):
+            L.pic_box_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state transfer
+    def _grid(self):
+        return torch.empty((3, self.n[2], self.n[1], self.n[0]), dtype=torch.float32, device="cuda")
+
+    def set_fields(self, E, B):
+        E = torch.as_tensor(E, dtype=torch.float32).cuda().contiguous()
+        B = torch.as_tensor(B, dtype=torch.float32).cuda().contiguous()
+        L.pic_set_fields(self.h, E.data_ptr(), B.data_ptr())
+        self.stream.synchronize()
+
+    def get_fields(self):
+        E, B = self._grid(), self._grid()
+        L.pic_get_fields(self.h, E.data_ptr(), B.data_ptr())
+        return E, B
+
+    def get_current(self):
+        J = self._grid()
+        L.pic_get_current(self.h, J.data_ptr())
+        return J
+
+    def set_particles(self, species, cell, off, u, ids=None, dr=None):
+        cell = torch.as_tensor(cell, dtype=torch.int32).cuda().contiguous()
+        off = torch.as_tensor(off, dtype=torch.float32).cuda().contiguous()
+        u = torch.as_tensor(u, dtype=torch.float32).cuda().contiguous()
+        n = cell.numel()
+        assert off.shape == (self.dim, n) and u.shape == (3, n)
+        ip = dp = None
+        if ids is not None:
+            ids = torch.as_tensor(ids, dtype=torch.int64).to(torch.int32).cuda().contiguous()
+            ip = ids.data_ptr()
+        if dr is not None:
+            dr = torch.as_tensor(dr, dtype=torch.float32).cuda().contiguous()
+            assert dr.shape == (3, n)
+            dp = dr.data_ptr()
+        self.stream.synchronize()
+        L.pic_set_particles(self.h, species, n, cell.data_ptr(), off.data_ptr(), u.data_ptr(), ip, dp)
+
+    def count(self, species=0) -> int:
+        return int(self.info().n_particles[species])
+
+    def get_particles(self, species=0):
+        n = self.count(species)
+        cell = torch.empty(n, dtype=torch.int32, device="cuda")
+        off = torch.empty((self.dim, n), dtype=torch.float32, device="cuda")
+        u = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        ids = torch.empty(n, dtype=torch.int32, device="cuda")
+        dr = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+        L.pic_get_particles(self.h, species, cell.data_ptr(), off.data_ptr(), u.data_ptr(),
+                            ids.data_ptr(), dr.data_ptr())
+        return dict(cell=cell, off=off, u=u, id=ids, dr=dr)
+
+    def get_sort(self, species=0):
+        """(perm, offsets) of the last tile sort: perm[i] = pre-sort index of sorted slot i."""
+        import ctypes as C
+        nt = C.c_int32()
+        L.check(L.lib().pic_get_sort(self.h, species, None, None, C.byref(nt)), "pic_get_sort")
+        off = torch.empty(nt.value + 1, dtype=torch.int32, device="cuda")
+        L.pic_get_sort(self.h, species, None, off.data_ptr())
+        n = int(off[-1].item())
+        perm = torch.empty(max(1, n), dtype=torch.int32, device="cuda")
+        L.pic_get_sort(self.h, species, perm.data_ptr(), None)
+        return perm[:n], off
+
+    # ---- the hot path
+    def sort(self):
+        L.pic_tile_sort([self.h])
+
+    def push(self, fuse=True):
+        L.pic_gather_push([self.h], L.FUSE_DEPOSIT if fuse else 0)
+
+    def deposit(self):
+        L.pic_deposit([self.h])
+
+    def remap(self, what=L.REMAP_CURRENT | L.REMAP_FIELDS):
+        L.pic_shear_remap([self.h], what)
+
+    def maxwell(self):
+        L.pic_maxwell_step([self.h])
+
+    def escape_compact(self):
+        L.pic_escape_compact([self.h])
+
+    def step(self):
+        L.pic_step([self.h])
+
+    def info(self) -> L.pic_box_info:
+        return L.pic_box_get(self.h)

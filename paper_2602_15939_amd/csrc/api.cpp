@@ -1,0 +1,817 @@
+// api.cpp — host driver of the C ABI declared in include/pic.h: box lifetime, state
+// transfer, per-step scalars (computed in FP64 on the host: t, Delta y_s(t), l(t), Lambda)
+// and the orchestration of the HIP kernels on the box stream.
+#include "pic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Species {
+    int64_t cap = 0;
+    int n_upper = 0;  // slots the sort looks at (host upper bound of the live count)
+    int cur = 0;      // particle buffer holding the current state
+    int32_t* cell[2] = {};
+    float* off[2][3] = {};
+    float* u[2][3] = {};
+    uint32_t* id[2] = {};
+    float* dr[2][3] = {};
+    SortBufs sb{};
+    int which = 0;          // sort buffer holding the sorted (key, index) pairs
+    int32_t* toff = nullptr;  // n_tiles + 2
+    int32_t* n_live = nullptr;
+    int32_t* ws_cell = nullptr;
+    float* ws_off[3] = {};
+    float* ws_disp[3] = {};
+    double qm = 0, q = 0;
+};
+
+}  // namespace
+
+struct pic_box {
+    pic_box_desc d{};
+    hipStream_t st = nullptr;
+    int dim = 3;
+    int n[3] = {1, 1, 1};
+    int tile[3] = {1, 1, 1};
+    GridDev G{};
+    int64_t comp_elems = 0;  // floats per guarded component array
+    int64_t origin = 0;      // offset of interior (0,0,0)
+    CellCode cc{};
+    Tiles tl{};
+    int nsp = 1;
+    Species sp[kMaxSpecies];
+    // field sets: set[s][0..2] = B, set[s][3..5] = E (shearing box keeps 3 sets for the
+    // fixed-point iterates); cur_set is the one holding the fields
+    float* set[3][6] = {};
+    int nsets = 1;
+    int cur_set = 0;
+    float* J[3] = {};
+    float* Jt[3] = {};
+    float* mj = nullptr;
+    uint32_t* err = nullptr;
+    unsigned long long* ctr = nullptr;
+    double* red_part = nullptr;
+    double* red_out = nullptr;
+    int64_t step = 0;
+    bool sorted = false;
+    bool deposit_pending = false;
+    bool track_ids = false;
+    std::vector<void*> allocs;
+
+    float* E(int c) const { return set[cur_set][3 + c]; }
+    float* B(int c) const { return set[cur_set][c]; }
+};
+
+namespace {
+
+constexpr int kRedBlocks = 1024;
+
+int32_t hip_fail(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EDEVICE; }
+
+template <class T>
+int32_t dalloc(pic_box* b, T*& p, size_t count)
+{
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return PIC_ENOMEM;
+    b->allocs.push_back(q);
+    p = static_cast<T*>(q);
+    return PIC_OK;
+}
+
+int ceil_log2(int v)
+{
+    int b = 0;
+    while ((1 << b) < v) b++;
+    return b;
+}
+
+double time_of(const pic_box* b, int64_t step) { return (double)step * b->d.dt; }
+
+// Sec. 2.1: Delta y_s(t) = s Omega0 (x_o - x_i) t, reduced modulo n[1]
+double shear_offset(const pic_box* b, double t)
+{
+    if (b->d.frame != PIC_FRAME_SHEAR) return 0.0;
+    const double ny = b->n[1];
+    double v = std::fmod(b->d.shear_s * b->d.shear_omega0 * (double)b->n[0] * t, ny);
+    if (v < 0) v += ny;
+    if (v >= ny) v = 0.0;
+    return v;
+}
+
+// Sec. 3.1: l_d(t) = 1 + adot t on the expanding axes
+double scale_of(const pic_box* b, int axis, double t)
+{
+    if (b->d.frame != PIC_FRAME_EXPAND || !((b->d.expand_axis_mask >> axis) & 1)) return 1.0;
+    return 1.0 + b->d.expand_adot * t;
+}
+
+// ---------------------------------------------------------------- reinjection table
+// Maxwell-Juttner inverse CDF of |u| (density u^2 exp(-(gamma-1)/theta)): bulk quantiles
+// i/kMjBins and tail quantiles 1 - 2^-(12 + 20 k/kMjTail).  Panel masses by 8-point
+// Gauss-Legendre, summed from the top; inside the bracketing panel the quantile is refined by
+// Newton iterations on the partial-panel mass.
+const double kGLx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
+                        0.9602898564975363};
+const double kGLw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745,
+                        0.1012285362903763};
+
+double mj_g(double u, double th) { return u * u * std::exp(-(std::sqrt(1.0 + u * u) - 1.0) / th); }
+
+double gl_mass(double a, double c, double th)
+{
+    const double m = 0.5 * (a + c), h = 0.5 * (c - a);
+    double s = 0;
+    for (int i = 0; i < 4; i++) s += kGLw[i] * (mj_g(m - h * kGLx[i], th) + mj_g(m + h * kGLx[i], th));
+    return s * h;
+}
+
+void build_mj_table(double theta, std::vector<float>& out)
+{
+    const int P = 1 << 15;
+    const double gmax = 1.0 + 60.0 * theta, umax = std::sqrt(gmax * gmax - 1.0), h = umax / P;
+    std::vector<double> Q(P + 1, 0.0);  // mass above panel edge k
+    for (int k = P - 1; k >= 0; k--) Q[k] = Q[k + 1] + gl_mass(k * h, (k + 1) * h, theta);
+    const double tot = Q[0];
+    auto quantile = [&](double q) -> double {  // |u| with (mass above)/tot = q
+        if (q >= 1.0) return 0.0;
+        const double target = q * tot;
+        int lo = 0, hi = P;  // Q[lo] >= target > Q[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (Q[mid] >= target)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const double a = lo * h, c = hi * h;
+        double u = a + (Q[lo] - target) / (Q[lo] - Q[hi]) * h;
+        for (int it = 0; it < 8; it++) {
+            const double f = Q[hi] + gl_mass(u, c, theta) - target;
+            const double fp = -mj_g(u, theta);
+            if (fp == 0.0) break;
+            double un = u - f / fp;
+            if (un < a) un = a;
+            if (un > c) un = c;
+            u = un;
+        }
+        return u;
+    };
+    out.resize(kMjBins + kMjTail);
+    for (int i = 0; i < kMjBins; i++) out[i] = (float)quantile(1.0 - (double)i / kMjBins);
+    const int bits = 12;  // log2(kMjBins)
+    for (int k = 0; k <= kMjTail; k++)
+        out[kMjBins - 1 + k] = (float)quantile(std::ldexp(1.0, -bits) *
+                                               std::exp2(-(32.0 - bits) * k / kMjTail));
+}
+
+// ---------------------------------------------------------------- descriptor of one push
+StepDev make_step(pic_box* b)
+{
+    StepDev P{};
+    P.dim = b->dim;
+    P.frame = b->d.frame;
+    for (int k = 0; k < 3; k++) P.n[k] = b->n[k];
+    P.cc = b->cc;
+    P.tl = b->tl;
+    P.sy = b->G.sy;
+    P.sz = b->G.sz;
+    for (int c = 0; c < 3; c++) {
+        P.E[c] = b->E(c);
+        P.B[c] = b->B(c);
+        P.J[c] = b->J[c];
+    }
+    const double dt = b->d.dt;
+    P.dt = (float)dt;
+    const double tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
+    const double sO = b->d.shear_s * b->d.shear_omega0;
+    P.sO = (float)sO;
+    P.om_dt = (float)(b->d.shear_omega0 * dt);
+    P.alpha1 = (float)(sO * dt / 2.0);
+    P.half_nx = 0.5f * (float)b->n[0];
+    const double dys1 = shear_offset(b, t1);
+    const double fl = std::floor(dys1);
+    P.dys_int = (int)fl;
+    P.dys_frac = (float)(dys1 - fl);
+    if (P.dys_frac >= 1.f) {  // FP32 rounding of a fraction just below 1
+        P.dys_frac = 0.f;
+        P.dys_int = (P.dys_int + 1) % b->n[1];
+    }
+    for (int k = 0; k < 3; k++) {
+        const double rate =
+            (b->d.frame == PIC_FRAME_EXPAND && ((b->d.expand_axis_mask >> k) & 1)) ? b->d.expand_adot : 0.0;
+        const double lam = -0.5 * dt * rate / scale_of(b, k, tn);  // Lambda at t^n
+        P.lam1p[k] = (float)(1.0 + lam);
+        P.ltil[k] = (float)((1.0 + lam) / (1.0 - lam));
+        P.tfac[k] = (float)(1.0 / (1.0 - lam));
+        P.linv[k] = (float)(1.0 / scale_of(b, k, th));  // (L^-1)^{n+1/2}
+    }
+    P.leaky_mode = b->d.leaky_mode;
+    P.use_3vec = b->d.leaky_use_3vec;
+    P.l_esc = (float)b->d.leaky_l_esc;
+    {
+        const double p = b->d.leaky_t_esc > 0 ? dt / b->d.leaky_t_esc : 0.0;
+        const double th32 = std::floor(p * 4294967296.0);
+        P.esc_thr = th32 >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th32;
+    }
+    P.g2thr = b->d.leaky_gamma_thr * b->d.leaky_gamma_thr - 1.0;
+    P.key0 = (uint32_t)b->d.seed;
+    P.key1 = (uint32_t)(b->d.seed >> 32);
+    P.step_lo = (uint32_t)b->step;
+    P.box_id = b->d.box_id;
+    P.mj = b->mj;
+    P.err = b->err;
+    P.ctr = b->ctr;
+    P.nsp = b->nsp;
+    P.track_ids = b->track_ids ? 1 : 0;
+    for (int s = 0; s < b->nsp; s++) {
+        Species& S = b->sp[s];
+        SpeciesDev& D = P.sp[s];
+        const int i = S.cur, o = S.cur ^ 1;
+        D.cell_in = S.cell[i];
+        D.cell_out = S.cell[o];
+        for (int c = 0; c < 3; c++) {
+            D.off_in[c] = S.off[i][c];
+            D.off_out[c] = S.off[o][c];
+            D.u_in[c] = S.u[i][c];
+            D.u_out[c] = S.u[o][c];
+            D.dr_in[c] = S.dr[i][c];
+            D.dr_out[c] = S.dr[o][c];
+            D.ws_off[c] = S.ws_off[c];
+            D.ws_disp[c] = S.ws_disp[c];
+        }
+        D.id_in = S.id[i];
+        D.id_out = S.id[o];
+        D.perm = reinterpret_cast<const int32_t*>(S.sb.vals[S.which]);
+        D.toff = S.toff;
+        D.ws_cell = S.ws_cell;
+        D.qm_hdt = (float)(S.qm * dt / 2.0);
+        D.q_dt = (float)(S.q / dt);
+    }
+    return P;
+}
+
+int32_t check_boxes(pic_box* const* boxes, int32_t nb)
+{
+    if (!boxes || nb < 1) return PIC_EINVAL;
+    for (int i = 0; i < nb; i++)
+        if (!boxes[i]) return PIC_EINVAL;
+    return PIC_OK;
+}
+
+int32_t sort_box(pic_box* b)
+{
+    for (int s = 0; s < b->nsp; s++) {
+        Species& S = b->sp[s];
+        hipError_t e = tile_sort(S.cell[S.cur], S.n_live, S.n_upper, b->cc, b->tl, S.sb, S.toff,
+                                 S.n_live, S.which, b->st);
+        if (e != hipSuccess) return PIC_EDEVICE;
+    }
+    b->sorted = true;
+    return PIC_OK;
+}
+
+int32_t zero_current(pic_box* b)
+{
+    for (int c = 0; c < 3; c++)
+        if (zero_floats(b->J[c] - b->origin, b->comp_elems, b->st) != hipSuccess) return PIC_EDEVICE;
+    return PIC_OK;
+}
+
+int32_t push_box(pic_box* b, bool fuse)
+{
+    if (!b->sorted) return PIC_ESTATE;
+    if (fuse) {
+        int32_t r = zero_current(b);
+        if (r) return r;
+    } else {
+        // workspace of the unfused deposit (old position and deposit displacement per slot)
+        for (int s = 0; s < b->nsp; s++) {
+            Species& S = b->sp[s];
+            if (S.ws_cell) continue;
+            const size_t cap = (size_t)S.cap + 1;
+            int32_t r = dalloc(b, S.ws_cell, cap);
+            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.ws_off[c], cap);
+            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.ws_disp[c], cap);
+            if (r) return r;
+        }
+    }
+    StepDev P = make_step(b);
+    if (launch_gather_push(P, b->tile, fuse ? 1 : 0, b->st) != hipSuccess) return PIC_EDEVICE;
+    for (int s = 0; s < b->nsp; s++) b->sp[s].cur ^= 1;
+    b->sorted = false;
+    b->deposit_pending = !fuse;
+    return PIC_OK;
+}
+
+int32_t deposit_box(pic_box* b)
+{
+    if (!b->deposit_pending) return PIC_ESTATE;
+    int32_t r = zero_current(b);
+    if (r) return r;
+    // the saved slots and tile offsets belong to the sort before the push
+    StepDev P = make_step(b);
+    if (launch_deposit(P, b->tile, b->st) != hipSuccess) return PIC_EDEVICE;
+    b->deposit_pending = false;
+    return PIC_OK;
+}
+
+float* const* field_ptrs(pic_box* b) { return b->set[b->cur_set]; }
+
+int32_t fill_field_guards(pic_box* b, double t)
+{
+    return hip_fail(fill_guards(b->G, field_ptrs(b), 6, b->d.frame == PIC_FRAME_SHEAR ? 1 : 0,
+                                shear_offset(b, t), b->st));
+}
+
+int32_t fold_box(pic_box* b)
+{
+    const double th = time_of(b, b->step) + 0.5 * b->d.dt;
+    const int shear = b->d.frame == PIC_FRAME_SHEAR;
+    return hip_fail(fold_current(b->G, b->J, b->Jt, shear, b->d.shear_s * b->d.shear_omega0,
+                                 b->d.dt, shear_offset(b, th), b->st));
+}
+
+int32_t maxwell_box(pic_box* b)
+{
+    const double dt = b->d.dt;
+    const double tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
+    hipStream_t st = b->st;
+    if (b->d.frame == PIC_FRAME_SHEAR) {
+        // implicit midpoint by fixed-point sweeps; F^0 = F^n (with its own guards), every later
+        // iterate has its guards filled at t^{n+1}
+        const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
+        const int sn = b->cur_set;
+        int sk = sn;
+        int so = (sn + 1) % 3;
+        const double dys1 = shear_offset(b, t1);
+        for (int k = 0; k < K; k++) {
+            KsbDev Kd{};
+            Kd.G = b->G;
+            for (int c = 0; c < 6; c++) {
+                Kd.Fn[c] = b->set[sn][c];
+                Kd.Fk[c] = b->set[sk][c];
+                Kd.Fo[c] = b->set[so][c];
+            }
+            for (int c = 0; c < 3; c++) Kd.J[c] = b->J[c];
+            Kd.dt = (float)dt;
+            Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
+            Kd.half_nx = 0.5f * (float)b->n[0];
+            if (ksb_sweep(Kd, st) != hipSuccess) return PIC_EDEVICE;
+            if (fill_guards(b->G, b->set[so], 6, 1, dys1, st) != hipSuccess) return PIC_EDEVICE;
+            sk = so;
+            so = (so + 1) % 3;
+            if (so == sn) so = (so + 1) % 3;
+        }
+        b->cur_set = sk;
+        return PIC_OK;
+    }
+    // Yee: B half step, E full step, B half step, with the expanding-box factors
+    double ln[3], lh[3], l1[3];
+    for (int k = 0; k < 3; k++) {
+        ln[k] = scale_of(b, k, tn);
+        lh[k] = scale_of(b, k, th);
+        l1[k] = scale_of(b, k, t1);
+    }
+    const double elln = ln[0] * ln[1] * ln[2], ellh = lh[0] * lh[1] * lh[2], ell1 = l1[0] * l1[1] * l1[2];
+    MaxwellDev M{};
+    M.G = b->G;
+    for (int c = 0; c < 3; c++) {
+        M.E[c] = b->E(c);
+        M.B[c] = b->B(c);
+        M.J[c] = b->J[c];
+    }
+    M.dt = (float)dt;
+    float* Bp[3] = {b->B(0), b->B(1), b->B(2)};
+    float* Ep[3] = {b->E(0), b->E(1), b->E(2)};
+    // B'^{n+1/2} = B'^n - dt/2 curl(L^n E^n), B^{n+1/2} = (l/ell)^{n+1/2} B'
+    for (int c = 0; c < 3; c++) {
+        M.fin[c] = (float)(elln / ln[c]);
+        M.fout[c] = (float)(lh[c] / ellh);
+        M.gf[c] = (float)ln[c];
+    }
+    if (yee_b(M, st) != hipSuccess) return PIC_EDEVICE;
+    if (fill_guards(b->G, Bp, 3, 0, 0.0, st) != hipSuccess) return PIC_EDEVICE;
+    // E'^{n+1} = E'^n + dt curl(L^{n+1/2} B^{n+1/2}) - 4 pi dt (l J'), E^{n+1} = (l/ell)^{n+1} E'
+    for (int c = 0; c < 3; c++) {
+        M.fin[c] = (float)(elln / ln[c]);
+        M.fout[c] = (float)(l1[c] / ell1);
+        M.gf[c] = (float)lh[c];
+    }
+    if (yee_e(M, st) != hipSuccess) return PIC_EDEVICE;
+    if (fill_guards(b->G, Ep, 3, 0, 0.0, st) != hipSuccess) return PIC_EDEVICE;
+    // B'^{n+1} = B'^{n+1/2} - dt/2 curl(L^{n+1} E^{n+1}), B^{n+1} = (l/ell)^{n+1} B'
+    for (int c = 0; c < 3; c++) {
+        M.fin[c] = (float)(ellh / lh[c]);
+        M.fout[c] = (float)(l1[c] / ell1);
+        M.gf[c] = (float)l1[c];
+    }
+    if (yee_b(M, st) != hipSuccess) return PIC_EDEVICE;
+    if (fill_guards(b->G, Bp, 3, 0, 0.0, st) != hipSuccess) return PIC_EDEVICE;
+    return PIC_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* pic_status_str(int32_t s)
+{
+    switch (s) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_ENOMEM: return "device allocation failed";
+    case PIC_EDEVICE: return "HIP call failed";
+    case PIC_ESTATE: return "call not valid in the current box state";
+    case PIC_ECAP: return "particle count above capacity";
+    default: return "unknown status";
+    }
+}
+
+int32_t pic_box_destroy(pic_box* b)
+{
+    if (!b) return PIC_OK;
+    hipStreamSynchronize(b->st);
+    for (void* p : b->allocs) hipFree(p);
+    delete b;
+    return PIC_OK;
+}
+
+int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
+{
+    if (!d || !out) return PIC_EINVAL;
+    if (d->dim != 2 && d->dim != 3) return PIC_EINVAL;
+    int n[3] = {d->n[0], d->n[1], d->dim == 3 ? d->n[2] : 1};
+    if (d->dim == 2 && d->n[2] != 1 && d->n[2] != 0) return PIC_EINVAL;
+    for (int k = 0; k < d->dim; k++)
+        if (n[k] < 4) return PIC_EINVAL;
+    if (!(d->dt > 0) || d->dt * std::sqrt((double)d->dim) >= 1.0) return PIC_EINVAL;
+    if (d->frame < 0 || d->frame > 3) return PIC_EINVAL;
+    if (d->n_species < 1 || d->n_species > 2) return PIC_EINVAL;
+    if (d->frame == PIC_FRAME_LEAKY) {
+        if (d->leaky_mode == PIC_LEAKY_DISPLACEMENT && !(d->leaky_l_esc > 0 && d->leaky_theta_inj > 0))
+            return PIC_EINVAL;
+        if (d->leaky_mode == PIC_LEAKY_PROBABILISTIC && !(d->leaky_t_esc > 0)) return PIC_EINVAL;
+        if (d->leaky_mode != 0 && d->leaky_mode != 1) return PIC_EINVAL;
+    }
+    int tile[3];
+    for (int k = 0; k < 3; k++) tile[k] = d->tile[k];
+    if (tile[0] == 0) {
+        tile[0] = tile[1] = d->dim == 3 ? 8 : 16;
+        tile[2] = d->dim == 3 ? 8 : 1;
+    }
+    if (d->dim == 2) tile[2] = 1;
+    if (!tile_shape_supported(d->dim, tile)) return PIC_EINVAL;
+    int bits[3];
+    for (int k = 0; k < 3; k++) bits[k] = ceil_log2(n[k]);
+    if (bits[0] + bits[1] + bits[2] > 31) return PIC_EINVAL;
+    for (int s = 0; s < d->n_species; s++)
+        if (d->capacity[s] < 0 || d->capacity[s] >= (1ll << 31) - 4096) return PIC_EINVAL;
+
+    pic_box* b = new (std::nothrow) pic_box();
+    if (!b) return PIC_ENOMEM;
+    b->d = *d;
+    b->st = static_cast<hipStream_t>(d->stream);
+    b->dim = d->dim;
+    for (int k = 0; k < 3; k++) {
+        b->n[k] = n[k];
+        b->tile[k] = tile[k];
+    }
+    b->cc.b0 = bits[0];
+    b->cc.b1 = bits[1];
+    b->cc.m0 = (1u << bits[0]) - 1u;
+    b->cc.m1 = (1u << bits[1]) - 1u;
+    for (int k = 0; k < 3; k++) {
+        b->tl.lt[k] = ceil_log2(tile[k]);
+        b->tl.nt[k] = (n[k] + tile[k] - 1) / tile[k];
+    }
+    b->tl.n_tiles = b->tl.nt[0] * b->tl.nt[1] * b->tl.nt[2];
+    GridDev& G = b->G;
+    G.dim = b->dim;
+    for (int k = 0; k < 3; k++) {
+        G.n[k] = n[k];
+        G.g[k] = (k < b->dim) ? kGuard : 0;
+    }
+    const int NXg = n[0] + 2 * G.g[0], NYg = n[1] + 2 * G.g[1], NZg = n[2] + 2 * G.g[2];
+    G.sy = NXg;
+    G.sz = NXg * NYg;
+    b->comp_elems = (int64_t)NXg * NYg * NZg;
+    b->origin = (int64_t)G.g[0] + (int64_t)G.sy * G.g[1] + (int64_t)G.sz * G.g[2];
+    b->nsp = d->n_species;
+    b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || d->frame == PIC_FRAME_LEAKY;
+
+    int32_t r = PIC_OK;
+    auto grid_alloc = [&](float*& p) -> int32_t {
+        float* q = nullptr;
+        int32_t rr = dalloc(b, q, (size_t)b->comp_elems);
+        if (rr) return rr;
+        if (hipMemsetAsync(q, 0, sizeof(float) * b->comp_elems, b->st) != hipSuccess) return PIC_EDEVICE;
+        p = q + b->origin;
+        return PIC_OK;
+    };
+    b->nsets = d->frame == PIC_FRAME_SHEAR ? 3 : 1;
+    for (int s = 0; s < b->nsets && !r; s++)
+        for (int c = 0; c < 6 && !r; c++) r = grid_alloc(b->set[s][c]);
+    for (int c = 0; c < 3 && !r; c++) r = grid_alloc(b->J[c]);
+    if (d->frame == PIC_FRAME_SHEAR)
+        for (int c = 0; c < 3 && !r; c++) r = grid_alloc(b->Jt[c]);
+    for (int s = 0; s < b->nsp && !r; s++) {
+        Species& S = b->sp[s];
+        S.cap = d->capacity[s];
+        S.qm = d->q_over_m[s];
+        S.q = d->q_macro[s];
+        const size_t cap = (size_t)S.cap + 1;
+        for (int k = 0; k < 2 && !r; k++) {
+            r = dalloc(b, S.cell[k], cap);
+            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.off[k][c], c < b->dim ? cap : 1);
+            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.u[k][c], cap);
+            if (!r && b->track_ids) r = dalloc(b, S.id[k], cap);
+            if (d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
+                for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.dr[k][c], cap);
+        }
+        for (int k = 0; k < 2 && !r; k++) {
+            r = dalloc(b, S.sb.keys[k], cap);
+            if (!r) r = dalloc(b, S.sb.vals[k], cap);
+        }
+        if (!r) r = dalloc(b, S.sb.hist, sort_hist_words((int64_t)cap));
+        if (!r) r = dalloc(b, S.sb.scratch, scan_scratch_words((int64_t)sort_hist_words((int64_t)cap)));
+        if (!r) r = dalloc(b, S.toff, (size_t)b->tl.n_tiles + 2);
+        if (!r) r = dalloc(b, S.n_live, 2);
+        if (!r && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
+    }
+    if (!r) r = dalloc(b, b->err, 4);
+    if (!r) r = dalloc(b, b->ctr, 4);
+    if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
+    if (!r) r = dalloc(b, b->red_out, 16);
+    if (!r && hipMemsetAsync(b->err, 0, 4 * sizeof(uint32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
+    if (!r && hipMemsetAsync(b->ctr, 0, 4 * sizeof(unsigned long long), b->st) != hipSuccess) r = PIC_EDEVICE;
+    if (!r && d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT) {
+        std::vector<float> tab;
+        build_mj_table(d->leaky_theta_inj, tab);
+        r = dalloc(b, b->mj, tab.size());
+        if (!r && hipMemcpy(b->mj, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            r = PIC_EDEVICE;
+    }
+    if (!r && hipStreamSynchronize(b->st) != hipSuccess) r = PIC_EDEVICE;
+    if (r) {
+        pic_box_destroy(b);
+        return r;
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+int32_t pic_set_fields(pic_box* b, const float* E, const float* B)
+{
+    if (!b || !E || !B) return PIC_EINVAL;
+    const int64_t nc = (int64_t)b->n[0] * b->n[1] * b->n[2];
+    for (int c = 0; c < 3; c++) {
+        if (interior_copy(b->G, b->E(c), const_cast<float*>(E) + c * nc, 0, b->st) != hipSuccess)
+            return PIC_EDEVICE;
+        if (interior_copy(b->G, b->B(c), const_cast<float*>(B) + c * nc, 0, b->st) != hipSuccess)
+            return PIC_EDEVICE;
+    }
+    return fill_field_guards(b, time_of(b, b->step));
+}
+
+int32_t pic_get_fields(pic_box* b, float* E, float* B)
+{
+    if (!b) return PIC_EINVAL;
+    const int64_t nc = (int64_t)b->n[0] * b->n[1] * b->n[2];
+    for (int c = 0; c < 3; c++) {
+        if (E && interior_copy(b->G, b->E(c), E + c * nc, 1, b->st) != hipSuccess) return PIC_EDEVICE;
+        if (B && interior_copy(b->G, b->B(c), B + c * nc, 1, b->st) != hipSuccess) return PIC_EDEVICE;
+    }
+    return hip_fail(hipStreamSynchronize(b->st));
+}
+
+int32_t pic_get_current(pic_box* b, float* J)
+{
+    if (!b || !J) return PIC_EINVAL;
+    const int64_t nc = (int64_t)b->n[0] * b->n[1] * b->n[2];
+    for (int c = 0; c < 3; c++)
+        if (interior_copy(b->G, b->J[c], J + c * nc, 1, b->st) != hipSuccess) return PIC_EDEVICE;
+    return hip_fail(hipStreamSynchronize(b->st));
+}
+
+int32_t pic_set_particles(pic_box* b, int32_t s, int64_t n, const int32_t* cell, const float* off,
+                          const float* u, const uint32_t* id, const float* dr)
+{
+    if (!b || s < 0 || s >= b->nsp || n < 0 || (n > 0 && (!cell || !off || !u))) return PIC_EINVAL;
+    Species& S = b->sp[s];
+    if (n > S.cap) return PIC_ECAP;
+    hipStream_t st = b->st;
+    const int k = S.cur;
+    if (cells_linear_to_packed(cell, S.cell[k], n, b->n, b->cc, b->err, st) != hipSuccess) return PIC_EDEVICE;
+    const size_t fb = sizeof(float) * (size_t)n;
+    for (int c = 0; c < b->dim; c++)
+        if (n && hipMemcpyAsync(S.off[k][c], off + c * n, fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    for (int c = 0; c < 3; c++)
+        if (n && hipMemcpyAsync(S.u[k][c], u + c * n, fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    if (b->track_ids) {
+        if (id) {
+            if (n && hipMemcpyAsync(S.id[k], id, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return PIC_EDEVICE;
+        } else if (iota_u32(S.id[k], n, st) != hipSuccess) {
+            return PIC_EDEVICE;
+        }
+    }
+    if (S.dr[k][0]) {
+        for (int c = 0; c < 3; c++) {
+            if (dr) {
+                if (n && hipMemcpyAsync(S.dr[k][c], dr + c * n, fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    return PIC_EDEVICE;
+            } else if (zero_floats(S.dr[k][c], n, st) != hipSuccess) {
+                return PIC_EDEVICE;
+            }
+        }
+    }
+    const int32_t nn = (int32_t)n;
+    if (hipMemcpyAsync(S.n_live, &nn, sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EDEVICE;
+    S.n_upper = (int)n;
+    b->sorted = false;
+    return PIC_OK;
+}
+
+int32_t pic_get_particles(pic_box* b, int32_t s, int64_t* n_out, int32_t* cell, float* off, float* u,
+                          uint32_t* id, float* dr)
+{
+    if (!b || s < 0 || s >= b->nsp) return PIC_EINVAL;
+    Species& S = b->sp[s];
+    int32_t n = 0;
+    if (hipMemcpyAsync(&n, S.n_live, sizeof(int32_t), hipMemcpyDeviceToHost, b->st) != hipSuccess ||
+        hipStreamSynchronize(b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (n_out) *n_out = n;
+    const int k = S.cur;
+    hipStream_t st = b->st;
+    const size_t fb = sizeof(float) * (size_t)n;
+    if (cell && cells_packed_to_linear(S.cell[k], cell, n, b->n, b->cc, st) != hipSuccess) return PIC_EDEVICE;
+    for (int c = 0; c < b->dim && off; c++)
+        if (n && hipMemcpyAsync(off + c * n, S.off[k][c], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    for (int c = 0; c < 3 && u; c++)
+        if (n && hipMemcpyAsync(u + c * n, S.u[k][c], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    if (id && b->track_ids && n &&
+        hipMemcpyAsync(id, S.id[k], sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return PIC_EDEVICE;
+    for (int c = 0; c < 3 && dr && S.dr[k][0]; c++)
+        if (n && hipMemcpyAsync(dr + c * n, S.dr[k][c], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    return hip_fail(hipStreamSynchronize(st));
+}
+
+int32_t pic_get_sort(pic_box* b, int32_t s, int32_t* perm, int32_t* offsets, int32_t* n_tiles_out)
+{
+    if (!b || s < 0 || s >= b->nsp) return PIC_EINVAL;
+    Species& S = b->sp[s];
+    if (n_tiles_out) *n_tiles_out = b->tl.n_tiles;
+    int32_t n = 0;
+    if (hipMemcpyAsync(&n, S.toff + b->tl.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, b->st) != hipSuccess ||
+        hipStreamSynchronize(b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (perm && n &&
+        hipMemcpyAsync(perm, S.sb.vals[S.which], sizeof(int32_t) * n, hipMemcpyDeviceToDevice, b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (offsets && hipMemcpyAsync(offsets, S.toff, sizeof(int32_t) * (b->tl.n_tiles + 1),
+                                  hipMemcpyDeviceToDevice, b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    return hip_fail(hipStreamSynchronize(b->st));
+}
+
+int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t)
+{
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) r = sort_box(boxes[i]);
+    return r;
+}
+
+int32_t pic_gather_push(pic_box* const* boxes, int32_t nb, uint32_t flags)
+{
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) r = push_box(boxes[i], (flags & PIC_FUSE_DEPOSIT) != 0);
+    return r;
+}
+
+int32_t pic_deposit(pic_box* const* boxes, int32_t nb, uint32_t)
+{
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) r = deposit_box(boxes[i]);
+    return r;
+}
+
+int32_t pic_shear_remap(pic_box* const* boxes, int32_t nb, uint32_t what)
+{
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) {
+        pic_box* b = boxes[i];
+        if (what & PIC_REMAP_CURRENT) r = fold_box(b);
+        if (!r && (what & PIC_REMAP_FIELDS)) r = fill_field_guards(b, time_of(b, b->step));
+    }
+    return r;
+}
+
+int32_t pic_maxwell_step(pic_box* const* boxes, int32_t nb, uint32_t)
+{
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) {
+        pic_box* b = boxes[i];
+        r = maxwell_box(b);
+        if (!r) {
+            b->step += 1;
+            if (b->d.frame != PIC_FRAME_SHEAR) r = fill_field_guards(b, time_of(b, b->step));
+        }
+    }
+    return r;
+}
+
+int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags)
+{
+    return pic_tile_sort(boxes, nb, flags);
+}
+
+int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t)
+{
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) {
+        pic_box* b = boxes[i];
+        r = sort_box(b);
+        if (!r) r = push_box(b, true);
+        if (!r) r = fold_box(b);
+        if (!r) r = maxwell_box(b);
+        if (!r) {
+            b->step += 1;
+            if (b->d.frame != PIC_FRAME_SHEAR) r = fill_field_guards(b, time_of(b, b->step));
+        }
+    }
+    return r;
+}
+
+int32_t pic_box_get(pic_box* b, pic_box_info* info)
+{
+    if (!b || !info) return PIC_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    hipStream_t st = b->st;
+    if (field_energy(b->G, field_ptrs(b), 6, b->red_part, kRedBlocks, b->red_out, st) != hipSuccess)
+        return PIC_EDEVICE;
+    double fe[6];
+    if (hipMemcpyAsync(fe, b->red_out, sizeof(fe), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return PIC_EDEVICE;
+    for (int c = 0; c < 3; c++) {
+        info->field_energy_B[c] = fe[c] / (8.0 * kPi);  // set order: B then E
+        info->field_energy_E[c] = fe[3 + c] / (8.0 * kPi);
+    }
+    for (int s = 0; s < b->nsp; s++) {
+        Species& S = b->sp[s];
+        const int k = S.cur;
+        if (particle_sums(S.u[k][0], S.u[k][1], S.u[k][2], S.n_live, b->red_part, kRedBlocks,
+                          b->red_out, st) != hipSuccess)
+            return PIC_EDEVICE;
+        double ps[4];
+        int32_t n = 0;
+        if (hipMemcpyAsync(ps, b->red_out, sizeof(ps), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&n, S.n_live, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return PIC_EDEVICE;
+        const double m = S.qm != 0 ? std::fabs(S.q / S.qm) : 0.0;
+        info->kinetic_energy += m * ps[0];
+        for (int c = 0; c < 3; c++) info->momentum[c] += m * ps[1 + c];
+        info->n_particles[s] = n;
+    }
+    uint32_t err = 0;
+    unsigned long long ctr[2] = {0, 0};
+    if (hipMemcpy(&err, b->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ctr, b->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EDEVICE;
+    info->errors = err;
+    info->n_slow = (int64_t)ctr[0];
+    info->n_escaped = (int64_t)ctr[1];
+    info->step = b->step;
+    info->t = time_of(b, b->step);
+    info->dys = shear_offset(b, info->t);
+    info->a = 1.0;
+    for (int k = 0; k < 3; k++)
+        if (b->d.frame == PIC_FRAME_EXPAND && ((b->d.expand_axis_mask >> k) & 1)) info->a = scale_of(b, k, info->t);
+    return PIC_OK;
+}
+
+}  // extern "C"

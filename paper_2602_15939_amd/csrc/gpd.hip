@@ -1,0 +1,635 @@
+// gpd.hip — the particle hot path on gfx950: field gather from the Yee grid, the frame's
+// Boris-like push, position update with the boundary conditions, leaky-box escape and the
+// charge-conserving (Esirkepov) current deposit, fused in one kernel per tile.
+//
+// One workgroup owns one tile: it stages E and B of the tile plus one guard cell per side in
+// LDS, accumulates the tile's current (plus the deposit halo) in LDS with ds_add_f32, and
+// flushes it once to HBM with float atomics (only the halo overlaps a neighbour tile).
+// Particles are read through the sort permutation and written in sorted slot order, so the
+// tile sort's scatter is fused into this pass.  A particle found outside its tile (only
+// possible without a sort since the last push) takes the global-memory path.
+#include "pic_internal.h"
+
+namespace pic {
+
+// ------------------------------------------------------------------ small vector helpers
+struct f3 {
+    float x, y, z;
+};
+__device__ inline f3 mk(float a, float b, float c) { return f3{a, b, c}; }
+__device__ inline f3 operator+(f3 a, f3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ inline f3 operator*(float s, f3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__device__ inline float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline f3 cross(f3 a, f3 b)
+{
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// ------------------------------------------------------------------ interpolation
+// Linear (CIC) interpolation of one component on its own staggered lattice (base index and
+// weights per axis), from an array with element strides (1, sy, sz).
+template <int DIM>
+__device__ inline float interp(const float* __restrict__ F, int bx, int by, int bz, float wx,
+                               float wy, float wz, int sy, int sz)
+{
+    const float* p = F + bx + sy * by + (DIM == 3 ? sz * bz : 0);
+    float a = p[0] + wx * (p[1] - p[0]);
+    float b = p[sy] + wx * (p[sy + 1] - p[sy]);
+    float r = a + wy * (b - a);
+    if (DIM == 3) {
+        const float* q = p + sz;
+        float c = q[0] + wx * (q[1] - q[0]);
+        float d = q[sy] + wx * (q[sy + 1] - q[sy]);
+        float r2 = c + wy * (d - c);
+        r = r + wz * (r2 - r);
+    }
+    return r;
+}
+
+// Per axis: the integer lattice uses (cell, offset); the half-shifted lattice uses
+// (cell-1, offset+1/2) below the cell centre and (cell, offset-1/2) above it.
+struct AxisW {
+    int b0, bh;
+    float w0, wh;
+};
+__device__ inline AxisW axis_weights(int c, float o)
+{
+    AxisW a;
+    const bool lo = o < 0.5f;
+    a.b0 = c;
+    a.w0 = o;
+    a.bh = lo ? c - 1 : c;
+    a.wh = lo ? o + 0.5f : o - 0.5f;
+    return a;
+}
+
+// Gather the six Yee components at a particle.  Fields are arrays 0..2 = E, 3..5 = B.
+template <int DIM, class FieldAt>
+__device__ inline void gather(FieldAt fa, int sy, int sz, int cx, int cy, int cz, float ox,
+                              float oy, float oz, f3& E, f3& B)
+{
+    const AxisW X = axis_weights(cx, ox), Y = axis_weights(cy, oy);
+    AxisW Z = axis_weights(cz, oz);
+    if (DIM == 2) Z = AxisW{0, 0, 0.f, 0.f};
+    E.x = interp<DIM>(fa(0), X.bh, Y.b0, Z.b0, X.wh, Y.w0, Z.w0, sy, sz);
+    E.y = interp<DIM>(fa(1), X.b0, Y.bh, Z.b0, X.w0, Y.wh, Z.w0, sy, sz);
+    E.z = interp<DIM>(fa(2), X.b0, Y.b0, Z.bh, X.w0, Y.w0, Z.wh, sy, sz);
+    B.x = interp<DIM>(fa(3), X.b0, Y.bh, Z.bh, X.w0, Y.wh, Z.wh, sy, sz);
+    B.y = interp<DIM>(fa(4), X.bh, Y.b0, Z.bh, X.wh, Y.w0, Z.wh, sy, sz);
+    B.z = interp<DIM>(fa(5), X.bh, Y.bh, Z.b0, X.wh, Y.wh, Z.w0, sy, sz);
+}
+
+// ------------------------------------------------------------------ pushers
+// Standard Boris (the alpha = 0 and Lambda = 0 limits of the operators of Secs. 2.2, 3.2).
+__device__ inline f3 push_boris(f3 u, f3 E, f3 B, float qm_hdt)
+{
+    const f3 eps = qm_hdt * E;
+    const f3 um = u + eps;
+    const float ig = rsqrtf(1.f + dot(um, um));
+    const f3 t = (qm_hdt * ig) * B;
+    const float d = 2.f / (1.f + dot(t, t));
+    const f3 c1 = cross(um, t);
+    const f3 c2 = cross(c1, t);
+    return um + d * (c1 + c2) + eps;
+}
+
+// Shearing-box push (Sec. 2.2, eq. OAu_disc): closed form
+//   u+ = B(u-) + R(S u-) + R(S w)/(1-g),  w = B(u-) + R(S u-),  g = S_2 . R(e_y),
+// with S u = e_y (s2 . u); R(e_y) written out.  gamma-bar from the printed first-order
+// approximation refined by two fixed-point steps of g^2 = 1 + A + K/g.
+__device__ inline f3 push_shear(f3 u, f3 E, f3 B, float qm_hdt, float alpha1, float alpha2,
+                                float om_dt)
+{
+    const f3 eps = qm_hdt * E;
+    const f3 um = u + eps;
+    const float uu = dot(um, um);
+    const float ue = dot(um, eps);
+    const float A = uu + 2.f * alpha1 * um.x * um.y;
+    const float K = 2.f * alpha2 * ue * um.y;
+    const float g0 = sqrtf(1.f + uu);
+    float g = g0 + (alpha1 * um.x * um.y * g0 + alpha2 * ue * um.y) / (g0 * g0);
+    g = sqrtf(1.f + A + K / g);
+    g = sqrtf(1.f + A + K / g);
+    const float ig = 1.f / g;
+    f3 t = (qm_hdt * ig) * B;
+    t.z += om_dt;
+    const f3 et = ig * eps;
+    const f3 s2 = mk(alpha1 + alpha2 * et.x, alpha2 * et.y, alpha2 * et.z);
+    const float d = 1.f / (1.f + dot(t, t));
+    const f3 c1 = cross(um, t);
+    const f3 c2 = cross(c1, t);
+    const f3 Bu = um + (2.f * d) * (c1 + c2);
+    const f3 Rey = mk(d * (t.z + t.x * t.y), 1.f - d * (t.x * t.x + t.z * t.z), d * (t.y * t.z - t.x));
+    const float gg = dot(s2, Rey);
+    const f3 w = Bu + dot(s2, um) * Rey;
+    const f3 up = w + (dot(s2, w) / (1.f - gg)) * Rey;
+    return up + eps;
+}
+
+// Expanding-box push (Sec. 3.2, eq. EBu_disc) with the printed modified Boris operator
+//   B^(L)(v) = L~ v + ((1+L~) v x t~ + ((1+L~) v x t~) x t~)/(1 + t~^2),
+// gamma-bar = sqrt(1 + ((1+Lambda) u-)^2), t~ = tau/(1-Lambda).
+__device__ inline f3 push_expand(f3 u, f3 E, f3 B, float qm_hdt, const float lam1p[3],
+                                 const float ltil[3], const float tfac[3])
+{
+    const f3 eps = qm_hdt * E;
+    const f3 um = u + eps;
+    const f3 lu = mk(lam1p[0] * um.x, lam1p[1] * um.y, lam1p[2] * um.z);
+    const float ig = rsqrtf(1.f + dot(lu, lu));
+    const float s = qm_hdt * ig;
+    const f3 t = mk(s * tfac[0] * B.x, s * tfac[1] * B.y, s * tfac[2] * B.z);
+    const f3 w = mk((1.f + ltil[0]) * um.x, (1.f + ltil[1]) * um.y, (1.f + ltil[2]) * um.z);
+    const float d = 1.f / (1.f + dot(t, t));
+    const f3 c1 = cross(w, t);
+    const f3 c2 = cross(c1, t);
+    const f3 up = mk(ltil[0] * um.x, ltil[1] * um.y, ltil[2] * um.z) + d * (c1 + c2);
+    return up + eps;
+}
+
+// ------------------------------------------------------------------ positions
+// In-cell offset renormalisation after s = off + delta (|delta| < 1), in FP32:
+// s >= 1 -> (+1, s-1) exact; s < 0 -> t = s+1, (-1, t) if t < 1 else (0, 0).
+__device__ inline float renorm(float s, int& dc)
+{
+    if (s >= 1.f) {
+        dc = 1;
+        return __fsub_rn(s, 1.f);
+    }
+    if (s < 0.f) {
+        const float t = __fadd_rn(s, 1.f);
+        if (t < 1.f) {
+            dc = -1;
+            return t;
+        }
+        dc = 0;
+        return 0.f;
+    }
+    dc = 0;
+    return s;
+}
+
+// ------------------------------------------------------------------ Esirkepov deposit
+// CIC shape on the 3 nodes nearest-1..nearest+1 of one axis, xi = position - nearest node.
+struct Shape3 {
+    float s0[3], ds[3];
+};
+__device__ inline Shape3 shape3(float xi0, float xi1)
+{
+    Shape3 S;
+    const float a0 = fmaxf(0.f, -xi0), b0 = 1.f - fabsf(xi0), c0 = fmaxf(0.f, xi0);
+    const float a1 = fmaxf(0.f, -xi1), b1 = 1.f - fabsf(xi1), c1 = fmaxf(0.f, xi1);
+    S.s0[0] = a0;
+    S.s0[1] = b0;
+    S.s0[2] = c0;
+    S.ds[0] = a1 - a0;
+    S.ds[1] = b1 - b0;
+    S.ds[2] = c1 - c0;
+    return S;
+}
+
+// Esirkepov decomposition of the density change into currents (CIC):
+//   J_x on the two edges around the nearest node: -q/dt DS_x[-1] P and +q/dt DS_x[+1] P,
+//   P = S0_y (S0_z + DS_z/2) + DS_y (S0_z/2 + DS_z/3) (cyclic for y and z);
+//   2D: P = S0_y + DS_y/2, and J_z = q dz/dt (S0_x (S0_y + DS_y/2) + DS_x (S0_y/2 + DS_y/3)).
+// Acc::add(c, x, y, z, v) accumulates v into component c at (edge/node) index (x, y, z)
+// relative to the nearest node minus one.
+template <int DIM, class Acc>
+__device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, const Shape3& Z,
+                                 float q_dt, float dz)
+{
+    if (DIM == 3) {
+        float z1[3], z2[3], y1[3], y2[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            z1[c] = Z.s0[c] + 0.5f * Z.ds[c];
+            z2[c] = 0.5f * Z.s0[c] + (1.f / 3.f) * Z.ds[c];
+            y1[c] = Y.s0[c] + 0.5f * Y.ds[c];
+            y2[c] = 0.5f * Y.s0[c] + (1.f / 3.f) * Y.ds[c];
+        }
+        const float xl = -q_dt * X.ds[0], xh = q_dt * X.ds[2];
+        const float yl = -q_dt * Y.ds[0], yh = q_dt * Y.ds[2];
+        const float zl = -q_dt * Z.ds[0], zh = q_dt * Z.ds[2];
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const float Pyz = Y.s0[b] * z1[c] + Y.ds[b] * z2[c];
+                acc.add(0, 0, b, c, xl * Pyz);
+                acc.add(0, 1, b, c, xh * Pyz);
+                const float Pxz = X.s0[b] * z1[c] + X.ds[b] * z2[c];
+                acc.add(1, b, 0, c, yl * Pxz);
+                acc.add(1, b, 1, c, yh * Pxz);
+                const float Pxy = X.s0[b] * y1[c] + X.ds[b] * y2[c];
+                acc.add(2, b, c, 0, zl * Pxy);
+                acc.add(2, b, c, 1, zh * Pxy);
+            }
+    } else {
+        const float xl = -q_dt * X.ds[0], xh = q_dt * X.ds[2];
+        const float yl = -q_dt * Y.ds[0], yh = q_dt * Y.ds[2];
+        const float jz = q_dt * dz;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const float Py = Y.s0[b] + 0.5f * Y.ds[b];
+            acc.add(0, 0, b, 0, xl * Py);
+            acc.add(0, 1, b, 0, xh * Py);
+            const float Px = X.s0[b] + 0.5f * X.ds[b];
+            acc.add(1, b, 0, 0, yl * Px);
+            acc.add(1, b, 1, 0, yh * Px);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                const float W = X.s0[a] * (Y.s0[b] + 0.5f * Y.ds[b]) +
+                                X.ds[a] * (0.5f * Y.s0[b] + (1.f / 3.f) * Y.ds[b]);
+                acc.add(2, a, b, 0, jz * W);
+            }
+        }
+    }
+}
+
+// LDS accumulator: (JX, JY, JZ) region per component, origin at the tile origin minus one.
+template <int JX, int JY, int JZ>
+struct LdsAcc {
+    float* J;
+    int base;  // index of (nearest node - 1) per axis in the region
+    __device__ inline void add(int c, int x, int y, int z, float v)
+    {
+        atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], v);
+    }
+};
+
+// Global accumulator on the guarded current arrays (slow path).
+struct GlobalAcc {
+    float* const* J;
+    int64_t base;
+    int sy, sz;
+    __device__ inline void add(int c, int x, int y, int z, float v)
+    {
+        if (v != 0.f) unsafeAtomicAdd(&J[c][base + x + (int64_t)sy * y + (int64_t)sz * z], v);
+    }
+};
+
+// ------------------------------------------------------------------ the fused kernel
+template <int DIM, int TX, int TY, int TZ>
+struct Geo {
+    static constexpr int FX = TX + 2, FY = TY + 2, FZ = DIM == 3 ? TZ + 2 : 1;
+    static constexpr int FS = FX * FY * FZ;
+    static constexpr int JX = TX + 3, JY = TY + 3, JZ = DIM == 3 ? TZ + 3 : 1;
+    static constexpr int JS = JX * JY * JZ;
+    static constexpr int LDS_FLOATS = 6 * FS + 3 * JS;
+};
+
+template <int DIM>
+__device__ inline void tile_origin(const StepDev& P, int tile, int t0[3], int ext[3])
+{
+    const int tx = tile % P.tl.nt[0];
+    const int r = tile / P.tl.nt[0];
+    const int ty = r % P.tl.nt[1];
+    const int tz = r / P.tl.nt[1];
+    const int tc[3] = {tx, ty, tz};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        t0[d] = tc[d] << P.tl.lt[d];
+        const int e = P.n[d] - t0[d];
+        ext[d] = e < (1 << P.tl.lt[d]) ? e : (1 << P.tl.lt[d]);
+    }
+    if (DIM == 2) {
+        t0[2] = 0;
+        ext[2] = 1;
+    }
+}
+
+__device__ inline void latch(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
+
+template <int DIM, int TX, int TY, int TZ, int FRAME>
+__global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
+{
+    using G = Geo<DIM, TX, TY, TZ>;
+    __shared__ float lds[G::LDS_FLOATS];
+    float* const F = lds;              // 6 field components
+    float* const Jl = lds + 6 * G::FS; // 3 current components
+
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    int t0[3], ext[3];
+    tile_origin<DIM>(P, tile, t0, ext);
+    const int tid = threadIdx.x;
+
+    // stage E, B of the tile and one guard cell per side
+    for (int e = tid; e < 6 * G::FS; e += kBlock) {
+        const int comp = e / G::FS;
+        const int r = e - comp * G::FS;
+        const int lx = r % G::FX, ly = (r / G::FX) % G::FY, lz = r / (G::FX * G::FY);
+        float v = 0.f;
+        if (lx < ext[0] + 2 && ly < ext[1] + 2 && (DIM == 2 || lz < ext[2] + 2)) {
+            const float* src = comp < 3 ? P.E[comp] : P.B[comp - 3];
+            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
+                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
+            v = src[g];
+        }
+        F[e] = v;
+    }
+    if (fuse)
+        for (int e = tid; e < 3 * G::JS; e += kBlock) Jl[e] = 0.f;
+    __syncthreads();
+
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    for (int s = 0; s < P.nsp; s++) {
+        const SpeciesDev& S = P.sp[s];
+        const int beg = S.toff[tile], end = S.toff[tile + 1];
+        for (int slot = beg + tid; slot < end; slot += kBlock) {
+            const int src = S.perm[slot];
+            int cx, cy, cz;
+            P.cc.decode(S.cell_in[src], cx, cy, cz);
+            const float ox = S.off_in[0][src], oy = S.off_in[1][src];
+            const float oz = DIM == 3 ? S.off_in[2][src] : 0.f;
+            f3 u = mk(S.u_in[0][src], S.u_in[1][src], S.u_in[2][src]);
+
+            const int lx = cx - t0[0] + 1, ly = cy - t0[1] + 1, lz = DIM == 3 ? cz - t0[2] + 1 : 0;
+            const bool in_tile = (unsigned)(lx - 1) < (unsigned)ext[0] &&
+                                 (unsigned)(ly - 1) < (unsigned)ext[1] &&
+                                 (DIM == 2 || (unsigned)(lz - 1) < (unsigned)ext[2]);
+            f3 E, B;
+            if (in_tile) {
+                auto fa = [&](int c) -> const float* { return F + c * G::FS; };
+                gather<DIM>(fa, G::FX, G::FX * G::FY, lx, ly, lz, ox, oy, oz, E, B);
+            } else {
+                auto fa = [&](int c) -> const float* { return c < 3 ? P.E[c] : P.B[c - 3]; };
+                gather<DIM>(fa, P.sy, P.sz, cx, cy, cz, ox, oy, oz, E, B);
+                atomicAdd(&P.ctr[0], 1ull);
+                latch(P.err, 4u);
+            }
+
+            // ---- push
+            const float xr = (float)cx - P.half_nx + ox; // radial x of the shearing box
+            if (FRAME == kShear)
+                u = push_shear(u, E, B, S.qm_hdt, P.alpha1, P.sO * xr, P.om_dt);
+            else if (FRAME == kExpand)
+                u = push_expand(u, E, B, S.qm_hdt, P.lam1p, P.ltil, P.tfac);
+            else
+                u = push_boris(u, E, B, S.qm_hdt);
+            if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z))) latch(P.err, 2u);
+
+            // ---- displacement of the deposit (comoving for the shearing box, primed for the
+            // expanding box)
+            const float ig = rsqrtf(1.f + dot(u, u));
+            const float hs = P.dt * ig;
+            f3 D = hs * u;
+            if (FRAME == kExpand) D = mk(D.x * P.linv[0], D.y * P.linv[1], D.z * P.linv[2]);
+            if (fabsf(D.x) >= 0.5f || fabsf(D.y) >= 0.5f || (DIM == 3 && fabsf(D.z) >= 0.5f))
+                latch(P.err, 1u);
+
+            // ---- deposit xn -> xn + D
+            if (fuse) {
+                const int hx = ox >= 0.5f, hy = oy >= 0.5f, hz = DIM == 3 ? (oz >= 0.5f) : 0;
+                const float x0 = ox - (float)hx, y0 = oy - (float)hy, z0 = oz - (float)hz;
+                const Shape3 SX = shape3(x0, x0 + D.x), SY = shape3(y0, y0 + D.y);
+                const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}};
+                if (in_tile) {
+                    LdsAcc<G::JX, G::JY, G::JZ> acc{
+                        Jl, (lx + hx - 1) + G::JX * ((ly + hy - 1) + G::JY * (DIM == 3 ? lz + hz - 1 : 0))};
+                    esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
+                } else {
+                    GlobalAcc acc{P.J, (int64_t)(cx + hx - 1) + (int64_t)P.sy * (cy + hy - 1) +
+                                           (DIM == 3 ? (int64_t)P.sz * (cz + hz - 1) : 0),
+                                  P.sy, P.sz};
+                    esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
+                }
+            } else {
+                S.ws_cell[slot] = P.cc.encode(cx, cy, cz);
+                S.ws_off[0][slot] = ox;
+                S.ws_off[1][slot] = oy;
+                if (DIM == 3) S.ws_off[2][slot] = oz;
+                S.ws_disp[0][slot] = D.x;
+                S.ws_disp[1][slot] = D.y;
+                S.ws_disp[2][slot] = D.z;
+            }
+
+            // ---- new position: x' = x^n + D, then (shearing box) the shear move
+            // y -= s Omega0 (x' + x^n)/2 dt (Sec. 2.2)
+            float dyt = D.y;
+            if (FRAME == kShear) dyt = D.y - P.sO * P.dt * (xr + 0.5f * D.x);
+            int dcx, dcy, dcz = 0;
+            float nox = renorm(__fadd_rn(ox, D.x), dcx);
+            float noy = renorm(__fadd_rn(oy, dyt), dcy);
+            float noz = DIM == 3 ? renorm(__fadd_rn(oz, D.z), dcz) : 0.f;
+            int ncx = cx + dcx, ncy = cy + dcy, ncz = cz + dcz;
+            if (ncx >= nx || ncx < 0) {
+                // shearing-periodic x (Sec. 2.1): leaving through x_o re-enters at x_i with
+                // y + Delta y_s(t^{n+1}); leaving through x_i re-enters at x_o with y - Delta y_s
+                const bool out = ncx >= nx;
+                ncx += out ? -nx : nx;
+                if (FRAME == kShear) {
+                    int d2;
+                    noy = renorm(__fadd_rn(noy, out ? P.dys_frac : -P.dys_frac), d2);
+                    ncy += (out ? P.dys_int : -P.dys_int) + d2;
+                    ncy %= ny;
+                    if (ncy < 0) ncy += ny;
+                }
+            }
+            if (ncy >= ny) ncy -= ny;
+            if (ncy < 0) ncy += ny;
+            if (DIM == 3) {
+                if (ncz >= nz) ncz -= nz;
+                if (ncz < 0) ncz += nz;
+            }
+            int32_t ncell = P.cc.encode(ncx, ncy, ncz);
+
+            // ---- leaky box (Sec. 4.1)
+            if (FRAME == kLeaky) {
+                const uint32_t pid = S.id_in[src];
+                if (P.leaky_mode == 0) {
+                    float rx = S.dr_in[0][src] + D.x, ry = S.dr_in[1][src] + D.y;
+                    float rz = S.dr_in[2][src] + D.z;
+                    float m = fmaxf(fabsf(rx), fabsf(ry));
+                    if (P.use_3vec) m = fmaxf(m, fabsf(rz));
+                    if (m >= P.l_esc) {
+                        uint32_t w[4] = {pid, P.step_lo, 1u, P.box_id};
+                        philox4x32_10(w, P.key0, P.key1);
+                        // inverse CDF of |u| (bulk bins linear in p, top bin linear in -log2(1-p))
+                        const uint32_t bin = w[0] >> 20, rr = w[0] & 0xFFFFFu;
+                        float um;
+                        if (bin < (uint32_t)(kMjBins - 1)) {
+                            const float fr = (float)rr * (1.f / 1048576.f);
+                            um = P.mj[bin] + fr * (P.mj[bin + 1] - P.mj[bin]);
+                        } else {
+                            const float sv = 20.f - log2f((float)(0x100000u - rr));
+                            const float xk = sv * ((float)kMjTail / 20.f);
+                            int k = (int)xk;
+                            k = k > kMjTail - 1 ? kMjTail - 1 : k;
+                            const float fr = xk - (float)k;
+                            const float* T = P.mj + kMjBins - 1;
+                            um = T[k] + fr * (T[k + 1] - T[k]);
+                        }
+                        const float mu = 2.f * ((float)(w[1] >> 8) * (1.f / 16777216.f)) - 1.f;
+                        const float phi = 6.283185307179586f * ((float)(w[2] >> 8) * (1.f / 16777216.f));
+                        float sp, cp;
+                        sincosf(phi, &sp, &cp);
+                        const float st = sqrtf(fmaxf(0.f, 1.f - mu * mu));
+                        u = mk(um * st * cp, um * st * sp, um * mu);
+                        rx = ry = rz = 0.f;
+                    }
+                    S.dr_out[0][slot] = rx;
+                    S.dr_out[1][slot] = ry;
+                    S.dr_out[2][slot] = rz;
+                } else {
+                    const double g2m1 = ((double)u.x * (double)u.x + (double)u.y * (double)u.y) +
+                                        (double)u.z * (double)u.z;
+                    if (g2m1 > P.g2thr) {
+                        uint32_t w[4] = {pid, P.step_lo, 0u, P.box_id};
+                        philox4x32_10(w, P.key0, P.key1);
+                        if (w[0] < P.esc_thr) {
+                            ncell = -1;
+                            atomicAdd(&P.ctr[1], 1ull);
+                        }
+                    }
+                }
+            }
+
+            S.cell_out[slot] = ncell;
+            S.off_out[0][slot] = nox;
+            S.off_out[1][slot] = noy;
+            if (DIM == 3) S.off_out[2][slot] = noz;
+            S.u_out[0][slot] = u.x;
+            S.u_out[1][slot] = u.y;
+            S.u_out[2][slot] = u.z;
+            if (P.track_ids) S.id_out[slot] = S.id_in[src];
+        }
+    }
+
+    if (!fuse) return;
+    __syncthreads();
+    // flush the tile current (interior + deposit halo) with float atomics
+    for (int e = tid; e < 3 * G::JS; e += kBlock) {
+        const float v = Jl[e];
+        if (v == 0.f) continue;
+        const int comp = e / G::JS;
+        const int r = e - comp * G::JS;
+        const int lx = r % G::JX, ly = (r / G::JX) % G::JY, lz = r / (G::JX * G::JY);
+        if (lx < ext[0] + 3 && ly < ext[1] + 3 && (DIM == 2 || lz < ext[2] + 3)) {
+            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
+                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
+            unsafeAtomicAdd(&P.J[comp][g], v);
+        }
+    }
+}
+
+// Unfused deposit: the same Esirkepov tile accumulation from the positions and deposit
+// displacements saved by an unfused push (in sorted slot order).
+template <int DIM, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void deposit_kernel(StepDev P)
+{
+    using G = Geo<DIM, TX, TY, TZ>;
+    __shared__ float Jl[3 * G::JS];
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    int t0[3], ext[3];
+    tile_origin<DIM>(P, tile, t0, ext);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 3 * G::JS; e += kBlock) Jl[e] = 0.f;
+    __syncthreads();
+    for (int s = 0; s < P.nsp; s++) {
+        const SpeciesDev& S = P.sp[s];
+        const int beg = S.toff[tile], end = S.toff[tile + 1];
+        for (int slot = beg + tid; slot < end; slot += kBlock) {
+            int cx, cy, cz;
+            P.cc.decode(S.ws_cell[slot], cx, cy, cz);
+            const float ox = S.ws_off[0][slot], oy = S.ws_off[1][slot];
+            const float oz = DIM == 3 ? S.ws_off[2][slot] : 0.f;
+            const f3 D = mk(S.ws_disp[0][slot], S.ws_disp[1][slot], S.ws_disp[2][slot]);
+            const int lx = cx - t0[0] + 1, ly = cy - t0[1] + 1, lz = DIM == 3 ? cz - t0[2] + 1 : 0;
+            const bool in_tile = (unsigned)(lx - 1) < (unsigned)ext[0] &&
+                                 (unsigned)(ly - 1) < (unsigned)ext[1] &&
+                                 (DIM == 2 || (unsigned)(lz - 1) < (unsigned)ext[2]);
+            const int hx = ox >= 0.5f, hy = oy >= 0.5f, hz = DIM == 3 ? (oz >= 0.5f) : 0;
+            const float x0 = ox - (float)hx, y0 = oy - (float)hy, z0 = oz - (float)hz;
+            const Shape3 SX = shape3(x0, x0 + D.x), SY = shape3(y0, y0 + D.y);
+            const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}};
+            if (in_tile) {
+                LdsAcc<G::JX, G::JY, G::JZ> acc{
+                    Jl, (lx + hx - 1) + G::JX * ((ly + hy - 1) + G::JY * (DIM == 3 ? lz + hz - 1 : 0))};
+                esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
+            } else {
+                GlobalAcc acc{P.J, (int64_t)(cx + hx - 1) + (int64_t)P.sy * (cy + hy - 1) +
+                                       (DIM == 3 ? (int64_t)P.sz * (cz + hz - 1) : 0),
+                              P.sy, P.sz};
+                esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 3 * G::JS; e += kBlock) {
+        const float v = Jl[e];
+        if (v == 0.f) continue;
+        const int comp = e / G::JS;
+        const int r = e - comp * G::JS;
+        const int lx = r % G::JX, ly = (r / G::JX) % G::JY, lz = r / (G::JX * G::JY);
+        if (lx < ext[0] + 3 && ly < ext[1] + 3 && (DIM == 2 || lz < ext[2] + 3)) {
+            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
+                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
+            unsafeAtomicAdd(&P.J[comp][g], v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <int DIM, int TX, int TY, int TZ>
+static hipError_t launch_shape(const StepDev& P, int fuse, hipStream_t st)
+{
+    const dim3 grid(P.tl.n_tiles), block(kBlock);
+    switch (P.frame) {
+    case kShear:
+        gpd_kernel<DIM, TX, TY, TZ, kShear><<<grid, block, 0, st>>>(P, fuse);
+        break;
+    case kExpand:
+        gpd_kernel<DIM, TX, TY, TZ, kExpand><<<grid, block, 0, st>>>(P, fuse);
+        break;
+    case kLeaky:
+        gpd_kernel<DIM, TX, TY, TZ, kLeaky><<<grid, block, 0, st>>>(P, fuse);
+        break;
+    default:
+        gpd_kernel<DIM, TX, TY, TZ, kPlain><<<grid, block, 0, st>>>(P, fuse);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int DIM, int TX, int TY, int TZ>
+static hipError_t launch_dep_shape(const StepDev& P, hipStream_t st)
+{
+    deposit_kernel<DIM, TX, TY, TZ><<<dim3(P.tl.n_tiles), dim3(kBlock), 0, st>>>(P);
+    return hipGetLastError();
+}
+
+// Supported tile shapes (edges in cells).  Returns false for an unsupported shape.
+bool tile_shape_supported(int dim, const int t[3])
+{
+    if (dim == 3) return (t[0] == 8 && t[1] == 8 && t[2] == 8) || (t[0] == 4 && t[1] == 4 && t[2] == 4);
+    return t[2] == 1 && ((t[0] == 16 && t[1] == 16) || (t[0] == 32 && t[1] == 32) ||
+                         (t[0] == 8 && t[1] == 8) || (t[0] == 32 && t[1] == 16));
+}
+
+hipError_t launch_gather_push(const StepDev& P, const int t[3], int fuse, hipStream_t st)
+{
+    if (P.dim == 3) {
+        if (t[0] == 8) return launch_shape<3, 8, 8, 8>(P, fuse, st);
+        return launch_shape<3, 4, 4, 4>(P, fuse, st);
+    }
+    if (t[0] == 16) return launch_shape<2, 16, 16, 1>(P, fuse, st);
+    if (t[0] == 8) return launch_shape<2, 8, 8, 1>(P, fuse, st);
+    if (t[1] == 16) return launch_shape<2, 32, 16, 1>(P, fuse, st);
+    return launch_shape<2, 32, 32, 1>(P, fuse, st);
+}
+
+hipError_t launch_deposit(const StepDev& P, const int t[3], hipStream_t st)
+{
+    if (P.dim == 3) {
+        if (t[0] == 8) return launch_dep_shape<3, 8, 8, 8>(P, st);
+        return launch_dep_shape<3, 4, 4, 4>(P, st);
+    }
+    if (t[0] == 16) return launch_dep_shape<2, 16, 16, 1>(P, st);
+    if (t[0] == 8) return launch_dep_shape<2, 8, 8, 1>(P, st);
+    if (t[1] == 16) return launch_dep_shape<2, 32, 16, 1>(P, st);
+    return launch_dep_shape<2, 32, 32, 1>(P, st);
+}
+
+}  // namespace pic

@@ -1,0 +1,516 @@
+// grid.hip — grid kernels of the particle hot path (gfx950): guard fills with the
+// shearing-periodic boundary (Sec. 2.1), the current fold with the J' transport along y
+// (Sec. 2.2), the Maxwell steps of the three frames (Yee; Yee with the expanding-box scale
+// factors of Sec. 3.2; implicit midpoint with upwinded advection solved by fixed-point
+// iteration, Sec. 2.2) and the FP64 reductions.
+//
+// Every grid array carries kGuard guard cells on each side of each axis (z: none in 2D);
+// pointers address the interior cell (0,0,0) and the x stride is 1.
+#include "pic_internal.h"
+
+namespace pic {
+
+__device__ inline int64_t gidx(const GridDev& G, int x, int y, int z)
+{
+    return (int64_t)x + (int64_t)G.sy * y + (int64_t)G.sz * z;
+}
+__device__ inline int wrapn(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// ------------------------------------------------------------------ guard fill
+// Every guard cell takes its value from interior cells: y, z periodic; x periodic, or for the
+// shearing box F(x_o + m, y) = F(x_i + m, y + dys) and F(x_i - m, y) = F(x_o - m, y - dys)
+// with a fractional dys applied by linear interpolation along y.
+struct Comp6 {
+    float* p[6];
+};
+
+__global__ __launch_bounds__(kBlock) void fill_guards_kernel(GridDev G, Comp6 A, int slab,
+                                                             int shear, int dys_int, float dys_w)
+{
+    const int c = blockIdx.y;
+    float* F = A.p[c];
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+    const int NYg = G.n[1] + 2 * gy, NZg = G.n[2] + 2 * gz;
+    int x, y, z;
+    if (slab == 0) {  // x guard slabs over the whole guarded y, z
+        const int64_t tot = (int64_t)2 * gx * NYg * NZg;
+        if (t >= tot) return;
+        int m = (int)(t % (2 * gx));
+        int64_t r = t / (2 * gx);
+        y = (int)(r % NYg) - gy;
+        z = (int)(r / NYg) - gz;
+        x = m < gx ? m - gx : G.n[0] + (m - gx);
+    } else if (slab == 1) {  // y guard slabs over interior x, guarded z
+        const int64_t tot = (int64_t)G.n[0] * 2 * gy * NZg;
+        if (t >= tot) return;
+        x = (int)(t % G.n[0]);
+        int64_t r = t / G.n[0];
+        int m = (int)(r % (2 * gy));
+        z = (int)(r / (2 * gy)) - gz;
+        y = m < gy ? m - gy : G.n[1] + (m - gy);
+    } else {  // z guard slabs over interior x, y
+        const int64_t tot = (int64_t)G.n[0] * G.n[1] * 2 * gz;
+        if (t >= tot) return;
+        x = (int)(t % G.n[0]);
+        int64_t r = t / G.n[0];
+        y = (int)(r % G.n[1]);
+        int m = (int)(r / G.n[1]);
+        z = m < gz ? m - gz : G.n[2] + (m - gz);
+    }
+    const int sz_ = wrapn(z, G.n[2]);
+    float v;
+    if (x < 0 || x >= G.n[0]) {
+        const bool hi = x >= G.n[0];
+        const int sx = hi ? x - G.n[0] : x + G.n[0];
+        if (shear) {
+            // hi: y + dys = y + dys_int + w; lo: y - dys = y - dys_int - 1 + (1 - w)
+            int js;
+            float w;
+            if (hi) {
+                js = dys_int;
+                w = dys_w;
+            } else {
+                js = -dys_int - (dys_w > 0.f ? 1 : 0);
+                w = dys_w > 0.f ? 1.f - dys_w : 0.f;
+            }
+            const float a = F[gidx(G, sx, wrapn(y + js, G.n[1]), sz_)];
+            const float b = F[gidx(G, sx, wrapn(y + js + 1, G.n[1]), sz_)];
+            v = (1.f - w) * a + w * b;
+        } else {
+            v = F[gidx(G, sx, wrapn(y, G.n[1]), sz_)];
+        }
+    } else {
+        v = F[gidx(G, x, wrapn(y, G.n[1]), sz_)];
+    }
+    F[gidx(G, x, y, z)] = v;
+}
+
+// ------------------------------------------------------------------ current fold
+struct Comp3 {
+    float* p[3];
+};
+
+// Periodic fold along axis a (1 = y, 2 = z) over the whole guarded extent of the axes before
+// it (x and, for z, y) and the interior of the others.
+__global__ __launch_bounds__(kBlock) void fold_periodic_kernel(GridDev G, Comp3 J, int a)
+{
+    float* F = J.p[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int gx = G.g[0], gy = G.g[1];
+    const int NXg = G.n[0] + 2 * gx, NYg = G.n[1] + 2 * gy;
+    const int na = G.n[a], ga = G.g[a];
+    const int nl = na < 2 * ga ? na : 2 * ga;  // boundary layers that receive
+    int x, y, z, m;
+    if (a == 2) {
+        const int64_t tot = (int64_t)NXg * NYg * nl;
+        if (t >= tot) return;
+        x = (int)(t % NXg) - gx;
+        int64_t r = t / NXg;
+        y = (int)(r % NYg) - gy;
+        m = (int)(r / NYg);
+        z = m < ga ? m : na - (m - ga) - 1;
+        if (m >= ga && z < ga) return;  // a small axis: layer already handled
+    } else {
+        const int64_t tot = (int64_t)NXg * nl * G.n[2];
+        if (t >= tot) return;
+        x = (int)(t % NXg) - gx;
+        int64_t r = t / NXg;
+        m = (int)(r % nl);
+        z = (int)(r / nl);
+        y = m < ga ? m : na - (m - ga) - 1;
+        if (m >= ga && y < ga) return;
+    }
+    const int i = a == 2 ? z : y;
+    float v = 0.f;
+    int64_t self = gidx(G, x, y, z);
+    if (i < ga) v += F[self + (int64_t)na * (a == 2 ? G.sz : G.sy)];
+    if (i >= na - ga) v += F[self - (int64_t)na * (a == 2 ? G.sz : G.sy)];
+    F[self] += v;
+}
+
+// J' transport along y by d = v_{s,y}(x) dt/2, v_{s,y} = -s Omega0 x at each component's x
+// (Sec. 2.2), as J(y - d) by linear interpolation, over the guarded x range; out = in moved.
+__global__ __launch_bounds__(kBlock) void shear_advect_kernel(GridDev G, Comp3 Jin, Comp3 Jout,
+                                                              float sO_hdt, float half_nx)
+{
+    const int c = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int gx = G.g[0];
+    const int NXg = G.n[0] + 2 * gx;
+    const int64_t tot = (int64_t)NXg * G.n[1] * G.n[2];
+    if (t >= tot) return;
+    const int x = (int)(t % NXg) - gx;
+    const int64_t r = t / NXg;
+    const int y = (int)(r % G.n[1]);
+    const int z = (int)(r / G.n[1]);
+    const float xc = (float)x + (c == 0 ? 0.5f : 0.f) - half_nx;
+    const float d = -sO_hdt * xc;
+    const float fl = floorf(d);
+    const int m = (int)fl;
+    const float w = d - fl;
+    const float* F = Jin.p[c];
+    const float a = F[gidx(G, x, wrapn(y - m, G.n[1]), z)];
+    const float b = F[gidx(G, x, wrapn(y - m - 1, G.n[1]), z)];
+    Jout.p[c][gidx(G, x, y, z)] = (1.f - w) * a + w * b;
+}
+
+// x fold as a gather into interior cells: out(i) = in(i) plus the x guard columns that map
+// to i (periodic, or shearing-periodic at dys as the transpose of the guard interpolation).
+// Runs over all interior cells when in != out, else over the boundary layers only.
+__global__ __launch_bounds__(kBlock) void fold_x_kernel(GridDev G, Comp3 Jin, Comp3 Jout,
+                                                        int all, int shear, int dys_int,
+                                                        float dys_w)
+{
+    const int c = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int nx = G.n[0], ga = G.g[0];
+    const int nl = all ? nx : (nx < 2 * ga ? nx : 2 * ga);
+    const int64_t tot = (int64_t)nl * G.n[1] * G.n[2];
+    if (t >= tot) return;
+    int m = (int)(t % nl);
+    const int64_t r = t / nl;
+    const int y = (int)(r % G.n[1]);
+    const int z = (int)(r / G.n[1]);
+    int x;
+    if (all) {
+        x = m;
+    } else {
+        x = m < ga ? m : nx - (m - ga) - 1;
+        if (m >= ga && x < ga) return;
+    }
+    const float* F = Jin.p[c];
+    float v = F[gidx(G, x, y, z)];
+    if (x < ga) {  // receives guard column x + nx, the image of (x, y + dys)
+        if (shear) {
+            // guard (nx+x, j) adds (1-w) to (x, j + js) and w to (x, j + js + 1), js = dys_int
+            v += (1.f - dys_w) * F[gidx(G, x + nx, wrapn(y - dys_int, G.n[1]), z)] +
+                 dys_w * F[gidx(G, x + nx, wrapn(y - dys_int - 1, G.n[1]), z)];
+        } else {
+            v += F[gidx(G, x + nx, y, z)];
+        }
+    }
+    if (x >= nx - ga) {  // receives guard column x - nx, the image of (x, y - dys)
+        if (shear) {
+            // shift -dys = js' + w' with js' = -dys_int - 1, w' = 1 - w (w > 0), else -dys_int
+            int js = -dys_int;
+            float w = 0.f;
+            if (dys_w > 0.f) {
+                js = -dys_int - 1;
+                w = 1.f - dys_w;
+            }
+            v += (1.f - w) * F[gidx(G, x - nx, wrapn(y - js, G.n[1]), z)] +
+                 w * F[gidx(G, x - nx, wrapn(y - js - 1, G.n[1]), z)];
+        } else {
+            v += F[gidx(G, x - nx, y, z)];
+        }
+    }
+    Jout.p[c][gidx(G, x, y, z)] = v;
+}
+
+// ------------------------------------------------------------------ Maxwell
+// Yee curls (c = 1, dx = 1).  E_j and B_j enter multiplied by ge[j], gb[j] (the l_j of the
+// expanding box, 1 otherwise).
+
+__device__ inline void cell_of(const GridDev& G, int64_t t, int& x, int& y, int& z)
+{
+    x = (int)(t % G.n[0]);
+    const int64_t r = t / G.n[0];
+    y = (int)(r % G.n[1]);
+    z = (int)(r / G.n[1]);
+}
+
+// B_i <- fout_i (fin_i B_i - dt/2 curl(g E)_i)
+__global__ __launch_bounds__(kBlock) void yee_b_kernel(MaxwellDev M)
+{
+    const GridDev& G = M.G;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
+    int x, y, z;
+    cell_of(G, t, x, y, z);
+    const int64_t i = gidx(G, x, y, z);
+    const int64_t sy = G.sy, sz = G.sz;
+    const bool d3 = G.dim == 3;
+    const float* Ex = M.E[0];
+    const float* Ey = M.E[1];
+    const float* Ez = M.E[2];
+    const float g0 = M.gf[0], g1 = M.gf[1], g2 = M.gf[2];
+    const float cx = g2 * (Ez[i + sy] - Ez[i]) - (d3 ? g1 * (Ey[i + sz] - Ey[i]) : 0.f);
+    const float cy = (d3 ? g0 * (Ex[i + sz] - Ex[i]) : 0.f) - g2 * (Ez[i + 1] - Ez[i]);
+    const float cz = g1 * (Ey[i + 1] - Ey[i]) - g0 * (Ex[i + sy] - Ex[i]);
+    const float h = 0.5f * M.dt;
+    M.B[0][i] = M.fout[0] * (M.fin[0] * M.B[0][i] - h * cx);
+    M.B[1][i] = M.fout[1] * (M.fin[1] * M.B[1][i] - h * cy);
+    M.B[2][i] = M.fout[2] * (M.fin[2] * M.B[2][i] - h * cz);
+}
+
+// E_i <- fout_i (fin_i E_i + dt curl(g B)_i - 4 pi dt J_i)
+__global__ __launch_bounds__(kBlock) void yee_e_kernel(MaxwellDev M)
+{
+    const GridDev& G = M.G;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
+    int x, y, z;
+    cell_of(G, t, x, y, z);
+    const int64_t i = gidx(G, x, y, z);
+    const int64_t sy = G.sy, sz = G.sz;
+    const bool d3 = G.dim == 3;
+    const float* Bx = M.B[0];
+    const float* By = M.B[1];
+    const float* Bz = M.B[2];
+    const float g0 = M.gf[0], g1 = M.gf[1], g2 = M.gf[2];
+    const float cx = g2 * (Bz[i] - Bz[i - sy]) - (d3 ? g1 * (By[i] - By[i - sz]) : 0.f);
+    const float cy = (d3 ? g0 * (Bx[i] - Bx[i - sz]) : 0.f) - g2 * (Bz[i] - Bz[i - 1]);
+    const float cz = g1 * (By[i] - By[i - 1]) - g0 * (Bx[i] - Bx[i - sy]);
+    const float fp = 4.f * 3.14159265358979f * M.dt;
+    M.E[0][i] = M.fout[0] * (M.fin[0] * M.E[0][i] + M.dt * cx - fp * M.J[0][i]);
+    M.E[1][i] = M.fout[1] * (M.fin[1] * M.E[1][i] + M.dt * cy - fp * M.J[1][i]);
+    M.E[2][i] = M.fout[2] * (M.fin[2] * M.E[2][i] + M.dt * cz - fp * M.J[2][i]);
+}
+
+// Shearing box, one fixed-point sweep of the implicit midpoint rule (Sec. 2.2):
+//   F_out = F^n + dt RHS((F^n + F^k)/2, J'),
+// RHS of eq. OAB / eq. OAE with v = -s Omega0 x:
+//   dB/dt  = -curl E' - v dB/dy (upwind) - s Omega0 <Bx> e_y
+//   dE'/dt = curl B - 4 pi J' + (+v dEx/dy, -v dEy/dy, +v dEz/dy) (upwind)
+//            - v (dEy/dx, dEx/dx + dEz/dz, dEy/dz) (central, averaged onto the component).
+
+__device__ inline float midv(const KsbDev& K, int c, int64_t i)
+{
+    return 0.5f * (K.Fn[c][i] + K.Fk[c][i]);
+}
+// upwind difference along y at i for transport velocity w
+__device__ inline float updy(const KsbDev& K, int c, int64_t i, int64_t sy, float w)
+{
+    return w > 0.f ? midv(K, c, i) - midv(K, c, i - sy) : midv(K, c, i + sy) - midv(K, c, i);
+}
+
+__global__ __launch_bounds__(kBlock) void ksb_sweep_kernel(KsbDev K)
+{
+    const GridDev& G = K.G;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
+    int x, y, z;
+    cell_of(G, t, x, y, z);
+    const int64_t i = gidx(G, x, y, z);
+    const int64_t sy = G.sy, sz = G.sz;
+    const bool d3 = G.dim == 3;
+    const float v0 = -K.sO * ((float)x - K.half_nx);         // at x = i
+    const float vh = -K.sO * ((float)x + 0.5f - K.half_nx);  // at x = i + 1/2
+    enum { BX = 0, BY, BZ, EX, EY, EZ };
+#define M(c, o) midv(K, c, i + (o))
+    // curl E' at the B locations, curl B at the E locations
+    const float cEx = (M(EZ, sy) - M(EZ, 0)) - (d3 ? M(EY, sz) - M(EY, 0) : 0.f);
+    const float cEy = (d3 ? M(EX, sz) - M(EX, 0) : 0.f) - (M(EZ, 1) - M(EZ, 0));
+    const float cEz = (M(EY, 1) - M(EY, 0)) - (M(EX, sy) - M(EX, 0));
+    const float cBx = (M(BZ, 0) - M(BZ, -sy)) - (d3 ? M(BY, 0) - M(BY, -sz) : 0.f);
+    const float cBy = (d3 ? M(BX, 0) - M(BX, -sz) : 0.f) - (M(BZ, 0) - M(BZ, -1));
+    const float cBz = (M(BY, 0) - M(BY, -1)) - (M(BX, 0) - M(BX, -sy));
+    const float bxa = 0.25f * (M(BX, 0) + M(BX, 1) + M(BX, -sy) + M(BX, 1 - sy));
+    const float dEy_dx = 0.5f * ((M(EY, 1) - M(EY, 0)) + (M(EY, 1 - sy) - M(EY, -sy)));
+    const float dEx_dx = 0.5f * ((M(EX, 0) - M(EX, -1)) + (M(EX, sy) - M(EX, sy - 1)));
+    const float dEz_dz = d3 ? 0.5f * ((M(EZ, 0) - M(EZ, -sz)) + (M(EZ, sy) - M(EZ, sy - sz))) : 0.f;
+    const float dEy_dz = d3 ? 0.5f * ((M(EY, sz) - M(EY, 0)) + (M(EY, sz - sy) - M(EY, -sy))) : 0.f;
+#undef M
+    const float fp = 4.f * 3.14159265358979f;
+    const float rBx = -cEx - v0 * updy(K, BX, i, sy, v0);
+    const float rBy = -cEy - vh * updy(K, BY, i, sy, vh) - K.sO * bxa;
+    const float rBz = -cEz - vh * updy(K, BZ, i, sy, vh);
+    const float rEx = cBx - fp * K.J[0][i] + vh * updy(K, EX, i, sy, -vh) - vh * dEy_dx;
+    const float rEy = cBy - fp * K.J[1][i] - v0 * updy(K, EY, i, sy, v0) - v0 * (dEx_dx + dEz_dz);
+    const float rEz = cBz - fp * K.J[2][i] + v0 * updy(K, EZ, i, sy, -v0) - v0 * dEy_dz;
+    const float dt = K.dt;
+    K.Fo[BX][i] = K.Fn[BX][i] + dt * rBx;
+    K.Fo[BY][i] = K.Fn[BY][i] + dt * rBy;
+    K.Fo[BZ][i] = K.Fn[BZ][i] + dt * rBz;
+    K.Fo[EX][i] = K.Fn[EX][i] + dt * rEx;
+    K.Fo[EY][i] = K.Fn[EY][i] + dt * rEy;
+    K.Fo[EZ][i] = K.Fn[EZ][i] + dt * rEz;
+}
+
+// ------------------------------------------------------------------ utilities
+__global__ __launch_bounds__(kBlock) void zero_kernel(float* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// interior <-> dense copies: dense index x + n0*(y + n1*z)
+__global__ __launch_bounds__(kBlock) void interior_copy_kernel(GridDev G, float* guarded,
+                                                               float* dense, int to_dense)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
+    int x, y, z;
+    cell_of(G, t, x, y, z);
+    const int64_t i = gidx(G, x, y, z);
+    if (to_dense)
+        dense[t] = guarded[i];
+    else
+        guarded[i] = dense[t];
+}
+
+// FP64 block partial sums of squares of up to 6 interior component arrays
+__global__ __launch_bounds__(kBlock) void field_energy_kernel(GridDev G, Comp6 A, double* part)
+{
+    __shared__ double sh[kBlock];
+    const int c = blockIdx.y;
+    double acc = 0.0;
+    const int64_t ncell = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * kBlock) {
+        int x, y, z;
+        cell_of(G, t, x, y, z);
+        const double v = A.p[c][gidx(G, x, y, z)];
+        acc += v * v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[c * gridDim.x + blockIdx.x] = sh[0];
+}
+
+// FP64 block partial sums of (gamma-1), u_x, u_y, u_z over the live particles
+__global__ __launch_bounds__(kBlock) void particle_sums_kernel(const float* ux, const float* uy,
+                                                               const float* uz,
+                                                               const int32_t* n_live,
+                                                               double* part)
+{
+    __shared__ double sh[4][kBlock];
+    double a[4] = {0, 0, 0, 0};
+    const int n = *n_live;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double x = ux[i], y = uy[i], z = uz[i];
+        const double uu = x * x + y * y + z * z;
+        a[0] += uu / (sqrt(1.0 + uu) + 1.0);  // gamma - 1 without cancellation
+        a[1] += x;
+        a[2] += y;
+        a[3] += z;
+    }
+    for (int k = 0; k < 4; k++) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; k++) part[k * gridDim.x + blockIdx.x] = sh[k][0];
+}
+
+// fixed-order final sum of nrow rows of ncol partials (one thread per row)
+__global__ void sum_rows_kernel(const double* part, int nrow, int ncol, double* out)
+{
+    const int r = threadIdx.x;
+    if (r >= nrow) return;
+    double s = 0.0;
+    for (int k = 0; k < ncol; k++) s += part[r * ncol + k];
+    out[r] = s;
+}
+
+// ------------------------------------------------------------------ host launchers
+static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
+                       hipStream_t st)
+{
+    Comp6 A{};
+    for (int c = 0; c < ncomp; c++) A.p[c] = comps[c];
+    const double fl = floor(dys);
+    const int di = (int)fl;
+    const float w = (float)(dys - fl);
+    const int NYg = G.n[1] + 2 * G.g[1], NZg = G.n[2] + 2 * G.g[2];
+    fill_guards_kernel<<<dim3(nblocks((int64_t)2 * G.g[0] * NYg * NZg), ncomp), kBlock, 0, st>>>(
+        G, A, 0, shear, di, w);
+    fill_guards_kernel<<<dim3(nblocks((int64_t)G.n[0] * 2 * G.g[1] * NZg), ncomp), kBlock, 0, st>>>(
+        G, A, 1, shear, di, w);
+    if (G.g[2] > 0)
+        fill_guards_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * 2 * G.g[2]), ncomp), kBlock, 0,
+                             st>>>(G, A, 2, shear, di, w);
+    return hipGetLastError();
+}
+
+// Fold the deposited current.  For the shearing box tmp receives the transported current and
+// the fold writes every interior cell of J.
+hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, int shear,
+                        double sO, double dt, double dys_half, hipStream_t st)
+{
+    Comp3 Jc{{J[0], J[1], J[2]}};
+    const int NXg = G.n[0] + 2 * G.g[0], NYg = G.n[1] + 2 * G.g[1];
+    if (G.g[2] > 0) {
+        const int nl = G.n[2] < 2 * G.g[2] ? G.n[2] : 2 * G.g[2];
+        fold_periodic_kernel<<<dim3(nblocks((int64_t)NXg * NYg * nl), 3), kBlock, 0, st>>>(G, Jc, 2);
+    }
+    {
+        const int nl = G.n[1] < 2 * G.g[1] ? G.n[1] : 2 * G.g[1];
+        fold_periodic_kernel<<<dim3(nblocks((int64_t)NXg * nl * G.n[2]), 3), kBlock, 0, st>>>(G, Jc, 1);
+    }
+    const double fl = floor(dys_half);
+    const int di = (int)fl;
+    const float w = (float)(dys_half - fl);
+    if (shear) {
+        Comp3 Tc{{tmp[0], tmp[1], tmp[2]}};
+        shear_advect_kernel<<<dim3(nblocks((int64_t)NXg * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
+            G, Jc, Tc, (float)(sO * dt / 2.0), 0.5f * G.n[0]);
+        fold_x_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
+            G, Tc, Jc, 1, 1, di, w);
+    } else {
+        const int nl = G.n[0] < 2 * G.g[0] ? G.n[0] : 2 * G.g[0];
+        fold_x_kernel<<<dim3(nblocks((int64_t)nl * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
+            G, Jc, Jc, 0, 0, 0, 0.f);
+    }
+    return hipGetLastError();
+}
+
+hipError_t yee_b(const MaxwellDev& M, hipStream_t st)
+{
+    yee_b_kernel<<<nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kBlock, 0, st>>>(M);
+    return hipGetLastError();
+}
+hipError_t yee_e(const MaxwellDev& M, hipStream_t st)
+{
+    yee_e_kernel<<<nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kBlock, 0, st>>>(M);
+    return hipGetLastError();
+}
+hipError_t ksb_sweep(const KsbDev& K, hipStream_t st)
+{
+    ksb_sweep_kernel<<<nblocks((int64_t)K.G.n[0] * K.G.n[1] * K.G.n[2]), kBlock, 0, st>>>(K);
+    return hipGetLastError();
+}
+hipError_t zero_floats(float* p, int64_t n, hipStream_t st)
+{
+    if (n > 0) zero_kernel<<<nblocks(n), kBlock, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense, hipStream_t st)
+{
+    interior_copy_kernel<<<nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), kBlock, 0, st>>>(G, guarded,
+                                                                                      dense, to_dense);
+    return hipGetLastError();
+}
+hipError_t field_energy(const GridDev& G, float* const* comps, int ncomp, double* part, int nblk,
+                        double* out, hipStream_t st)
+{
+    Comp6 A{};
+    for (int c = 0; c < ncomp; c++) A.p[c] = comps[c];
+    field_energy_kernel<<<dim3(nblk, ncomp), kBlock, 0, st>>>(G, A, part);
+    sum_rows_kernel<<<1, 64, 0, st>>>(part, ncomp, nblk, out);
+    return hipGetLastError();
+}
+hipError_t particle_sums(const float* ux, const float* uy, const float* uz, const int32_t* n_live,
+                         double* part, int nblk, double* out, hipStream_t st)
+{
+    particle_sums_kernel<<<nblk, kBlock, 0, st>>>(ux, uy, uz, n_live, part);
+    sum_rows_kernel<<<1, 64, 0, st>>>(part, 4, nblk, out);
+    return hipGetLastError();
+}
+
+}  // namespace pic

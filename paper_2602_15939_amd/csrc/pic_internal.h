@@ -1,0 +1,205 @@
+// pic_internal.h — device-side layout shared by the HIP kernels and the host driver of
+// the particle hot path (gfx950).  Not part of the public C ABI (include/pic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pic {
+
+constexpr int kGuard = 2;      // guard cells on each side of every grid axis (z: 0 in 2D)
+constexpr int kMaxSpecies = 2;
+constexpr int kBlock = 256;    // threads per workgroup of the particle kernels (4 wave64)
+constexpr int kMjBins = 4096;  // reinjection sampler: bulk inverse-CDF bins
+constexpr int kMjTail = 64;    // reinjection sampler: tail bins in -log2(1-p)
+
+enum Frame { kPlain = 0, kShear = 1, kExpand = 2, kLeaky = 3 };
+
+// Particle cells are packed as i | j << b0 | k << (b0+b1) with b_d = ceil(log2 n_d),
+// so decoding is shifts and masks.  A dead particle has cell -1.
+struct CellCode {
+    int b0, b1;
+    unsigned m0, m1;
+    __host__ __device__ inline void decode(int32_t c, int& i, int& j, int& k) const
+    {
+        unsigned u = (unsigned)c;
+        i = (int)(u & m0);
+        j = (int)((u >> b0) & m1);
+        k = (int)(u >> (b0 + b1));
+    }
+    __host__ __device__ inline int32_t encode(int i, int j, int k) const
+    {
+        return (int32_t)((unsigned)i | ((unsigned)j << b0) | ((unsigned)k << (b0 + b1)));
+    }
+};
+
+// Geometry of the tile decomposition (power-of-two tile edges).
+struct Tiles {
+    int lt[3];    // log2 of the tile edge per axis
+    int nt[3];    // tiles per axis
+    int n_tiles;
+    __host__ __device__ inline int key(int i, int j, int k) const
+    {
+        return (i >> lt[0]) + nt[0] * ((j >> lt[1]) + nt[1] * (k >> lt[2]));
+    }
+};
+
+// One species as seen by a push launch: input arrays (read through perm), output arrays
+// (written in sorted slot order) and the unfused-deposit workspace.
+struct SpeciesDev {
+    const int32_t* cell_in;
+    const float* off_in[3];
+    const float* u_in[3];
+    const uint32_t* id_in;
+    const float* dr_in[3];
+    int32_t* cell_out;
+    float* off_out[3];
+    float* u_out[3];
+    uint32_t* id_out;
+    float* dr_out[3];
+    const int32_t* perm;  // sorted slot -> input index
+    const int32_t* toff;  // tile offsets, n_tiles + 1
+    int32_t* ws_cell;     // unfused deposit: old cell, old offsets, deposit displacement
+    float* ws_off[3];
+    float* ws_disp[3];
+    float qm_hdt;         // (q/m) dt/2
+    float q_dt;           // macro charge / dt
+};
+
+// Everything one push or deposit launch of one box needs, passed by value.
+struct StepDev {
+    int dim, frame;
+    int n[3];
+    CellCode cc;
+    Tiles tl;
+    int sy, sz;           // element strides of the guarded grid arrays (x stride 1)
+    float* E[3];          // pointers to interior (0,0,0) of the guarded arrays
+    float* B[3];
+    float* J[3];
+    float dt;
+    // shearing box
+    float sO;             // s Omega0
+    float om_dt;          // Omega0 dt
+    float alpha1;         // s Omega0 dt/2
+    float half_nx;        // n[0]/2
+    int dys_int;          // Delta y_s(t^{n+1}) = dys_int + dys_frac, dys_frac in [0,1)
+    float dys_frac;
+    // expanding box (Lambda at t^n, L^-1 at t^{n+1/2})
+    float lam1p[3];       // 1 + Lambda_ii
+    float ltil[3];        // (1 + Lambda_ii)/(1 - Lambda_ii)
+    float tfac[3];        // 1/(1 - Lambda_ii)
+    float linv[3];        // 1/l_i(t^{n+1/2})
+    // leaky box
+    int leaky_mode, use_3vec;
+    float l_esc;
+    uint32_t esc_thr;     // floor((dt/t_esc) 2^32)
+    double g2thr;         // gamma_thr^2 - 1
+    uint32_t key0, key1, step_lo, box_id;
+    const float* mj;      // kMjBins + kMjTail values
+    // bookkeeping
+    uint32_t* err;
+    unsigned long long* ctr;  // [0] slow-path particles, [1] escapes
+    int nsp;
+    int track_ids;
+    SpeciesDev sp[kMaxSpecies];
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of the two 32x32->64
+// multiplications with the published multipliers, key bumped by the published Weyl
+// constants between rounds.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        const uint32_t a0 = c[0], a2 = c[2];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, a0), lo0 = 0xD2511F53u * a0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, a2), lo1 = 0xCD9E8D57u * a2;
+        c[0] = hi1 ^ c[1] ^ k0;
+        c[1] = lo1;
+        c[2] = hi0 ^ c[3] ^ k1;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Maps block b of a grid of nblk blocks to a work index so that each of the 8 XCDs (which
+// receive blocks round-robin) processes one contiguous range of tiles and shares its L2
+// for the overlapping tile halos.
+__device__ inline int xcd_contiguous(int b, int nblk)
+{
+    const int x = b & 7, local = b >> 3;
+    const int full = nblk >> 3, rem = nblk & 7;
+    return x * full + (x < rem ? x : rem) + local;
+}
+
+// Geometry of a guarded grid array.
+struct GridDev {
+    int dim;
+    int n[3];
+    int g[3];    // guard width per axis
+    int sy, sz;  // element strides (x stride 1)
+};
+
+// One Yee update: X_i <- fout_i (fin_i X_i +/- dt curl(g Y)_i [- 4 pi dt J_i]).
+struct MaxwellDev {
+    GridDev G;
+    float* E[3];
+    float* B[3];
+    const float* J[3];
+    float dt;
+    float fin[3], fout[3], gf[3];
+};
+
+// One fixed-point sweep of the shearing-box implicit midpoint rule.
+struct KsbDev {
+    GridDev G;
+    const float* Fn[6];  // Bx By Bz Ex Ey Ez at t^n
+    const float* Fk[6];  // current iterate
+    float* Fo[6];        // next iterate
+    const float* J[3];
+    float dt, sO, half_nx;
+};
+
+// Sort workspace of one species.
+struct SortBufs {
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    uint32_t* hist;
+    uint32_t* scratch;
+};
+
+// ---- launchers (gpd.hip, sort.hip, grid.hip, xfer.hip)
+bool tile_shape_supported(int dim, const int t[3]);
+hipError_t launch_gather_push(const StepDev& P, const int t[3], int fuse, hipStream_t st);
+hipError_t launch_deposit(const StepDev& P, const int t[3], hipStream_t st);
+
+size_t scan_scratch_words(int64_t n);
+size_t sort_hist_words(int64_t n);
+hipError_t tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper, CellCode cc,
+                     Tiles tl, SortBufs& sb, int32_t* toff, int32_t* n_live_out, int& which,
+                     hipStream_t st);
+
+hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
+                       hipStream_t st);
+hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, int shear,
+                        double sO, double dt, double dys_half, hipStream_t st);
+hipError_t yee_b(const MaxwellDev& M, hipStream_t st);
+hipError_t yee_e(const MaxwellDev& M, hipStream_t st);
+hipError_t ksb_sweep(const KsbDev& K, hipStream_t st);
+hipError_t zero_floats(float* p, int64_t n, hipStream_t st);
+hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense,
+                         hipStream_t st);
+hipError_t field_energy(const GridDev& G, float* const* comps, int ncomp, double* part, int nblk,
+                        double* out, hipStream_t st);
+hipError_t particle_sums(const float* ux, const float* uy, const float* uz, const int32_t* n_live,
+                         double* part, int nblk, double* out, hipStream_t st);
+
+hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n, const int nn[3],
+                                  CellCode cc, uint32_t* err, hipStream_t st);
+hipError_t cells_packed_to_linear(const int32_t* packed, int32_t* lin, int64_t n, const int nn[3],
+                                  CellCode cc, hipStream_t st);
+hipError_t iota_u32(uint32_t* p, int64_t n, hipStream_t st);
+
+}  // namespace pic

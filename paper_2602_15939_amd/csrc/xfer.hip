@@ -1,0 +1,69 @@
+// xfer.hip — conversions between the boundary particle layout (linear cell index) and the
+// packed cell code used inside the library.
+#include "pic_internal.h"
+
+namespace pic {
+
+__global__ __launch_bounds__(kBlock) void lin_to_packed_kernel(const int32_t* lin, int32_t* packed,
+                                                               int64_t n, int nx, int ny, int nz,
+                                                               CellCode cc, uint32_t* err)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = lin[i];
+    if (c < 0 || (int64_t)c >= (int64_t)nx * ny * nz) {
+        packed[i] = cc.encode(0, 0, 0);
+        atomicOr(err, 8u);
+        return;
+    }
+    const int x = c % nx;
+    const int r = c / nx;
+    packed[i] = cc.encode(x, r % ny, r / ny);
+}
+
+__global__ __launch_bounds__(kBlock) void packed_to_lin_kernel(const int32_t* packed, int32_t* lin,
+                                                               int64_t n, int nx, int ny,
+                                                               CellCode cc)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = packed[i];
+    if (c < 0) {
+        lin[i] = -1;
+        return;
+    }
+    int x, y, z;
+    cc.decode(c, x, y, z);
+    lin[i] = x + nx * (y + ny * z);
+}
+
+__global__ __launch_bounds__(kBlock) void iota_kernel(uint32_t* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n, const int nn[3],
+                                  CellCode cc, uint32_t* err, hipStream_t st)
+{
+    if (n > 0)
+        lin_to_packed_kernel<<<nblk(n), kBlock, 0, st>>>(lin, packed, n, nn[0], nn[1], nn[2], cc, err);
+    return hipGetLastError();
+}
+
+hipError_t cells_packed_to_linear(const int32_t* packed, int32_t* lin, int64_t n, const int nn[3],
+                                  CellCode cc, hipStream_t st)
+{
+    if (n > 0) packed_to_lin_kernel<<<nblk(n), kBlock, 0, st>>>(packed, lin, n, nn[0], nn[1], cc);
+    return hipGetLastError();
+}
+
+hipError_t iota_u32(uint32_t* p, int64_t n, hipStream_t st)
+{
+    if (n > 0) iota_kernel<<<nblk(n), kBlock, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -232,6 +232,16 @@ StepDev make_step(pic_box* b)
     P.step_lo = (uint32_t)b->step;
     P.box_id = b->d.box_id;
     P.mj = b->mj;
+    // Largest single deposit contribution: |q|/dt * |DS| * P with |DS| < 1/2 (CFL), or the 2D
+    // J_z term |q v_z W| <= |q|; it maps to 2^30 fixed-point units of the LDS tile sum.
+    {
+        double qmax = 0.0;
+        for (int s = 0; s < b->nsp; s++) qmax = std::fmax(qmax, std::fabs(b->sp[s].q));
+        const double bound = std::fmax(0.5 * qmax / dt, qmax);
+        const double unit = bound > 0 ? bound / 1073741824.0 : 1.0;
+        P.junit = (float)unit;
+        P.jscale = (float)(1.0 / unit);
+    }
     P.err = b->err;
     P.ctr = b->ctr;
     P.nsp = b->nsp;

@@ -25,6 +25,11 @@ __device__ inline f3 cross(f3 a, f3 b)
     return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
+// Hardware reciprocal and square root (v_rcp_f32, v_sqrt_f32: about 1 ulp), used instead of
+// the correctly rounded division and square-root sequences.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ------------------------------------------------------------------ interpolation
 // Linear (CIC) interpolation of one component on its own staggered lattice (base index and
 // weights per axis), from an array with element strides (1, sy, sz).
@@ -87,7 +92,7 @@ __device__ inline f3 push_boris(f3 u, f3 E, f3 B, float qm_hdt)
     const f3 um = u + eps;
     const float ig = rsqrtf(1.f + dot(um, um));
     const f3 t = (qm_hdt * ig) * B;
-    const float d = 2.f / (1.f + dot(t, t));
+    const float d = 2.f * rcp(1.f + dot(t, t));
     const f3 c1 = cross(um, t);
     const f3 c2 = cross(c1, t);
     return um + d * (c1 + c2) + eps;
@@ -106,23 +111,23 @@ __device__ inline f3 push_shear(f3 u, f3 E, f3 B, float qm_hdt, float alpha1, fl
     const float ue = dot(um, eps);
     const float A = uu + 2.f * alpha1 * um.x * um.y;
     const float K = 2.f * alpha2 * ue * um.y;
-    const float g0 = sqrtf(1.f + uu);
-    float g = g0 + (alpha1 * um.x * um.y * g0 + alpha2 * ue * um.y) / (g0 * g0);
-    g = sqrtf(1.f + A + K / g);
-    g = sqrtf(1.f + A + K / g);
-    const float ig = 1.f / g;
+    const float g0 = fsqrt(1.f + uu);
+    float g = g0 + (alpha1 * um.x * um.y * g0 + alpha2 * ue * um.y) * rcp(1.f + uu);
+    g = fsqrt(1.f + A + K * rcp(g));
+    g = fsqrt(1.f + A + K * rcp(g));
+    const float ig = rcp(g);
     f3 t = (qm_hdt * ig) * B;
     t.z += om_dt;
     const f3 et = ig * eps;
     const f3 s2 = mk(alpha1 + alpha2 * et.x, alpha2 * et.y, alpha2 * et.z);
-    const float d = 1.f / (1.f + dot(t, t));
+    const float d = rcp(1.f + dot(t, t));
     const f3 c1 = cross(um, t);
     const f3 c2 = cross(c1, t);
     const f3 Bu = um + (2.f * d) * (c1 + c2);
     const f3 Rey = mk(d * (t.z + t.x * t.y), 1.f - d * (t.x * t.x + t.z * t.z), d * (t.y * t.z - t.x));
     const float gg = dot(s2, Rey);
     const f3 w = Bu + dot(s2, um) * Rey;
-    const f3 up = w + (dot(s2, w) / (1.f - gg)) * Rey;
+    const f3 up = w + (dot(s2, w) * rcp(1.f - gg)) * Rey;
     return up + eps;
 }
 
@@ -139,7 +144,7 @@ __device__ inline f3 push_expand(f3 u, f3 E, f3 B, float qm_hdt, const float lam
     const float s = qm_hdt * ig;
     const f3 t = mk(s * tfac[0] * B.x, s * tfac[1] * B.y, s * tfac[2] * B.z);
     const f3 w = mk((1.f + ltil[0]) * um.x, (1.f + ltil[1]) * um.y, (1.f + ltil[2]) * um.z);
-    const float d = 1.f / (1.f + dot(t, t));
+    const float d = rcp(1.f + dot(t, t));
     const f3 c1 = cross(w, t);
     const f3 c2 = cross(c1, t);
     const f3 up = mk(ltil[0] * um.x, ltil[1] * um.y, ltil[2] * um.z) + d * (c1 + c2);
@@ -249,13 +254,18 @@ __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, con
 }
 
 // LDS accumulator: (JX, JY, JZ) region per component, origin at the tile origin minus one.
+// The tile current is summed in 64-bit fixed point: a contribution arrives pre-scaled so that
+// the largest possible single contribution is 2^30 units, is truncated to int32 and added with
+// ds_add_u64 (integer LDS atomics cost a few cycles per wave instruction, while FP32 LDS
+// atomics are serialised per lane).  Integer sums are exact and independent of the order.
 template <int JX, int JY, int JZ>
 struct LdsAcc {
-    float* J;
+    unsigned long long* J;
     int base;  // index of (nearest node - 1) per axis in the region
     __device__ inline void add(int c, int x, int y, int z, float v)
     {
-        atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], v);
+        const long long q = (long long)__float2int_rz(v);
+        atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], (unsigned long long)q);
     }
 };
 
@@ -277,7 +287,7 @@ struct Geo {
     static constexpr int FS = FX * FY * FZ;
     static constexpr int JX = TX + 3, JY = TY + 3, JZ = DIM == 3 ? TZ + 3 : 1;
     static constexpr int JS = JX * JY * JZ;
-    static constexpr int LDS_FLOATS = 6 * FS + 3 * JS;
+    static constexpr int LDS_BYTES = 6 * FS * 4 + 3 * JS * 8;
 };
 
 template <int DIM>
@@ -302,13 +312,22 @@ __device__ inline void tile_origin(const StepDev& P, int tile, int t0[3], int ex
 
 __device__ inline void latch(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
 
-template <int DIM, int TX, int TY, int TZ, int FRAME>
-__global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
+// int64 fixed-point tile sum -> FP32 current
+__device__ inline float fixed_to_float(unsigned long long a, float unit)
+{
+    const long long v = (long long)a;
+    const int hi = (int)(v >> 32);
+    const unsigned lo = (unsigned)v;
+    return (float)(((double)hi * 4294967296.0 + (double)lo) * (double)unit);
+}
+
+template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
+__global__ __launch_bounds__(NT) void gpd_kernel(StepDev P, int fuse)
 {
     using G = Geo<DIM, TX, TY, TZ>;
-    __shared__ float lds[G::LDS_FLOATS];
-    float* const F = lds;              // 6 field components
-    float* const Jl = lds + 6 * G::FS; // 3 current components
+    __shared__ __attribute__((aligned(16))) unsigned char lds[G::LDS_BYTES];
+    float* const F = reinterpret_cast<float*>(lds);                                   // E, B
+    unsigned long long* const Jl = reinterpret_cast<unsigned long long*>(lds + 6 * G::FS * 4);  // J
 
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
     int t0[3], ext[3];
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
     const int tid = threadIdx.x;
 
     // stage E, B of the tile and one guard cell per side
-    for (int e = tid; e < 6 * G::FS; e += kBlock) {
+    for (int e = tid; e < 6 * G::FS; e += NT) {
         const int comp = e / G::FS;
         const int r = e - comp * G::FS;
         const int lx = r % G::FX, ly = (r / G::FX) % G::FY, lz = r / (G::FX * G::FY);
@@ -330,14 +349,14 @@ __global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
         F[e] = v;
     }
     if (fuse)
-        for (int e = tid; e < 3 * G::JS; e += kBlock) Jl[e] = 0.f;
+        for (int e = tid; e < 3 * G::JS; e += NT) Jl[e] = 0ull;
     __syncthreads();
 
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     for (int s = 0; s < P.nsp; s++) {
         const SpeciesDev& S = P.sp[s];
         const int beg = S.toff[tile], end = S.toff[tile + 1];
-        for (int slot = beg + tid; slot < end; slot += kBlock) {
+        for (int slot = beg + tid; slot < end; slot += NT) {
             const int src = S.perm[slot];
             int cx, cy, cz;
             P.cc.decode(S.cell_in[src], cx, cy, cz);
@@ -388,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
                 if (in_tile) {
                     LdsAcc<G::JX, G::JY, G::JZ> acc{
                         Jl, (lx + hx - 1) + G::JX * ((ly + hy - 1) + G::JY * (DIM == 3 ? lz + hz - 1 : 0))};
-                    esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
+                    esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt * P.jscale, D.z);
                 } else {
                     GlobalAcc acc{P.J, (int64_t)(cx + hx - 1) + (int64_t)P.sy * (cy + hy - 1) +
                                            (DIM == 3 ? (int64_t)P.sz * (cz + hz - 1) : 0),
@@ -500,9 +519,10 @@ __global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
     if (!fuse) return;
     __syncthreads();
     // flush the tile current (interior + deposit halo) with float atomics
-    for (int e = tid; e < 3 * G::JS; e += kBlock) {
-        const float v = Jl[e];
-        if (v == 0.f) continue;
+    for (int e = tid; e < 3 * G::JS; e += NT) {
+        const unsigned long long a = Jl[e];
+        if (a == 0ull) continue;
+        const float v = fixed_to_float(a, P.junit);
         const int comp = e / G::JS;
         const int r = e - comp * G::JS;
         const int lx = r % G::JX, ly = (r / G::JX) % G::JY, lz = r / (G::JX * G::JY);
@@ -516,21 +536,21 @@ __global__ __launch_bounds__(kBlock) void gpd_kernel(StepDev P, int fuse)
 
 // Unfused deposit: the same Esirkepov tile accumulation from the positions and deposit
 // displacements saved by an unfused push (in sorted slot order).
-template <int DIM, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void deposit_kernel(StepDev P)
+template <int DIM, int TX, int TY, int TZ, int NT>
+__global__ __launch_bounds__(NT) void deposit_kernel(StepDev P)
 {
     using G = Geo<DIM, TX, TY, TZ>;
-    __shared__ float Jl[3 * G::JS];
+    __shared__ unsigned long long Jl[3 * G::JS];
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
     int t0[3], ext[3];
     tile_origin<DIM>(P, tile, t0, ext);
     const int tid = threadIdx.x;
-    for (int e = tid; e < 3 * G::JS; e += kBlock) Jl[e] = 0.f;
+    for (int e = tid; e < 3 * G::JS; e += NT) Jl[e] = 0ull;
     __syncthreads();
     for (int s = 0; s < P.nsp; s++) {
         const SpeciesDev& S = P.sp[s];
         const int beg = S.toff[tile], end = S.toff[tile + 1];
-        for (int slot = beg + tid; slot < end; slot += kBlock) {
+        for (int slot = beg + tid; slot < end; slot += NT) {
             int cx, cy, cz;
             P.cc.decode(S.ws_cell[slot], cx, cy, cz);
             const float ox = S.ws_off[0][slot], oy = S.ws_off[1][slot];
@@ -547,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(StepDev P)
             if (in_tile) {
                 LdsAcc<G::JX, G::JY, G::JZ> acc{
                     Jl, (lx + hx - 1) + G::JX * ((ly + hy - 1) + G::JY * (DIM == 3 ? lz + hz - 1 : 0))};
-                esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
+                esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt * P.jscale, D.z);
             } else {
                 GlobalAcc acc{P.J, (int64_t)(cx + hx - 1) + (int64_t)P.sy * (cy + hy - 1) +
                                        (DIM == 3 ? (int64_t)P.sz * (cz + hz - 1) : 0),
@@ -557,9 +577,10 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(StepDev P)
         }
     }
     __syncthreads();
-    for (int e = tid; e < 3 * G::JS; e += kBlock) {
-        const float v = Jl[e];
-        if (v == 0.f) continue;
+    for (int e = tid; e < 3 * G::JS; e += NT) {
+        const unsigned long long a = Jl[e];
+        if (a == 0ull) continue;
+        const float v = fixed_to_float(a, P.junit);
         const int comp = e / G::JS;
         const int r = e - comp * G::JS;
         const int lx = r % G::JX, ly = (r / G::JX) % G::JY, lz = r / (G::JX * G::JY);
@@ -572,22 +593,28 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(StepDev P)
 }
 
 // ------------------------------------------------------------------ launchers
+// threads per workgroup: 3D tiles hold a 56 KB LDS footprint (2 workgroups per CU), so they
+// use 8 waves per workgroup to keep 16 waves per CU
+template <int DIM>
+constexpr int threads_for() { return DIM == 3 ? 512 : 256; }
+
 template <int DIM, int TX, int TY, int TZ>
 static hipError_t launch_shape(const StepDev& P, int fuse, hipStream_t st)
 {
-    const dim3 grid(P.tl.n_tiles), block(kBlock);
+    constexpr int NT = threads_for<DIM>();
+    const dim3 grid(P.tl.n_tiles), block(NT);
     switch (P.frame) {
     case kShear:
-        gpd_kernel<DIM, TX, TY, TZ, kShear><<<grid, block, 0, st>>>(P, fuse);
+        gpd_kernel<DIM, TX, TY, TZ, kShear, NT><<<grid, block, 0, st>>>(P, fuse);
         break;
     case kExpand:
-        gpd_kernel<DIM, TX, TY, TZ, kExpand><<<grid, block, 0, st>>>(P, fuse);
+        gpd_kernel<DIM, TX, TY, TZ, kExpand, NT><<<grid, block, 0, st>>>(P, fuse);
         break;
     case kLeaky:
-        gpd_kernel<DIM, TX, TY, TZ, kLeaky><<<grid, block, 0, st>>>(P, fuse);
+        gpd_kernel<DIM, TX, TY, TZ, kLeaky, NT><<<grid, block, 0, st>>>(P, fuse);
         break;
     default:
-        gpd_kernel<DIM, TX, TY, TZ, kPlain><<<grid, block, 0, st>>>(P, fuse);
+        gpd_kernel<DIM, TX, TY, TZ, kPlain, NT><<<grid, block, 0, st>>>(P, fuse);
         break;
     }
     return hipGetLastError();
@@ -596,7 +623,8 @@ static hipError_t launch_shape(const StepDev& P, int fuse, hipStream_t st)
 template <int DIM, int TX, int TY, int TZ>
 static hipError_t launch_dep_shape(const StepDev& P, hipStream_t st)
 {
-    deposit_kernel<DIM, TX, TY, TZ><<<dim3(P.tl.n_tiles), dim3(kBlock), 0, st>>>(P);
+    constexpr int NT = threads_for<DIM>();
+    deposit_kernel<DIM, TX, TY, TZ, NT><<<dim3(P.tl.n_tiles), dim3(NT), 0, st>>>(P);
     return hipGetLastError();
 }
 

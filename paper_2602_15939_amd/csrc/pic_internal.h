@@ -97,6 +97,8 @@ struct StepDev {
     double g2thr;         // gamma_thr^2 - 1
     uint32_t key0, key1, step_lo, box_id;
     const float* mj;      // kMjBins + kMjTail values
+    // fixed-point tile current: contribution * jscale -> integer units, units * junit -> J
+    float jscale, junit;
     // bookkeeping
     uint32_t* err;
     unsigned long long* ctr;  // [0] slow-path particles, [1] escapes

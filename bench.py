@@ -24,6 +24,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+COPY_CAL_BYTES = 1 << 30  # plain device copy used to calibrate the FETCH/WRITE counters
+GPD_SOURCES = ("paper_2602_15939_amd/csrc/gpd.hip", "paper_2602_15939_amd/csrc/pic_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in GPD_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3 counter record,
+    only if it was taken on the current kernel source and workload; else None."""
+    path = os.path.join(ROOT, "profiles", "gpd_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def workload_shear3d(n=256, ppc=8):
@@ -111,6 +137,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=20260216)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: every box of this build lives on a single MI355X; "
@@ -149,11 +177,19 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     gpd_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    if args.copy_calibration:
+        src = torch.empty(COPY_CAL_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     info = box.info()
     assert info.errors & ~L.DERR_ORDER == 0, f"device error bits {info.errors}"
     value = npart * args.steps / el
     nbytes = algorithmic_bytes(w, npart)
     achieved = nbytes / (gpd_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w["name"])
     out = {
         "metric": "particle-steps/s (gather+push+deposit) & HBM %peak",
         "value": value,
@@ -170,9 +206,11 @@ def main():
         "config": {"workload": w["name"], "particles": npart, "frame": "shearing box",
                    "theta": w["theta"], "sigma": 0.05, "q": 1.5, "omega0_over_wc": 0.05,
                    "dt": w["dt"], "maxwell_iters": w["maxwell_iters"],
-                   "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": npart / (gpd_ms * 1e-3)},
+                   "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": npart / (gpd_ms * 1e-3),
+                   "gpd_algorithmic_bytes": nbytes, "slow_path_particles": int(info.n_slow),
+                   "kernel_source_hash": kernel_source_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
     box.close()
     if not args.no_cpu_baseline:

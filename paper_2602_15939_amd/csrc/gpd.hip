@@ -264,7 +264,7 @@ struct LdsAcc {
     int base;  // index of (nearest node - 1) per axis in the region
     __device__ inline void add(int c, int x, int y, int z, float v)
     {
-        const long long q = (long long)__float2int_rz(v);
+        const long long q = (long long)(int)v;  // v_cvt_i32_f32: truncates, saturates
         atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], (unsigned long long)q);
     }
 };

@@ -70,11 +70,16 @@ def uniform_positions(n_cells, count: int, gen: torch.Generator, device):
 
 
 def pair_plasma(n_cells, ppc_per_species: int, theta: float, seed: int, device="cpu"):
-    """Two species (electron first) sharing positions, independent momenta."""
+    """Two species (electron first) sharing positions, independent momenta.  Positions are
+    uniform random; the particles are stored in order of their cell (as a loader that fills the
+    grid cell by cell would lay them out), which only fixes the storage order."""
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
     count = ppc_per_species * int(np.prod(n_cells))
     cell, off = uniform_positions(n_cells, count, gen, device)
+    order = torch.argsort(cell, stable=True)
+    cell, off = cell[order].contiguous(), off[:, order].contiguous()
+    del order
     u_e = mj_momenta(count, theta, gen, device)
     u_p = mj_momenta(count, theta, gen, device)
     return [dict(cell=cell, off=off, u=u_e), dict(cell=cell.clone(), off=off.clone(), u=u_p)]

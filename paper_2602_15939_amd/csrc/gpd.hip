@@ -3,7 +3,7 @@
 // charge-conserving (Esirkepov) current deposit, fused in one kernel per tile.
 //
 // One workgroup owns one tile: it stages E and B of the tile plus one guard cell per side in
-// LDS, accumulates the tile's current (plus the deposit halo) in LDS with ds_add_f32, and
+// LDS, accumulates the tile's current (plus the deposit halo) in LDS as 64-bit fixed point, and
 // flushes it once to HBM with float atomics (only the halo overlaps a neighbour tile).
 // Particles are read through the sort permutation and written in sorted slot order, so the
 // tile sort's scatter is fused into this pass.  A particle found outside its tile (only
@@ -196,13 +196,29 @@ __device__ inline Shape3 shape3(float xi0, float xi1)
 //   J_x on the two edges around the nearest node: -q/dt DS_x[-1] P and +q/dt DS_x[+1] P,
 //   P = S0_y (S0_z + DS_z/2) + DS_y (S0_z/2 + DS_z/3) (cyclic for y and z);
 //   2D: P = S0_y + DS_y/2, and J_z = q dz/dt (S0_x (S0_y + DS_y/2) + DS_x (S0_y/2 + DS_y/3)).
-// Acc::add(c, x, y, z, v) accumulates v into component c at (edge/node) index (x, y, z)
-// relative to the nearest node minus one.
+// Acc::add(c, x, y, z, v, on) accumulates v into component c at (edge/node) index (x, y, z)
+// relative to the nearest node minus one.  `on` is false only where v is exactly zero: an outer
+// node that neither the old nor the new shape touches, or an edge whose DS factor is zero.  A
+// particle that stays on one side of its nearest node in every axis has 12 (3D) / 10 (2D)
+// non-zero terms out of 54 / 21, and skipping the rest leaves the integer sums unchanged.
+struct Use3 {
+    bool n0, n2;  // outer nodes touched by the old or the new shape
+    bool e0, e2;  // DS of the outer nodes non-zero (the two edges carry current)
+};
+__device__ inline Use3 use3(const Shape3& S)
+{
+    return Use3{S.s0[0] != 0.f || S.ds[0] != 0.f, S.s0[2] != 0.f || S.ds[2] != 0.f,
+                S.ds[0] != 0.f, S.ds[2] != 0.f};
+}
+__device__ inline bool used(const Use3& U, int b) { return b == 0 ? U.n0 : (b == 2 ? U.n2 : true); }
+
 template <int DIM, class Acc>
 __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, const Shape3& Z,
                                  float q_dt, float dz)
 {
+    const Use3 UX = use3(X), UY = use3(Y);
     if (DIM == 3) {
+        const Use3 UZ = use3(Z);
         float z1[3], z2[3], y1[3], y2[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
@@ -218,15 +234,18 @@ __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, con
         for (int b = 0; b < 3; b++)
 #pragma unroll
             for (int c = 0; c < 3; c++) {
+                const bool yz = used(UY, b) && used(UZ, c);
                 const float Pyz = Y.s0[b] * z1[c] + Y.ds[b] * z2[c];
-                acc.add(0, 0, b, c, xl * Pyz);
-                acc.add(0, 1, b, c, xh * Pyz);
+                acc.add(0, 0, b, c, xl * Pyz, UX.e0 && yz);
+                acc.add(0, 1, b, c, xh * Pyz, UX.e2 && yz);
+                const bool xz = used(UX, b) && used(UZ, c);
                 const float Pxz = X.s0[b] * z1[c] + X.ds[b] * z2[c];
-                acc.add(1, b, 0, c, yl * Pxz);
-                acc.add(1, b, 1, c, yh * Pxz);
+                acc.add(1, b, 0, c, yl * Pxz, UY.e0 && xz);
+                acc.add(1, b, 1, c, yh * Pxz, UY.e2 && xz);
+                const bool xy = used(UX, b) && used(UY, c);
                 const float Pxy = X.s0[b] * y1[c] + X.ds[b] * y2[c];
-                acc.add(2, b, c, 0, zl * Pxy);
-                acc.add(2, b, c, 1, zh * Pxy);
+                acc.add(2, b, c, 0, zl * Pxy, UZ.e0 && xy);
+                acc.add(2, b, c, 1, zh * Pxy, UZ.e2 && xy);
             }
     } else {
         const float xl = -q_dt * X.ds[0], xh = q_dt * X.ds[2];
@@ -235,11 +254,11 @@ __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, con
 #pragma unroll
         for (int b = 0; b < 3; b++) {
             const float Py = Y.s0[b] + 0.5f * Y.ds[b];
-            acc.add(0, 0, b, 0, xl * Py);
-            acc.add(0, 1, b, 0, xh * Py);
+            acc.add(0, 0, b, 0, xl * Py, UX.e0 && used(UY, b));
+            acc.add(0, 1, b, 0, xh * Py, UX.e2 && used(UY, b));
             const float Px = X.s0[b] + 0.5f * X.ds[b];
-            acc.add(1, b, 0, 0, yl * Px);
-            acc.add(1, b, 1, 0, yh * Px);
+            acc.add(1, b, 0, 0, yl * Px, UY.e0 && used(UX, b));
+            acc.add(1, b, 1, 0, yh * Px, UY.e2 && used(UX, b));
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -247,7 +266,7 @@ __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, con
             for (int b = 0; b < 3; b++) {
                 const float W = X.s0[a] * (Y.s0[b] + 0.5f * Y.ds[b]) +
                                 X.ds[a] * (0.5f * Y.s0[b] + (1.f / 3.f) * Y.ds[b]);
-                acc.add(2, a, b, 0, jz * W);
+                acc.add(2, a, b, 0, jz * W, used(UX, a) && used(UY, b));
             }
         }
     }
@@ -262,10 +281,10 @@ template <int JX, int JY, int JZ>
 struct LdsAcc {
     unsigned long long* J;
     int base;  // index of (nearest node - 1) per axis in the region
-    __device__ inline void add(int c, int x, int y, int z, float v)
+    __device__ inline void add(int c, int x, int y, int z, float v, bool on)
     {
         const long long q = (long long)(int)v;  // v_cvt_i32_f32: truncates, saturates
-        atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], (unsigned long long)q);
+        if (on) atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], (unsigned long long)q);
     }
 };
 
@@ -274,7 +293,7 @@ struct GlobalAcc {
     float* const* J;
     int64_t base;
     int sy, sz;
-    __device__ inline void add(int c, int x, int y, int z, float v)
+    __device__ inline void add(int c, int x, int y, int z, float v, bool)
     {
         if (v != 0.f) unsafeAtomicAdd(&J[c][base + x + (int64_t)sy * y + (int64_t)sz * z], v);
     }

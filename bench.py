@@ -181,7 +181,7 @@ def main():
         src = torch.empty(COPY_CAL_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        L.pic_device_copy(dst.data_ptr(), src.data_ptr(), COPY_CAL_BYTES, st.cuda_stream)
         torch.cuda.synchronize()
         del src, dst
     info = box.info()

@@ -180,6 +180,13 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
 /* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */
 int32_t pic_box_get(pic_box* box, pic_box_info* info);
 
+/* Measurement utility, not part of the method: a plain streaming device-to-device copy of
+   nbytes (a multiple of 16; both pointers 16-byte aligned device memory owned by the caller)
+   on `stream` (a hipStream_t, NULL for the default stream), asynchronous.  Its known traffic
+   (nbytes read, nbytes written) calibrates hardware memory counters.  PIC_EINVAL for a bad
+   size or alignment. */
+int32_t pic_device_copy(void* dst, const void* src, int64_t nbytes, void* stream);
+
 /* Static description of a pic_status. */
 const char* pic_status_str(int32_t status);
 

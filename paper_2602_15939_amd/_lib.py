@@ -79,6 +79,7 @@ def lib():
             "pic_step": ([boxes, i32, u32], i32),
             "pic_box_get": ([vp, C.POINTER(pic_box_info)], i32),
             "pic_status_str": ([i32], C.c_char_p),
+            "pic_device_copy": ([vp, vp, i64, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -97,6 +98,10 @@ def check(rc: int, what: str = "") -> None:
 def box_array(handles):
     arr = (C.c_void_p * len(handles))(*handles)
     return C.cast(arr, C.POINTER(C.c_void_p)), arr
+
+
+def pic_device_copy(dst_ptr, src_ptr, nbytes, stream_ptr=None):
+    check(lib().pic_device_copy(dst_ptr, src_ptr, nbytes, stream_ptr), "pic_device_copy")
 
 
 def pic_box_create(desc: pic_box_desc) -> int:

@@ -451,6 +451,15 @@ const char* pic_status_str(int32_t s)
     }
 }
 
+int32_t pic_device_copy(void* dst, const void* src, int64_t nbytes, void* stream)
+{
+    if (nbytes < 0 || (nbytes > 0 && (!dst || !src)) || (nbytes & 15) ||
+        ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return PIC_EINVAL;
+    return pic::device_copy16(dst, src, nbytes / 16, (hipStream_t)stream) == hipSuccess ? PIC_OK
+                                                                                        : PIC_EDEVICE;
+}
+
 int32_t pic_box_destroy(pic_box* b)
 {
     if (!b) return PIC_OK;

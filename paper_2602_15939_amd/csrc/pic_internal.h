@@ -202,6 +202,7 @@ hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n
                                   CellCode cc, uint32_t* err, hipStream_t st);
 hipError_t cells_packed_to_linear(const int32_t* packed, int32_t* lin, int64_t n, const int nn[3],
                                   CellCode cc, hipStream_t st);
+hipError_t device_copy16(void* dst, const void* src, int64_t nwords, hipStream_t st);
 hipError_t iota_u32(uint32_t* p, int64_t n, hipStream_t st);
 
 }  // namespace pic

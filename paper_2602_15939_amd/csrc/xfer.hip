@@ -43,6 +43,15 @@ __global__ __launch_bounds__(kBlock) void iota_kernel(uint32_t* p, int64_t n)
     if (i < n) p[i] = (uint32_t)i;
 }
 
+// Plain streaming copy in 16-byte words (the reference kernel of known traffic used to scale
+// hardware memory counters).
+__global__ __launch_bounds__(kBlock) void copy_kernel(uint4* __restrict__ dst,
+                                                      const uint4* __restrict__ src, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n, const int nn[3],
@@ -57,6 +66,17 @@ hipError_t cells_packed_to_linear(const int32_t* packed, int32_t* lin, int64_t n
                                   CellCode cc, hipStream_t st)
 {
     if (n > 0) packed_to_lin_kernel<<<nblk(n), kBlock, 0, st>>>(packed, lin, n, nn[0], nn[1], cc);
+    return hipGetLastError();
+}
+
+hipError_t device_copy16(void* dst, const void* src, int64_t nwords, hipStream_t st)
+{
+    if (nwords > 0) {
+        const int64_t want = (nwords + kBlock - 1) / kBlock;
+        const unsigned grid = (unsigned)(want < 256 * 64 ? want : 256 * 64);
+        copy_kernel<<<grid, kBlock, 0, st>>>(static_cast<uint4*>(dst), static_cast<const uint4*>(src),
+                                             nwords);
+    }
     return hipGetLastError();
 }
 

@@ -2,9 +2,11 @@
 
   python -m paper_2602_15939_amd.profile_summary trace <results.db>
       per-kernel call count and average / total duration (kernel trace)
-  python -m paper_2602_15939_amd.profile_summary traffic <fetch.db> <write.db> <copy_bytes>
-      FETCH_SIZE / WRITE_SIZE per dispatch of the fused push kernel, scaled by what the same
-      counters read for the plain device copy of copy_bytes in the same run
+  python -m paper_2602_15939_amd.profile_summary traffic <fetch.db> <write.db> <copy_bytes> \
+        [skip [record.json workload source_hash]]
+      FETCH_SIZE / WRITE_SIZE per dispatch of the fused push kernel (after the first `skip`
+      dispatches), scaled by what the same counters read for the plain device copy of
+      copy_bytes in the same run; optionally written as the JSON record bench.py reads
 """
 from __future__ import annotations
 
@@ -53,9 +55,10 @@ def main(argv):
     elif argv[0] == "traffic":
         fetch, write = counter_per_dispatch(argv[1], "FETCH_SIZE"), counter_per_dispatch(argv[2], "WRITE_SIZE")
         copy_bytes = float(argv[3])
-        cf, _ = mean_for([r for r in fetch if "copy" in r[0].lower() or "elementwise" in r[0].lower()], "")
-        cw, _ = mean_for([r for r in write if "copy" in r[0].lower() or "elementwise" in r[0].lower()], "")
         skip = int(argv[4]) if len(argv) > 4 else 0
+        # the calibration copy: the library's plain streaming copy kernel
+        cf = max(v for k, v in fetch if "copy_kernel" in k)
+        cw = max(v for k, v in write if "copy_kernel" in k)
         gfl = [r for r in fetch if "gpd_kernel" in r[0]][skip:]
         gwl = [r for r in write if "gpd_kernel" in r[0]][skip:]
         gf, nf = mean_for(gfl, "gpd_kernel")
@@ -63,10 +66,19 @@ def main(argv):
         print("gpd_kernel FETCH_SIZE per dispatch:", " ".join(f"{v:.4e}" for _, v in fetch if "gpd" in _))
         print("gpd_kernel WRITE_SIZE per dispatch:", " ".join(f"{v:.4e}" for _, v in write if "gpd" in _))
         sf, sw = copy_bytes / cf, copy_bytes / cw  # bytes per counter unit (KiB nominal)
-        print(f"copy kernel: FETCH_SIZE {cf:.4e} WRITE_SIZE {cw:.4e} for {copy_bytes:.4e} B each way")
+        print(f"calibration copy: FETCH_SIZE {cf:.4e} WRITE_SIZE {cw:.4e} for {copy_bytes:.4e} B each way")
         print(f"scale: fetch {sf:.2f} B/unit, write {sw:.2f} B/unit")
-        print(f"gpd_kernel ({nf} / {nw} dispatches): FETCH_SIZE {gf:.4e} -> {gf * sf:.4e} B, "
-              f"WRITE_SIZE {gw:.4e} -> {gw * sw:.4e} B, total {gf * sf + gw * sw:.4e} B per launch")
+        print(f"gpd_kernel ({nf} / {nw} dispatches after skipping {skip}): FETCH_SIZE {gf:.4e} -> "
+              f"{gf * sf:.4e} B, WRITE_SIZE {gw:.4e} -> {gw * sw:.4e} B, "
+              f"total {gf * sf + gw * sw:.4e} B per launch")
+        if len(argv) > 6:  # record for bench.py: <record.json> <workload> <source hash>
+            import json
+            rec = dict(workload=argv[6], source_hash=argv[7], fetch_bytes_per_launch=gf * sf,
+                       write_bytes_per_launch=gw * sw, traffic_bytes_per_launch=gf * sf + gw * sw,
+                       copy_scale_fetch=sf, copy_scale_write=sw, dispatches=nf)
+            with open(argv[5], "w") as fh:
+                json.dump(rec, fh, indent=1)
+            print("wrote", argv[5])
     else:
         raise SystemExit(__doc__)
 

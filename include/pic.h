@@ -105,6 +105,9 @@ typedef struct pic_box_info {
     double field_energy_E[3], field_energy_B[3];
     double kinetic_energy;
     double momentum[3];
+    int64_t n_sort_migrations; /* sorts done by the neighbour-migration counting sort */
+    int64_t n_sort_fallbacks;  /* of those, sorts that found a particle beyond the
+                                  neighbouring tiles and fell back to the radix sort */
 } pic_box_info;
 
 /* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard
@@ -144,7 +147,11 @@ int32_t pic_get_sort(pic_box* box, int32_t species, int32_t* perm_dev, int32_t* 
 
 /* Tile counting sort (stable): key = tile of the particle's cell, dead particles go to a
    dead bin and are dropped.  Produces the permutation used by the next pic_gather_push and
-   the per-tile offsets. */
+   the per-tile offsets.  After a push the particles are still grouped by the tiles of the
+   previous sort and each moved less than a cell, so (on tile grids with whole tiles and one
+   or at least three tiles per axis) the sort only counts moves to the neighbouring tiles;
+   a particle found farther away sends that sort to the general radix sort on the device.
+   Both give the same permutation.  PIC_ESTATE while an unfused push awaits pic_deposit. */
 int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t flags);
 
 /* Field gather at x^n, push u^{n-1/2} -> u^{n+1/2} with the frame's pusher (Boris;

@@ -42,6 +42,7 @@ class pic_box_info(C.Structure):
         ("n_escaped", C.c_int64), ("field_energy_E", C.c_double * 3),
         ("field_energy_B", C.c_double * 3), ("kinetic_energy", C.c_double),
         ("momentum", C.c_double * 3),
+        ("n_sort_migrations", C.c_int64), ("n_sort_fallbacks", C.c_int64),
     ]
 
 

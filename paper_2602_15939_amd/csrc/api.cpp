@@ -29,7 +29,9 @@ struct Species {
     float* dr[2][3] = {};
     SortBufs sb{};
     int which = 0;          // sort buffer holding the sorted (key, index) pairs
-    int32_t* toff = nullptr;  // n_tiles + 2
+    int32_t* toff[2] = {};  // tile offsets (n_tiles + 2) of the last two sorts
+    int toff_cur = 0;       // toff[toff_cur] belongs to the last sort
+    bool grouped = false;   // particle arrays are in the slot order of toff[toff_cur] (a push ran)
     int32_t* n_live = nullptr;
     int32_t* ws_cell = nullptr;
     float* ws_off[3] = {};
@@ -52,6 +54,8 @@ struct pic_box {
     Tiles tl{};
     int nsp = 1;
     Species sp[kMaxSpecies];
+    MigGeo mg{};            // migration sort geometry (y shifts set by each push)
+    bool mig_ok = false;    // the tile grid admits the migration sort
     // field sets: set[s][0..2] = B, set[s][3..5] = E (shearing box keeps 3 sets for the
     // fixed-point iterates); cur_set is the one holding the fields
     float* set[3][6] = {};
@@ -65,6 +69,7 @@ struct pic_box {
     double* red_part = nullptr;
     double* red_out = nullptr;
     int64_t step = 0;
+    int64_t n_migrations = 0;
     bool sorted = false;
     bool deposit_pending = false;
     bool track_ids = false;
@@ -265,7 +270,7 @@ StepDev make_step(pic_box* b)
         D.id_in = S.id[i];
         D.id_out = S.id[o];
         D.perm = reinterpret_cast<const int32_t*>(S.sb.vals[S.which]);
-        D.toff = S.toff;
+        D.toff = S.toff[S.toff_cur];
         D.ws_cell = S.ws_cell;
         D.qm_hdt = (float)(S.qm * dt / 2.0);
         D.q_dt = (float)(S.q / dt);
@@ -283,14 +288,41 @@ int32_t check_boxes(pic_box* const* boxes, int32_t nb)
 
 int32_t sort_box(pic_box* b)
 {
+    if (b->deposit_pending) return PIC_ESTATE;  // the unfused deposit reads this sort's slots
     for (int s = 0; s < b->nsp; s++) {
         Species& S = b->sp[s];
-        hipError_t e = tile_sort(S.cell[S.cur], S.n_live, S.n_upper, b->cc, b->tl, S.sb, S.toff,
-                                 S.n_live, S.which, b->st);
+        hipError_t e;
+        if (b->mig_ok && S.grouped) {
+            const int nxt = S.toff_cur ^ 1;
+            e = migrate_sort(S.cell[S.cur], S.toff[S.toff_cur], S.n_upper, b->cc, b->tl, b->mg,
+                             S.sb, S.toff[nxt], S.n_live, S.which, b->ctr + 2, b->st);
+            S.toff_cur = nxt;
+            b->n_migrations++;
+        } else {
+            e = tile_sort(S.cell[S.cur], S.n_live, S.n_upper, b->cc, b->tl, S.sb,
+                          S.toff[S.toff_cur], S.n_live, S.which, b->st);
+        }
         if (e != hipSuccess) return PIC_EDEVICE;
+        S.grouped = false;
     }
     b->sorted = true;
     return PIC_OK;
+}
+
+int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Tile y shifts of particles crossing the x faces of the shearing box in the push that uses
+// dys_int = floor(Delta y_s(t^{n+1})): the new y tile is within one of (old tile + shift).
+void set_migration_shift(pic_box* b, int dys_int)
+{
+    if (b->d.frame != PIC_FRAME_SHEAR) {
+        b->mg.cy_out = b->mg.cy_in = 0;
+        return;
+    }
+    const int TY = b->tile[1], nty = b->tl.nt[1];
+    auto wrap = [&](int v) { return ((v % nty) + nty) % nty; };
+    b->mg.cy_out = wrap(floor_div(dys_int - 1, TY) + 1);
+    b->mg.cy_in = wrap(floor_div(-dys_int - 2, TY) + 1);
 }
 
 int32_t zero_current(pic_box* b)
@@ -320,7 +352,11 @@ int32_t push_box(pic_box* b, bool fuse)
     }
     StepDev P = make_step(b);
     if (launch_gather_push(P, b->tile, fuse ? 1 : 0, b->st) != hipSuccess) return PIC_EDEVICE;
-    for (int s = 0; s < b->nsp; s++) b->sp[s].cur ^= 1;
+    set_migration_shift(b, P.dys_int);
+    for (int s = 0; s < b->nsp; s++) {
+        b->sp[s].cur ^= 1;
+        b->sp[s].grouped = true;
+    }
     b->sorted = false;
     b->deposit_pending = !fuse;
     return PIC_OK;
@@ -518,6 +554,17 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         b->tl.nt[k] = (n[k] + tile[k] - 1) / tile[k];
     }
     b->tl.n_tiles = b->tl.nt[0] * b->tl.nt[1] * b->tl.nt[2];
+    // migration sort: whole tiles, and on every axis one tile or at least three (so that the
+    // three steps -1, 0, +1 reach distinct tiles); the shearing box needs the x crossings
+    // visible in the tile index
+    b->mig_ok = true;
+    for (int k = 0; k < 3; k++) {
+        b->mg.nt[k] = b->tl.nt[k];
+        b->mg.lt[k] = b->tl.lt[k];
+        if (n[k] % tile[k] != 0 || b->tl.nt[k] == 2) b->mig_ok = false;
+    }
+    if (d->frame == PIC_FRAME_SHEAR && b->tl.nt[0] < 3) b->mig_ok = false;
+    b->mg.n_tiles = b->tl.n_tiles;
     GridDev& G = b->G;
     G.dim = b->dim;
     for (int k = 0; k < 3; k++) {
@@ -567,7 +614,16 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         }
         if (!r) r = dalloc(b, S.sb.hist, sort_hist_words((int64_t)cap));
         if (!r) r = dalloc(b, S.sb.scratch, scan_scratch_words((int64_t)sort_hist_words((int64_t)cap)));
-        if (!r) r = dalloc(b, S.toff, (size_t)b->tl.n_tiles + 2);
+        for (int k = 0; k < 2 && !r; k++) r = dalloc(b, S.toff[k], (size_t)b->tl.n_tiles + 2);
+        const size_t nt = (size_t)b->tl.n_tiles;
+        if (!r) r = dalloc(b, S.sb.mcnt, nt * kMigDirs);
+        if (!r) r = dalloc(b, S.sb.mpre, nt * kMigDirs);
+        if (!r) r = dalloc(b, S.sb.tot, nt + 1);
+        if (!r) r = dalloc(b, S.sb.start, nt + 1);
+        if (!r) r = dalloc(b, S.sb.dcnt, nt + 1);
+        if (!r) r = dalloc(b, S.sb.dpre, nt + 1);
+        if (!r) r = dalloc(b, S.sb.mscratch, migrate_scratch_words(b->tl.n_tiles));
+        if (!r) r = dalloc(b, S.sb.fallback, 1);
         if (!r) r = dalloc(b, S.n_live, 2);
         if (!r && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
     }
@@ -665,6 +721,7 @@ int32_t pic_set_particles(pic_box* b, int32_t s, int64_t n, const int32_t* cell,
         return PIC_EDEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return PIC_EDEVICE;
     S.n_upper = (int)n;
+    S.grouped = false;
     b->sorted = false;
     return PIC_OK;
 }
@@ -704,13 +761,14 @@ int32_t pic_get_sort(pic_box* b, int32_t s, int32_t* perm, int32_t* offsets, int
     Species& S = b->sp[s];
     if (n_tiles_out) *n_tiles_out = b->tl.n_tiles;
     int32_t n = 0;
-    if (hipMemcpyAsync(&n, S.toff + b->tl.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, b->st) != hipSuccess ||
+    const int32_t* toff = S.toff[S.toff_cur];
+    if (hipMemcpyAsync(&n, toff + b->tl.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, b->st) != hipSuccess ||
         hipStreamSynchronize(b->st) != hipSuccess)
         return PIC_EDEVICE;
     if (perm && n &&
         hipMemcpyAsync(perm, S.sb.vals[S.which], sizeof(int32_t) * n, hipMemcpyDeviceToDevice, b->st) != hipSuccess)
         return PIC_EDEVICE;
-    if (offsets && hipMemcpyAsync(offsets, S.toff, sizeof(int32_t) * (b->tl.n_tiles + 1),
+    if (offsets && hipMemcpyAsync(offsets, toff, sizeof(int32_t) * (b->tl.n_tiles + 1),
                                   hipMemcpyDeviceToDevice, b->st) != hipSuccess)
         return PIC_EDEVICE;
     return hip_fail(hipStreamSynchronize(b->st));
@@ -817,10 +875,12 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
         info->n_particles[s] = n;
     }
     uint32_t err = 0;
-    unsigned long long ctr[2] = {0, 0};
+    unsigned long long ctr[3] = {0, 0, 0};
     if (hipMemcpy(&err, b->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(ctr, b->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess)
         return PIC_EDEVICE;
+    info->n_sort_migrations = b->n_migrations;
+    info->n_sort_fallbacks = (int64_t)ctr[2];
     info->errors = err;
     info->n_slow = (int64_t)ctr[0];
     info->n_escaped = (int64_t)ctr[1];

@@ -170,6 +170,27 @@ struct SortBufs {
     uint32_t* vals[2];
     uint32_t* hist;
     uint32_t* scratch;
+    // migration sort (kMigDirs counters per source tile, per-destination scans)
+    uint32_t* mcnt;    // n_tiles * kMigDirs: particles of source tile s moving in direction d
+    uint32_t* mpre;    // n_tiles * kMigDirs: offset of (s, d) inside its destination tile
+    uint32_t* tot;     // n_tiles + 1: particles arriving in each tile (last entry 0)
+    uint32_t* start;   // n_tiles + 1: exclusive scan of tot
+    uint32_t* dcnt;    // n_tiles + 1: particles of each source tile that died (last entry 0)
+    uint32_t* dpre;    // n_tiles + 1: exclusive scan of dcnt
+    uint32_t* mscratch;
+    int32_t* fallback; // set when a particle left the neighbourhood the migration sort covers
+};
+
+// Directions of the migration sort: (dx, dy, dz) in {-1,0,1}^3 between the tile a particle
+// was sorted into and the tile of its new cell, index (dx+1) + 3 (dy+1) + 9 (dz+1); the last
+// direction is the dead bin.  Crossing the x faces of the shearing box shifts y by the tile
+// offset cy_out (leaving through the outer face) or cy_in (inner face) before dy is taken.
+constexpr int kMigDirs = 28;
+constexpr int kMigDead = 27;
+struct MigGeo {
+    int nt[3], lt[3];
+    int n_tiles;
+    int cy_out, cy_in;
 };
 
 // ---- launchers (gpd.hip, sort.hip, grid.hip, xfer.hip)
@@ -182,6 +203,16 @@ size_t sort_hist_words(int64_t n);
 hipError_t tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper, CellCode cc,
                      Tiles tl, SortBufs& sb, int32_t* toff, int32_t* n_live_out, int& which,
                      hipStream_t st);
+
+// Migration sort: stable counting sort by tile of arrays still grouped by the tiles of the
+// previous sort (toff_prev), every particle within one tile of its old one.  Falls back to
+// tile_sort on the device when a particle is outside that neighbourhood.  Writes the
+// permutation to sb.vals[which] and the offsets to toff.
+size_t migrate_scratch_words(int n_tiles);
+hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upper, CellCode cc,
+                        Tiles tl, const MigGeo& mg, SortBufs& sb, int32_t* toff,
+                        int32_t* n_live_out, int& which, unsigned long long* n_fallback,
+                        hipStream_t st);
 
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
                        hipStream_t st);

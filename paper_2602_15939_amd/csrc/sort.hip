@@ -13,14 +13,22 @@ namespace pic {
 constexpr int kItems = 16;                // items per thread per chunk
 constexpr int kChunk = kBlock * kItems;   // 4096 items per block
 
+// A launch gated on a device flag runs only when *flag == want (flag == nullptr: always), so
+// that a fallback path can be queued behind a test without a host round trip.
+struct Gate {
+    const int32_t* flag;
+    int want;
+    __device__ inline bool off() const { return flag && *flag != want; }
+};
+
 __global__ __launch_bounds__(kBlock) void make_keys_kernel(const int32_t* __restrict__ cell,
                                                            const int32_t* __restrict__ n_live,
                                                            int n_upper, CellCode cc, Tiles tl,
                                                            uint32_t* __restrict__ keys,
-                                                           uint32_t* __restrict__ vals)
+                                                           uint32_t* __restrict__ vals, Gate g)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_upper) return;
+    if (i >= n_upper || g.off()) return;
     const int nl = *n_live;
     uint32_t k = (uint32_t)tl.n_tiles;
     if (i < nl) {
@@ -37,8 +45,9 @@ __global__ __launch_bounds__(kBlock) void make_keys_kernel(const int32_t* __rest
 
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                             int n, int shift,
-                                                            uint32_t* __restrict__ hist)
+                                                            uint32_t* __restrict__ hist, Gate g)
 {
+    if (g.off()) return;
     __shared__ uint32_t cnt[256];
     const int tid = threadIdx.x;
     cnt[tid] = 0;
@@ -55,8 +64,10 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
 
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int n, int shift,
-    const uint32_t* __restrict__ hscan, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout)
+    const uint32_t* __restrict__ hscan, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+    Gate g)
 {
+    if (g.off()) return;
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -98,8 +109,9 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
 // count (dead bin starts there), off[n_tiles+1] = n.
 __global__ __launch_bounds__(kBlock) void offsets_kernel(const uint32_t* __restrict__ keys, int n,
                                                          int n_tiles, int32_t* __restrict__ off,
-                                                         int32_t* __restrict__ n_live)
+                                                         int32_t* __restrict__ n_live, Gate g)
 {
+    if (g.off()) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (n == 0) {
         if (i <= n_tiles + 1) off[i] = 0;
@@ -134,8 +146,9 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
 }
 
 __global__ __launch_bounds__(kBlock) void scan_blocks_kernel(const uint32_t* in, uint32_t* out,
-                                                             int n, uint32_t* bsum)
+                                                             int n, uint32_t* bsum, Gate g)
 {
+    if (g.off()) return;
     __shared__ uint32_t s[kChunk];
     __shared__ uint32_t ws[4];
     const int tid = threadIdx.x;
@@ -173,8 +186,9 @@ __global__ __launch_bounds__(kBlock) void scan_blocks_kernel(const uint32_t* in,
 }
 
 __global__ __launch_bounds__(kBlock) void scan_add_kernel(uint32_t* out, int n,
-                                                          const uint32_t* bpre)
+                                                          const uint32_t* bpre, Gate g)
 {
+    if (g.off()) return;
     const int64_t i = (int64_t)blockIdx.x * kChunk;
     const uint32_t add = bpre[blockIdx.x];
     for (int k = 0; k < kItems; k++) {
@@ -194,51 +208,353 @@ size_t scan_scratch_words(int64_t n)
     return w + 64;
 }
 
-hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int n, uint32_t* scratch,
-                          hipStream_t st)
+static hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int n, uint32_t* scratch,
+                                 hipStream_t st, Gate g)
 {
     if (n <= 0) return hipSuccess;
     const int nblk = (n + kChunk - 1) / kChunk;
     uint32_t* bsum = scratch;
     uint32_t* bpre = scratch + nblk;
-    scan_blocks_kernel<<<nblk, kBlock, 0, st>>>(in, out, n, nblk > 1 ? bsum : nullptr);
+    scan_blocks_kernel<<<nblk, kBlock, 0, st>>>(in, out, n, nblk > 1 ? bsum : nullptr, g);
     if (nblk > 1) {
-        hipError_t e = scan_exclusive(bsum, bpre, nblk, scratch + 2 * nblk + 64, st);
+        hipError_t e = scan_exclusive(bsum, bpre, nblk, scratch + 2 * nblk + 64, st, g);
         if (e != hipSuccess) return e;
-        scan_add_kernel<<<nblk, kBlock, 0, st>>>(out, n, bpre);
+        scan_add_kernel<<<nblk, kBlock, 0, st>>>(out, n, bpre, g);
     }
     return hipGetLastError();
 }
 
 size_t sort_hist_words(int64_t n) { return 256 * (size_t)((n + kChunk - 1) / kChunk) + 64; }
 
+static int radix_passes(const Tiles& tl)
+{
+    int bits = 0;
+    while ((1u << bits) <= (unsigned)tl.n_tiles) bits++;
+    return (bits + 7) / 8;
+}
+
+static hipError_t radix_tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper,
+                                  CellCode cc, Tiles tl, SortBufs& sb, int32_t* toff,
+                                  int32_t* n_live_out, int& which, hipStream_t st, Gate g)
+{
+    which = 0;
+    if (n_upper > 0) {
+        make_keys_kernel<<<(n_upper + kBlock - 1) / kBlock, kBlock, 0, st>>>(
+            cell, n_live_in, n_upper, cc, tl, sb.keys[0], sb.vals[0], g);
+        const int passes = radix_passes(tl);
+        const int nblk = (n_upper + kChunk - 1) / kChunk;
+        for (int p = 0; p < passes; p++) {
+            const int shift = 8 * p;
+            radix_hist_kernel<<<nblk, kBlock, 0, st>>>(sb.keys[which], n_upper, shift, sb.hist, g);
+            hipError_t e = scan_exclusive(sb.hist, sb.hist, 256 * nblk, sb.scratch, st, g);
+            if (e != hipSuccess) return e;
+            radix_scatter_kernel<<<nblk, kBlock, 0, st>>>(sb.keys[which], sb.vals[which], n_upper,
+                                                          shift, sb.hist, sb.keys[which ^ 1],
+                                                          sb.vals[which ^ 1], g);
+            which ^= 1;
+        }
+    }
+    const int nb = ((n_upper > tl.n_tiles + 2 ? n_upper : tl.n_tiles + 2) + kBlock - 1) / kBlock;
+    offsets_kernel<<<nb, kBlock, 0, st>>>(sb.keys[which], n_upper, tl.n_tiles, toff, n_live_out, g);
+    return hipGetLastError();
+}
+
 // Stable sort by tile; returns the buffer index (0/1) holding the sorted (key, index) pairs.
 hipError_t tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper, CellCode cc,
                      Tiles tl, SortBufs& sb, int32_t* toff, int32_t* n_live_out, int& which,
                      hipStream_t st)
 {
-    which = 0;
-    if (n_upper > 0) {
-        make_keys_kernel<<<(n_upper + kBlock - 1) / kBlock, kBlock, 0, st>>>(
-            cell, n_live_in, n_upper, cc, tl, sb.keys[0], sb.vals[0]);
-        int bits = 0;
-        while ((1u << bits) <= (unsigned)tl.n_tiles) bits++;
-        const int passes = (bits + 7) / 8;
-        const int nblk = (n_upper + kChunk - 1) / kChunk;
-        for (int p = 0; p < passes; p++) {
-            const int shift = 8 * p;
-            radix_hist_kernel<<<nblk, kBlock, 0, st>>>(sb.keys[which], n_upper, shift, sb.hist);
-            hipError_t e = scan_exclusive(sb.hist, sb.hist, 256 * nblk, sb.scratch, st);
-            if (e != hipSuccess) return e;
-            radix_scatter_kernel<<<nblk, kBlock, 0, st>>>(sb.keys[which], sb.vals[which], n_upper,
-                                                          shift, sb.hist, sb.keys[which ^ 1],
-                                                          sb.vals[which ^ 1]);
-            which ^= 1;
+    return radix_tile_sort(cell, n_live_in, n_upper, cc, tl, sb, toff, n_live_out, which, st,
+                           Gate{nullptr, 0});
+}
+
+// ------------------------------------------------------------------ migration sort
+// Between two sorts a particle moves less than one cell, so the particles of source tile s
+// (the slots toff_prev[s] .. toff_prev[s+1]-1, in the order of the previous sort) land in s or
+// one of its neighbours.  The stable counting sort by the new tile then needs, per source tile,
+// only the counts per direction (kMigDirs of them) instead of a full radix sort:
+//   count:   per source tile, particles per direction;
+//   offsets: per destination tile, its (at most 27) sources in increasing tile order give each
+//            (source, direction) pair its offset inside the destination, and the total;
+//   scans:   destination starts (= the new tile offsets) and the dead bin's per-source starts;
+//   scatter: per source tile, in slot order, stable ranks per direction by wave ballots.
+// The result equals the stable radix sort: within a destination tile the particles come in
+// increasing source tile, i.e. increasing slot.  Slots from the previous dead bin stay dead,
+// after the particles that died since.
+
+// d reduced on a ring of n tiles to -1, 0, +1, or 2 if it is farther
+__device__ inline int ring_step(int d, int n)
+{
+    if (n == 1) return 0;
+    int r = d % n;
+    if (r < 0) r += n;
+    if (r == 0) return 0;
+    if (r == 1) return 1;
+    if (r == n - 1) return -1;
+    return 2;
+}
+
+__device__ inline void tile_coords(const MigGeo& g, int t, int& x, int& y, int& z)
+{
+    x = t % g.nt[0];
+    const int r = t / g.nt[0];
+    y = r % g.nt[1];
+    z = r / g.nt[1];
+}
+
+// direction of a particle of source tile (sx, sy, sz) with new cell c, or -1 if its new tile is
+// not a neighbour
+__device__ inline int mig_dir(const MigGeo& g, const CellCode& cc, int sx, int sy, int sz,
+                              int32_t c)
+{
+    if (c < 0) return kMigDead;
+    int x, y, z;
+    cc.decode(c, x, y, z);
+    const int tx = x >> g.lt[0], ty = y >> g.lt[1], tz = z >> g.lt[2];
+    int dx = tx - sx, wx = 0;
+    if (g.nt[0] == 1) {
+        dx = 0;
+    } else if (dx == g.nt[0] - 1 && dx > 1) {  // through the inner x face
+        dx = -1;
+        wx = -1;
+    } else if (dx == 1 - g.nt[0] && dx < -1) {  // through the outer x face
+        dx = 1;
+        wx = 1;
+    } else if (dx < -1 || dx > 1) {
+        return -1;
+    }
+    const int shift = wx > 0 ? g.cy_out : (wx < 0 ? g.cy_in : 0);
+    const int dy = ring_step(ty - sy - shift, g.nt[1]);
+    const int dz = ring_step(tz - sz, g.nt[2]);
+    if (dy == 2 || dz == 2) return -1;
+    return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
+
+__device__ inline void dir_steps(int d, int& dx, int& dy, int& dz)
+{
+    dx = d % 3 - 1;
+    dy = (d / 3) % 3 - 1;
+    dz = d / 9 - 1;
+}
+
+__device__ inline bool dir_possible(const MigGeo& g, int dx, int dy, int dz)
+{
+    return (g.nt[0] > 1 || dx == 0) && (g.nt[1] > 1 || dy == 0) && (g.nt[2] > 1 || dz == 0);
+}
+
+__device__ inline int wrap_tile(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// tile reached from source (sx, sy, sz) in direction (dx, dy, dz)
+__device__ inline int mig_dst(const MigGeo& g, int sx, int sy, int sz, int dx, int dy, int dz)
+{
+    int tx = sx + dx, wx = 0;
+    if (tx >= g.nt[0]) {
+        tx -= g.nt[0];
+        wx = 1;
+    } else if (tx < 0) {
+        tx += g.nt[0];
+        wx = -1;
+    }
+    const int shift = wx > 0 ? g.cy_out : (wx < 0 ? g.cy_in : 0);
+    return tx + g.nt[0] * (wrap_tile(sy + dy + shift, g.nt[1]) + g.nt[1] * wrap_tile(sz + dz, g.nt[2]));
+}
+
+// source tile that reaches (tx, ty, tz) in direction (dx, dy, dz)
+__device__ inline int mig_src(const MigGeo& g, int tx, int ty, int tz, int dx, int dy, int dz)
+{
+    int sx = tx - dx, wx = 0;
+    if (sx < 0) {  // the source sits at the outer end and left through the outer face
+        sx += g.nt[0];
+        wx = 1;
+    } else if (sx >= g.nt[0]) {
+        sx -= g.nt[0];
+        wx = -1;
+    }
+    const int shift = wx > 0 ? g.cy_out : (wx < 0 ? g.cy_in : 0);
+    return sx + g.nt[0] * (wrap_tile(ty - dy - shift, g.nt[1]) + g.nt[1] * wrap_tile(tz - dz, g.nt[2]));
+}
+
+__global__ __launch_bounds__(kBlock) void mig_count_kernel(const int32_t* __restrict__ cell,
+                                                           const int32_t* __restrict__ toff_prev,
+                                                           CellCode cc, MigGeo g,
+                                                           uint32_t* __restrict__ mcnt,
+                                                           int32_t* __restrict__ fallback)
+{
+    __shared__ uint32_t cnt[kMigDirs];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    if (tid < kMigDirs) cnt[tid] = 0;
+    __syncthreads();
+    int sx, sy, sz;
+    tile_coords(g, s, sx, sy, sz);
+    const int beg = toff_prev[s], end = toff_prev[s + 1];
+    uint32_t stay = 0;
+    bool bad = false;
+    for (int i = beg + tid; i < end; i += kBlock) {
+        const int d = mig_dir(g, cc, sx, sy, sz, cell[i]);
+        if (d == 13)
+            stay++;
+        else if (d >= 0)
+            atomicAdd(&cnt[d], 1u);
+        else
+            bad = true;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) stay += __shfl_xor(stay, o, 64);
+    if ((tid & 63) == 0 && stay) atomicAdd(&cnt[13], stay);
+    if (bad) *fallback = 1;
+    __syncthreads();
+    if (tid < kMigDirs) mcnt[(size_t)s * kMigDirs + tid] = cnt[tid];
+}
+
+// one wave per destination tile
+__global__ __launch_bounds__(kBlock) void mig_offsets_kernel(const uint32_t* __restrict__ mcnt,
+                                                             MigGeo g, uint32_t* __restrict__ mpre,
+                                                             uint32_t* __restrict__ tot,
+                                                             uint32_t* __restrict__ dcnt, Gate gate)
+{
+    if (gate.off()) return;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (t == 0 && lane == 0) {
+        tot[g.n_tiles] = 0;
+        dcnt[g.n_tiles] = 0;
+    }
+    if (t >= g.n_tiles) return;
+    int tx, ty, tz;
+    tile_coords(g, t, tx, ty, tz);
+    uint32_t c = 0;
+    int key = 0x7fffffff, src = 0;
+    if (lane < 27) {
+        int dx, dy, dz;
+        dir_steps(lane, dx, dy, dz);
+        if (dir_possible(g, dx, dy, dz)) {
+            src = mig_src(g, tx, ty, tz, dx, dy, dz);
+            key = src;
+            c = mcnt[(size_t)src * kMigDirs + lane];
         }
     }
-    const int g = ((n_upper > tl.n_tiles + 2 ? n_upper : tl.n_tiles + 2) + kBlock - 1) / kBlock;
-    offsets_kernel<<<g, kBlock, 0, st>>>(sb.keys[which], n_upper, tl.n_tiles, toff, n_live_out);
-    return hipGetLastError();
+    uint32_t pre = 0, total = 0;
+    for (int k = 0; k < 27; k++) {
+        const int kk = __shfl(key, k, 64);
+        const uint32_t ck = __shfl(c, k, 64);
+        total += ck;
+        if (kk < key) pre += ck;
+    }
+    if (lane < 27 && key != 0x7fffffff) mpre[(size_t)src * kMigDirs + lane] = pre;
+    if (lane == 0) {
+        tot[t] = total;
+        dcnt[t] = mcnt[(size_t)t * kMigDirs + kMigDead];
+    }
+}
+
+// block s < n_tiles: the particles of source tile s; block n_tiles: the previous dead bin
+__global__ __launch_bounds__(kBlock) void mig_scatter_kernel(
+    const int32_t* __restrict__ cell, const int32_t* __restrict__ toff_prev, int n_upper,
+    CellCode cc, MigGeo g, const uint32_t* __restrict__ mpre, const uint32_t* __restrict__ start,
+    const uint32_t* __restrict__ dpre, uint32_t* __restrict__ perm, int32_t* __restrict__ toff,
+    int32_t* __restrict__ n_live, Gate gate)
+{
+    if (gate.off()) return;
+    __shared__ uint32_t run[2][kMigDirs];
+    __shared__ uint32_t wc[kBlock / 64][kMigDirs];
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t live = start[g.n_tiles];
+    if (s == g.n_tiles) {
+        const int beg = toff_prev[g.n_tiles];
+        const uint32_t base = live + dpre[g.n_tiles];
+        for (int i = beg + tid; i < n_upper; i += kBlock) perm[base + (uint32_t)(i - beg)] = (uint32_t)i;
+        if (tid == 0) {
+            toff[g.n_tiles] = (int32_t)live;
+            toff[g.n_tiles + 1] = n_upper;
+            *n_live = (int32_t)live;
+        }
+        return;
+    }
+    int sx, sy, sz;
+    tile_coords(g, s, sx, sy, sz);
+    if (tid == 0) toff[s] = (int32_t)start[s];
+    if (tid < kMigDirs) {
+        uint32_t b = 0;
+        if (tid == kMigDead) {
+            b = live + dpre[s];
+        } else {
+            int dx, dy, dz;
+            dir_steps(tid, dx, dy, dz);
+            if (dir_possible(g, dx, dy, dz))
+                b = start[mig_dst(g, sx, sy, sz, dx, dy, dz)] + mpre[(size_t)s * kMigDirs + tid];
+        }
+        run[0][tid] = b;
+    }
+    __syncthreads();
+    const int beg = toff_prev[s], end = toff_prev[s + 1];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int p = 0;
+    for (int cb = beg; cb < end; cb += kBlock) {
+        const int i = cb + tid;
+        const bool valid = i < end;
+        const int d = valid ? mig_dir(g, cc, sx, sy, sz, cell[i]) : -1;
+        unsigned long long rem = __ballot(valid);
+        uint32_t rank = 0, mine = 0;
+        while (rem) {
+            const int lead = __builtin_ctzll(rem);
+            const int dl = __shfl(d, lead, 64);
+            const unsigned long long m = __ballot(d == dl) & rem;
+            if (d == dl) rank = (uint32_t)__popcll(m & lt);
+            if (lane == dl) mine = (uint32_t)__popcll(m);
+            rem &= ~m;
+        }
+        if (lane < kMigDirs) wc[w][lane] = mine;
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[p][d] + rank;
+            for (int k = 0; k < w; k++) pos += wc[k][d];
+            perm[pos] = (uint32_t)i;
+        }
+        if (tid < kMigDirs) {
+            uint32_t a = run[p][tid];
+            for (int k = 0; k < kBlock / 64; k++) a += wc[k][tid];
+            run[p ^ 1][tid] = a;
+        }
+        __syncthreads();
+        p ^= 1;
+    }
+}
+
+__global__ void count_fallback_kernel(unsigned long long* ctr, Gate g)
+{
+    if (!g.off()) ctr[0] += 1ull;
+}
+
+size_t migrate_scratch_words(int n_tiles) { return scan_scratch_words((int64_t)n_tiles + 1); }
+
+hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upper, CellCode cc,
+                        Tiles tl, const MigGeo& mg, SortBufs& sb, int32_t* toff,
+                        int32_t* n_live_out, int& which, unsigned long long* n_fallback,
+                        hipStream_t st)
+{
+    const int nt = tl.n_tiles;
+    const Gate mig{sb.fallback, 0}, radix{sb.fallback, 1};
+    which = radix_passes(tl) & 1;  // where the radix fallback leaves its result
+    if (hipMemsetAsync(sb.fallback, 0, sizeof(int32_t), st) != hipSuccess) return hipGetLastError();
+    mig_count_kernel<<<nt, kBlock, 0, st>>>(cell, toff_prev, cc, mg, sb.mcnt, sb.fallback);
+    mig_offsets_kernel<<<(nt + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, st>>>(
+        sb.mcnt, mg, sb.mpre, sb.tot, sb.dcnt, mig);
+    hipError_t e = scan_exclusive(sb.tot, sb.start, nt + 1, sb.mscratch, st, mig);
+    if (e == hipSuccess) e = scan_exclusive(sb.dcnt, sb.dpre, nt + 1, sb.mscratch, st, mig);
+    if (e != hipSuccess) return e;
+    mig_scatter_kernel<<<nt + 1, kBlock, 0, st>>>(cell, toff_prev, n_upper, cc, mg, sb.mpre,
+                                                   sb.start, sb.dpre, sb.vals[which], toff,
+                                                   n_live_out, mig);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int w2 = 0;
+    e = radix_tile_sort(cell, toff_prev + nt, n_upper, cc, tl, sb, toff, n_live_out, w2, st, radix);
+    if (e == hipSuccess) count_fallback_kernel<<<1, 1, 0, st>>>(n_fallback, radix);
+    return e == hipSuccess ? hipGetLastError() : e;
 }
 
 }  // namespace pic

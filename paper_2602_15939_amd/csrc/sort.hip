@@ -27,81 +27,88 @@ __global__ __launch_bounds__(kBlock) void make_keys_kernel(const int32_t* __rest
                                                            uint32_t* __restrict__ keys,
                                                            uint32_t* __restrict__ vals, Gate g)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_upper || g.off()) return;
+    if (g.off()) return;
     const int nl = *n_live;
-    uint32_t k = (uint32_t)tl.n_tiles;
-    if (i < nl) {
-        const int32_t c = cell[i];
-        if (c >= 0) {
-            int x, y, z;
-            cc.decode(c, x, y, z);
-            k = (uint32_t)tl.key(x, y, z);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n_upper; i += gridDim.x * kBlock) {
+        uint32_t k = (uint32_t)tl.n_tiles;
+        if (i < nl) {
+            const int32_t c = cell[i];
+            if (c >= 0) {
+                int x, y, z;
+                cc.decode(c, x, y, z);
+                k = (uint32_t)tl.key(x, y, z);
+            }
         }
+        keys[i] = k;
+        vals[i] = (uint32_t)i;
     }
-    keys[i] = k;
-    vals[i] = (uint32_t)i;
 }
 
+// chunks of kChunk keys, a grid-stride loop over them (the grid is capped so that a gated-off
+// launch costs a few microseconds)
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                            int n, int shift,
+                                                            int n, int nchunks, int shift,
                                                             uint32_t* __restrict__ hist, Gate g)
 {
     if (g.off()) return;
     __shared__ uint32_t cnt[256];
     const int tid = threadIdx.x;
-    cnt[tid] = 0;
-    __syncthreads();
-    const int base = blockIdx.x * kChunk;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        cnt[tid] = 0;
+        __syncthreads();
+        const int base = ch * kChunk;
 #pragma unroll 4
-    for (int r = 0; r < kItems; r++) {
-        const int i = base + r * kBlock + tid;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        for (int r = 0; r < kItems; r++) {
+            const int i = base + r * kBlock + tid;
+            if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        hist[tid * nchunks + ch] = cnt[tid];
+        __syncthreads();
     }
-    __syncthreads();
-    hist[tid * gridDim.x + blockIdx.x] = cnt[tid];
 }
 
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int n, int shift,
-    const uint32_t* __restrict__ hscan, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-    Gate g)
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int n, int nchunks,
+    int shift, const uint32_t* __restrict__ hscan, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, Gate g)
 {
     if (g.off()) return;
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int nblk = gridDim.x, b = blockIdx.x;
-    base[tid] = hscan[tid * nblk + b];
     const unsigned long long lt = (1ull << lane) - 1ull;
-    for (int r = 0; r < kItems; r++) {
-        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
-        __syncthreads();
-        const int i = b * kChunk + r * kBlock + tid;
-        const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t val = valid ? vin[i] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-        unsigned long long m = __ballot(valid);
+    for (int b = blockIdx.x; b < nchunks; b += gridDim.x) {
+        base[tid] = hscan[tid * nchunks + b];
+        for (int r = 0; r < kItems; r++) {
+            wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+            __syncthreads();
+            const int i = b * kChunk + r * kBlock + tid;
+            const bool valid = i < n;
+            const uint32_t key = valid ? kin[i] : 0u;
+            const uint32_t val = valid ? vin[i] : 0u;
+            const uint32_t d = (key >> shift) & 255u;
+            unsigned long long m = __ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < 8; bit++) {
-            const bool on = (d >> bit) & 1u;
-            const unsigned long long bb = __ballot(on);
-            m &= on ? bb : ~bb;
+            for (int bit = 0; bit < 8; bit++) {
+                const bool on = (d >> bit) & 1u;
+                const unsigned long long bb = __ballot(on);
+                m &= on ? bb : ~bb;
+            }
+            const int rank = __popcll(m & lt);
+            if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(m);
+            __syncthreads();
+            if (valid) {
+                uint32_t pre = 0;
+                for (int k = 0; k < w; k++) pre += wcnt[k][d];
+                const uint32_t pos = base[d] + pre + (uint32_t)rank;
+                kout[pos] = key;
+                vout[pos] = val;
+            }
+            __syncthreads();
+            base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+            __syncthreads();
         }
-        const int rank = __popcll(m & lt);
-        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = 0;
-            for (int k = 0; k < w; k++) pre += wcnt[k][d];
-            const uint32_t pos = base[d] + pre + (uint32_t)rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-        __syncthreads();
     }
 }
 
@@ -112,23 +119,24 @@ __global__ __launch_bounds__(kBlock) void offsets_kernel(const uint32_t* __restr
                                                          int32_t* __restrict__ n_live, Gate g)
 {
     if (g.off()) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int stride = gridDim.x * kBlock;
     if (n == 0) {
-        if (i <= n_tiles + 1) off[i] = 0;
-        if (i == 0) *n_live = 0;
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i <= n_tiles + 1; i += stride) off[i] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) *n_live = 0;
         return;
     }
-    if (i >= n) return;
-    const int k = (int)keys[i];
-    const int kp = i > 0 ? (int)keys[i - 1] : -1;
-    for (int t = kp + 1; t <= k; t++) {
-        off[t] = i;
-        if (t == n_tiles) *n_live = i;
-    }
-    if (i == n - 1) {
-        for (int t = k + 1; t <= n_tiles + 1; t++) {
-            off[t] = n;
-            if (t == n_tiles) *n_live = n;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const int k = (int)keys[i];
+        const int kp = i > 0 ? (int)keys[i - 1] : -1;
+        for (int t = kp + 1; t <= k; t++) {
+            off[t] = i;
+            if (t == n_tiles) *n_live = i;
+        }
+        if (i == n - 1) {
+            for (int t = k + 1; t <= n_tiles + 1; t++) {
+                off[t] = n;
+                if (t == n_tiles) *n_live = n;
+            }
         }
     }
 }
@@ -226,6 +234,9 @@ static hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int n, uint3
 
 size_t sort_hist_words(int64_t n) { return 256 * (size_t)((n + kChunk - 1) / kChunk) + 64; }
 
+// grid of the radix kernels: enough workgroups to fill the chip, loops beyond
+static unsigned grid_cap(int blocks) { return (unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096); }
+
 static int radix_passes(const Tiles& tl)
 {
     int bits = 0;
@@ -239,23 +250,25 @@ static hipError_t radix_tile_sort(const int32_t* cell, const int32_t* n_live_in,
 {
     which = 0;
     if (n_upper > 0) {
-        make_keys_kernel<<<(n_upper + kBlock - 1) / kBlock, kBlock, 0, st>>>(
+        make_keys_kernel<<<grid_cap((n_upper + kBlock - 1) / kBlock), kBlock, 0, st>>>(
             cell, n_live_in, n_upper, cc, tl, sb.keys[0], sb.vals[0], g);
         const int passes = radix_passes(tl);
-        const int nblk = (n_upper + kChunk - 1) / kChunk;
+        const int nchunks = (n_upper + kChunk - 1) / kChunk;
         for (int p = 0; p < passes; p++) {
             const int shift = 8 * p;
-            radix_hist_kernel<<<nblk, kBlock, 0, st>>>(sb.keys[which], n_upper, shift, sb.hist, g);
-            hipError_t e = scan_exclusive(sb.hist, sb.hist, 256 * nblk, sb.scratch, st, g);
+            radix_hist_kernel<<<grid_cap(nchunks), kBlock, 0, st>>>(sb.keys[which], n_upper,
+                                                                     nchunks, shift, sb.hist, g);
+            hipError_t e = scan_exclusive(sb.hist, sb.hist, 256 * nchunks, sb.scratch, st, g);
             if (e != hipSuccess) return e;
-            radix_scatter_kernel<<<nblk, kBlock, 0, st>>>(sb.keys[which], sb.vals[which], n_upper,
-                                                          shift, sb.hist, sb.keys[which ^ 1],
-                                                          sb.vals[which ^ 1], g);
+            radix_scatter_kernel<<<grid_cap(nchunks), kBlock, 0, st>>>(
+                sb.keys[which], sb.vals[which], n_upper, nchunks, shift, sb.hist,
+                sb.keys[which ^ 1], sb.vals[which ^ 1], g);
             which ^= 1;
         }
     }
     const int nb = ((n_upper > tl.n_tiles + 2 ? n_upper : tl.n_tiles + 2) + kBlock - 1) / kBlock;
-    offsets_kernel<<<nb, kBlock, 0, st>>>(sb.keys[which], n_upper, tl.n_tiles, toff, n_live_out, g);
+    offsets_kernel<<<grid_cap(nb), kBlock, 0, st>>>(sb.keys[which], n_upper, tl.n_tiles, toff,
+                                                    n_live_out, g);
     return hipGetLastError();
 }
 
@@ -378,6 +391,8 @@ __device__ inline int mig_src(const MigGeo& g, int tx, int ty, int tz, int dx, i
     return sx + g.nt[0] * (wrap_tile(ty - dy - shift, g.nt[1]) + g.nt[1] * wrap_tile(tz - dz, g.nt[2]));
 }
 
+constexpr int kMigItems = 4;  // particles per thread per round of the migration kernels
+
 __global__ __launch_bounds__(kBlock) void mig_count_kernel(const int32_t* __restrict__ cell,
                                                            const int32_t* __restrict__ toff_prev,
                                                            CellCode cc, MigGeo g,
@@ -393,14 +408,24 @@ __global__ __launch_bounds__(kBlock) void mig_count_kernel(const int32_t* __rest
     const int beg = toff_prev[s], end = toff_prev[s + 1];
     uint32_t stay = 0;
     bool bad = false;
-    for (int i = beg + tid; i < end; i += kBlock) {
-        const int d = mig_dir(g, cc, sx, sy, sz, cell[i]);
-        if (d == 13)
-            stay++;
-        else if (d >= 0)
-            atomicAdd(&cnt[d], 1u);
-        else
-            bad = true;
+    for (int cb = beg; cb < end; cb += kBlock * kMigItems) {
+        int32_t c[kMigItems];
+#pragma unroll
+        for (int j = 0; j < kMigItems; j++) {
+            const int i = cb + j * kBlock + tid;
+            c[j] = i < end ? cell[i] : INT32_MIN;
+        }
+#pragma unroll
+        for (int j = 0; j < kMigItems; j++) {
+            if (c[j] == INT32_MIN) continue;
+            const int d = mig_dir(g, cc, sx, sy, sz, c[j]);
+            if (d == 13)
+                stay++;
+            else if (d >= 0)
+                atomicAdd(&cnt[d], 1u);
+            else
+                bad = true;
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) stay += __shfl_xor(stay, o, 64);
@@ -460,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void mig_scatter_kernel(
 {
     if (gate.off()) return;
     __shared__ uint32_t run[2][kMigDirs];
-    __shared__ uint32_t wc[kBlock / 64][kMigDirs];
+    __shared__ uint32_t wc[kMigItems][kBlock / 64][kMigDirs];
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t live = start[g.n_tiles];
     if (s == g.n_tiles) {
@@ -493,30 +518,49 @@ __global__ __launch_bounds__(kBlock) void mig_scatter_kernel(
     const int beg = toff_prev[s], end = toff_prev[s + 1];
     const unsigned long long lt = (1ull << lane) - 1ull;
     int p = 0;
-    for (int cb = beg; cb < end; cb += kBlock) {
-        const int i = cb + tid;
-        const bool valid = i < end;
-        const int d = valid ? mig_dir(g, cc, sx, sy, sz, cell[i]) : -1;
-        unsigned long long rem = __ballot(valid);
-        uint32_t rank = 0, mine = 0;
-        while (rem) {
-            const int lead = __builtin_ctzll(rem);
-            const int dl = __shfl(d, lead, 64);
-            const unsigned long long m = __ballot(d == dl) & rem;
-            if (d == dl) rank = (uint32_t)__popcll(m & lt);
-            if (lane == dl) mine = (uint32_t)__popcll(m);
-            rem &= ~m;
+    // rounds of kBlock * kMigItems slots; item j of a round covers slots j*kBlock .. +kBlock-1,
+    // so the stable order inside a round is (item, wave, lane)
+    for (int cb = beg; cb < end; cb += kBlock * kMigItems) {
+        int32_t c[kMigItems];
+#pragma unroll
+        for (int j = 0; j < kMigItems; j++) {
+            const int i = cb + j * kBlock + tid;
+            c[j] = i < end ? cell[i] : 0;
         }
-        if (lane < kMigDirs) wc[w][lane] = mine;
+        int d[kMigItems];
+        uint32_t rank[kMigItems];
+#pragma unroll
+        for (int j = 0; j < kMigItems; j++) {
+            const bool valid = cb + j * kBlock + tid < end;
+            d[j] = valid ? mig_dir(g, cc, sx, sy, sz, c[j]) : -1;
+            unsigned long long rem = __ballot(valid);
+            uint32_t r = 0, mine = 0;
+            while (rem) {
+                const int lead = __builtin_ctzll(rem);
+                const int dl = __shfl(d[j], lead, 64);
+                const unsigned long long m = __ballot(d[j] == dl) & rem;
+                if (d[j] == dl) r = (uint32_t)__popcll(m & lt);
+                if (lane == dl) mine = (uint32_t)__popcll(m);
+                rem &= ~m;
+            }
+            rank[j] = r;
+            if (lane < kMigDirs) wc[j][w][lane] = mine;
+        }
         __syncthreads();
-        if (valid) {
-            uint32_t pos = run[p][d] + rank;
-            for (int k = 0; k < w; k++) pos += wc[k][d];
-            perm[pos] = (uint32_t)i;
+#pragma unroll
+        for (int j = 0; j < kMigItems; j++) {
+            if (d[j] < 0) continue;
+            const int dj = d[j];
+            uint32_t pos = run[p][dj] + rank[j];
+            for (int jj = 0; jj < j; jj++)
+                for (int k = 0; k < kBlock / 64; k++) pos += wc[jj][k][dj];
+            for (int k = 0; k < w; k++) pos += wc[j][k][dj];
+            perm[pos] = (uint32_t)(cb + j * kBlock + tid);
         }
         if (tid < kMigDirs) {
             uint32_t a = run[p][tid];
-            for (int k = 0; k < kBlock / 64; k++) a += wc[k][tid];
+            for (int jj = 0; jj < kMigItems; jj++)
+                for (int k = 0; k < kBlock / 64; k++) a += wc[jj][k][tid];
             run[p ^ 1][tid] = a;
         }
         __syncthreads();

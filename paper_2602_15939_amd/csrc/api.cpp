@@ -82,6 +82,7 @@ struct pic_box {
 namespace {
 
 constexpr int kRedBlocks = 1024;
+constexpr int kRowAlign = 32;  // floats per 128-byte line
 
 int32_t hip_fail(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EDEVICE; }
 
@@ -396,30 +397,29 @@ int32_t maxwell_box(pic_box* b)
     const double tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
     hipStream_t st = b->st;
     if (b->d.frame == PIC_FRAME_SHEAR) {
-        // implicit midpoint by fixed-point sweeps; F^0 = F^n (with its own guards), every later
-        // iterate has its guards filled at t^{n+1}
+        // implicit midpoint by fixed-point sweeps from F^0 = F^n (with its own guards); every
+        // later iterate has its guards filled at t^{n+1}.  Three field sets: F^n (free once
+        // the first sweep has read it), C, and the iterates alternating with F^n's set.
         const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
-        const int sn = b->cur_set;
-        int sk = sn;
-        int so = (sn + 1) % 3;
+        const int sn = b->cur_set, sc = (sn + 1) % 3, sb2 = (sn + 2) % 3;
         const double dys1 = shear_offset(b, t1);
+        int sk = sn, so = sb2;
         for (int k = 0; k < K; k++) {
             KsbDev Kd{};
             Kd.G = b->G;
             for (int c = 0; c < 6; c++) {
-                Kd.Fn[c] = b->set[sn][c];
                 Kd.Fk[c] = b->set[sk][c];
+                Kd.C[c] = b->set[sc][c];
                 Kd.Fo[c] = b->set[so][c];
             }
             for (int c = 0; c < 3; c++) Kd.J[c] = b->J[c];
             Kd.dt = (float)dt;
             Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
             Kd.half_nx = 0.5f * (float)b->n[0];
-            if (ksb_sweep(Kd, st) != hipSuccess) return PIC_EDEVICE;
+            if (ksb_sweep(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
             if (fill_guards(b->G, b->set[so], 6, 1, dys1, st) != hipSuccess) return PIC_EDEVICE;
             sk = so;
-            so = (so + 1) % 3;
-            if (so == sn) so = (so + 1) % 3;
+            so = so == sb2 ? sn : sb2;
         }
         b->cur_set = sk;
         return PIC_OK;
@@ -571,11 +571,13 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         G.n[k] = n[k];
         G.g[k] = (k < b->dim) ? kGuard : 0;
     }
-    const int NXg = n[0] + 2 * G.g[0], NYg = n[1] + 2 * G.g[1], NZg = n[2] + 2 * G.g[2];
-    G.sy = NXg;
-    G.sz = NXg * NYg;
-    b->comp_elems = (int64_t)NXg * NYg * NZg;
-    b->origin = (int64_t)G.g[0] + (int64_t)G.sy * G.g[1] + (int64_t)G.sz * G.g[2];
+    // rows of kRowAlign floats: interior x = 0 starts a 128-byte line in every row (the x
+    // guards sit in the padding before and after the interior)
+    const int NYg = n[1] + 2 * G.g[1], NZg = n[2] + 2 * G.g[2];
+    G.sy = (kRowAlign + n[0] + G.g[0] + kRowAlign - 1) / kRowAlign * kRowAlign;
+    G.sz = G.sy * NYg;
+    b->comp_elems = (int64_t)G.sy * NYg * NZg;
+    b->origin = (int64_t)kRowAlign + (int64_t)G.sy * G.g[1] + (int64_t)G.sz * G.g[2];
     b->nsp = d->n_species;
     b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || d->frame == PIC_FRAME_LEAKY;
 

@@ -272,23 +272,71 @@ __global__ __launch_bounds__(kBlock) void yee_e_kernel(MaxwellDev M)
     M.E[2][i] = M.fout[2] * (M.fin[2] * M.E[2][i] + M.dt * cz - fp * M.J[2][i]);
 }
 
-// Shearing box, one fixed-point sweep of the implicit midpoint rule (Sec. 2.2):
-//   F_out = F^n + dt RHS((F^n + F^k)/2, J'),
+// Shearing box, fixed-point sweeps of the implicit midpoint rule (Sec. 2.2):
+//   F^{k+1} = F^n + dt RHS((F^n + F^k)/2, J'),
 // RHS of eq. OAB / eq. OAE with v = -s Omega0 x:
 //   dB/dt  = -curl E' - v dB/dy (upwind) - s Omega0 <Bx> e_y
 //   dE'/dt = curl B - 4 pi J' + (+v dEx/dy, -v dEy/dy, +v dEz/dy) (upwind)
 //            - v (dEy/dx, dEx/dx + dEz/dz, dEy/dz) (central, averaged onto the component).
+// The field part L of RHS is linear (the upwind side depends only on the sign of v at the
+// component), so with C = F^n + dt/2 L(F^n) - 4 pi dt J' (fixed during the step) every sweep is
+//   F^{k+1} = C + dt/2 L(F^k).
+// The first sweep (F^0 = F^n) also writes C.
+//
+// The stencil is written once against an accessor V(c, dx, dy, dz) of the iterate.
+enum { BX = 0, BY, BZ, EX, EY, EZ };
 
-__device__ inline float midv(const KsbDev& K, int c, int64_t i)
+template <bool D3, class Acc>
+__device__ inline void ksb_operator(const Acc& V, float v0, float vh, float sO, float L[6])
 {
-    return 0.5f * (K.Fn[c][i] + K.Fk[c][i]);
-}
-// upwind difference along y at i for transport velocity w
-__device__ inline float updy(const KsbDev& K, int c, int64_t i, int64_t sy, float w)
-{
-    return w > 0.f ? midv(K, c, i) - midv(K, c, i - sy) : midv(K, c, i + sy) - midv(K, c, i);
+    // curl E' at the B locations, curl B at the E locations
+    const float cEx = (V(EZ, 0, 1, 0) - V(EZ, 0, 0, 0)) - (D3 ? V(EY, 0, 0, 1) - V(EY, 0, 0, 0) : 0.f);
+    const float cEy = (D3 ? V(EX, 0, 0, 1) - V(EX, 0, 0, 0) : 0.f) - (V(EZ, 1, 0, 0) - V(EZ, 0, 0, 0));
+    const float cEz = (V(EY, 1, 0, 0) - V(EY, 0, 0, 0)) - (V(EX, 0, 1, 0) - V(EX, 0, 0, 0));
+    const float cBx = (V(BZ, 0, 0, 0) - V(BZ, 0, -1, 0)) - (D3 ? V(BY, 0, 0, 0) - V(BY, 0, 0, -1) : 0.f);
+    const float cBy = (D3 ? V(BX, 0, 0, 0) - V(BX, 0, 0, -1) : 0.f) - (V(BZ, 0, 0, 0) - V(BZ, -1, 0, 0));
+    const float cBz = (V(BY, 0, 0, 0) - V(BY, -1, 0, 0)) - (V(BX, 0, 0, 0) - V(BX, 0, -1, 0));
+    const float bxa = 0.25f * (V(BX, 0, 0, 0) + V(BX, 1, 0, 0) + V(BX, 0, -1, 0) + V(BX, 1, -1, 0));
+    const float dEy_dx = 0.5f * ((V(EY, 1, 0, 0) - V(EY, 0, 0, 0)) + (V(EY, 1, -1, 0) - V(EY, 0, -1, 0)));
+    const float dEx_dx = 0.5f * ((V(EX, 0, 0, 0) - V(EX, -1, 0, 0)) + (V(EX, 0, 1, 0) - V(EX, -1, 1, 0)));
+    const float dEz_dz =
+        D3 ? 0.5f * ((V(EZ, 0, 0, 0) - V(EZ, 0, 0, -1)) + (V(EZ, 0, 1, 0) - V(EZ, 0, 1, -1))) : 0.f;
+    const float dEy_dz =
+        D3 ? 0.5f * ((V(EY, 0, 0, 1) - V(EY, 0, 0, 0)) + (V(EY, 0, -1, 1) - V(EY, 0, -1, 0))) : 0.f;
+    // upwind difference along y for transport velocity w
+    auto updy = [&](int c, float w) {
+        return w > 0.f ? V(c, 0, 0, 0) - V(c, 0, -1, 0) : V(c, 0, 1, 0) - V(c, 0, 0, 0);
+    };
+    L[BX] = -cEx - v0 * updy(BX, v0);
+    L[BY] = -cEy - vh * updy(BY, vh) - sO * bxa;
+    L[BZ] = -cEz - vh * updy(BZ, vh);
+    L[EX] = cBx + vh * updy(EX, -vh) - vh * dEy_dx;
+    L[EY] = cBy - v0 * updy(EY, v0) - v0 * (dEx_dx + dEz_dz);
+    L[EZ] = cBz + v0 * updy(EZ, -v0) - v0 * dEy_dz;
 }
 
+// output of one cell: FIRST writes C and F^1 from F^n, later sweeps F^{k+1} from C
+template <bool FIRST>
+__device__ inline void ksb_store(const KsbDev& K, int64_t i, const float L[6], const float Fn[6])
+{
+    const float h = 0.5f * K.dt;
+    const float fpdt = 4.f * 3.14159265358979f * K.dt;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        float Cv;
+        if (FIRST) {
+            Cv = Fn[c] + h * L[c];
+            if (c >= EX) Cv -= fpdt * K.J[c - EX][i];
+            K.C[c][i] = Cv;
+        } else {
+            Cv = K.C[c][i];
+        }
+        K.Fo[c][i] = Cv + h * L[c];
+    }
+}
+
+// 2D (and any size): one thread per cell, neighbours straight from memory
+template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void ksb_sweep_kernel(KsbDev K)
 {
     const GridDev& G = K.G;
@@ -298,38 +346,118 @@ __global__ __launch_bounds__(kBlock) void ksb_sweep_kernel(KsbDev K)
     cell_of(G, t, x, y, z);
     const int64_t i = gidx(G, x, y, z);
     const int64_t sy = G.sy, sz = G.sz;
-    const bool d3 = G.dim == 3;
+    const float* const* F = K.Fk;
+    auto V = [&](int c, int dx, int dy, int dz) { return F[c][i + dx + sy * dy + sz * dz]; };
     const float v0 = -K.sO * ((float)x - K.half_nx);         // at x = i
     const float vh = -K.sO * ((float)x + 0.5f - K.half_nx);  // at x = i + 1/2
-    enum { BX = 0, BY, BZ, EX, EY, EZ };
-#define M(c, o) midv(K, c, i + (o))
-    // curl E' at the B locations, curl B at the E locations
-    const float cEx = (M(EZ, sy) - M(EZ, 0)) - (d3 ? M(EY, sz) - M(EY, 0) : 0.f);
-    const float cEy = (d3 ? M(EX, sz) - M(EX, 0) : 0.f) - (M(EZ, 1) - M(EZ, 0));
-    const float cEz = (M(EY, 1) - M(EY, 0)) - (M(EX, sy) - M(EX, 0));
-    const float cBx = (M(BZ, 0) - M(BZ, -sy)) - (d3 ? M(BY, 0) - M(BY, -sz) : 0.f);
-    const float cBy = (d3 ? M(BX, 0) - M(BX, -sz) : 0.f) - (M(BZ, 0) - M(BZ, -1));
-    const float cBz = (M(BY, 0) - M(BY, -1)) - (M(BX, 0) - M(BX, -sy));
-    const float bxa = 0.25f * (M(BX, 0) + M(BX, 1) + M(BX, -sy) + M(BX, 1 - sy));
-    const float dEy_dx = 0.5f * ((M(EY, 1) - M(EY, 0)) + (M(EY, 1 - sy) - M(EY, -sy)));
-    const float dEx_dx = 0.5f * ((M(EX, 0) - M(EX, -1)) + (M(EX, sy) - M(EX, sy - 1)));
-    const float dEz_dz = d3 ? 0.5f * ((M(EZ, 0) - M(EZ, -sz)) + (M(EZ, sy) - M(EZ, sy - sz))) : 0.f;
-    const float dEy_dz = d3 ? 0.5f * ((M(EY, sz) - M(EY, 0)) + (M(EY, sz - sy) - M(EY, -sy))) : 0.f;
-#undef M
-    const float fp = 4.f * 3.14159265358979f;
-    const float rBx = -cEx - v0 * updy(K, BX, i, sy, v0);
-    const float rBy = -cEy - vh * updy(K, BY, i, sy, vh) - K.sO * bxa;
-    const float rBz = -cEz - vh * updy(K, BZ, i, sy, vh);
-    const float rEx = cBx - fp * K.J[0][i] + vh * updy(K, EX, i, sy, -vh) - vh * dEy_dx;
-    const float rEy = cBy - fp * K.J[1][i] - v0 * updy(K, EY, i, sy, v0) - v0 * (dEx_dx + dEz_dz);
-    const float rEz = cBz - fp * K.J[2][i] + v0 * updy(K, EZ, i, sy, -v0) - v0 * dEy_dz;
-    const float dt = K.dt;
-    K.Fo[BX][i] = K.Fn[BX][i] + dt * rBx;
-    K.Fo[BY][i] = K.Fn[BY][i] + dt * rBy;
-    K.Fo[BZ][i] = K.Fn[BZ][i] + dt * rBz;
-    K.Fo[EX][i] = K.Fn[EX][i] + dt * rEx;
-    K.Fo[EY][i] = K.Fn[EY][i] + dt * rEy;
-    K.Fo[EZ][i] = K.Fn[EZ][i] + dt * rEz;
+    float L[6], Fn[6];
+    if (G.dim == 3)
+        ksb_operator<true>(V, v0, vh, K.sO, L);
+    else
+        ksb_operator<false>(V, v0, vh, K.sO, L);
+#pragma unroll
+    for (int c = 0; c < 6; c++) Fn[c] = F[c][i];
+    ksb_store<FIRST>(K, i, L, Fn);
+}
+
+// 3D: a workgroup owns a KX x KY column tile and marches over a chunk of KZ planes; three
+// consecutive planes of the iterate (tile plus a one-cell halo) sit in LDS.
+constexpr int KX = 32, KY = 8, KZ = 32;
+constexpr int KXH = KX + 2, KYH = KY + 2;
+
+template <bool FIRST>
+__global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
+{
+    constexpr int NT = KX * KY;
+    constexpr int PER = (KXH * KYH + NT - 1) / NT;  // plane positions per thread
+    __shared__ float P[3][6][KYH * KXH];
+    const GridDev& G = K.G;
+    const int tid = threadIdx.x, tx = tid % KX, ty = tid / KX;
+    // tiles x fastest, then y, then z chunk; each XCD takes a contiguous range so that the
+    // halos of neighbouring tiles are shared in its L2
+    const int ntx = (G.n[0] + KX - 1) / KX, nty = (G.n[1] + KY - 1) / KY;
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * KX, y0 = ((tile / ntx) % nty) * KY, z0 = (tile / (ntx * nty)) * KZ;
+    const int z1 = min(z0 + KZ, G.n[2]);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool inside = x < G.n[0] && y < G.n[1];
+    const float* const* F = K.Fk;
+    // halo positions beyond the guarded grid (ragged tiles) are never read by a valid cell
+    const int xmax = G.n[0] + G.g[0] - 1, ymax = G.n[1] + G.g[1] - 1;
+    int64_t off[PER];  // plane offset of each staged position (relative to the interior origin)
+    bool ok[PER];      // the position lies in the guarded grid
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int e = tid + j * NT;
+        const int lx = e % KXH, ly = e / KXH;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        ok[j] = e < KXH * KYH && gx <= xmax && gy <= ymax;
+        off[j] = ok[j] ? gidx(G, gx, gy, 0) : 0;
+    }
+    // register stage of one plane (loads in flight while the previous plane is computed)
+    float R[PER][6];
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int j = 0; j < PER; j++)
+#pragma unroll
+            for (int c = 0; c < 6; c++) R[j][c] = ok[j] ? F[c][off[j] + (int64_t)G.sz * z] : 0.f;
+    };
+    auto stash = [&](int slot) {
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            const int e = tid + j * NT;
+            if (e < KXH * KYH)
+#pragma unroll
+                for (int c = 0; c < 6; c++) P[slot][c][e] = R[j][c];
+        }
+    };
+    const float v0 = -K.sO * ((float)x - K.half_nx);
+    const float vh = -K.sO * ((float)x + 0.5f - K.half_nx);
+    fetch(z0 - 1);
+    stash(0);
+    fetch(z0);
+    stash(1);
+    fetch(z0 + 1);
+    int sm = 0, sc = 1, sp = 2;
+    const int c0 = (ty + 1) * KXH + (tx + 1);
+    const int64_t i0 = gidx(G, x, y, 0);
+    for (int z = z0; z < z1; z++) {
+        stash(sp);                   // plane z+1
+        if (z + 2 <= z1) fetch(z + 2);  // in flight during this plane
+        float Cv[6];
+        const int64_t i = i0 + (int64_t)G.sz * z;
+        if (!FIRST && inside)
+#pragma unroll
+            for (int c = 0; c < 6; c++) Cv[c] = K.C[c][i];
+        __syncthreads();
+        auto V = [&](int c, int dx, int dy, int dz) {
+            const int slot = dz < 0 ? sm : (dz > 0 ? sp : sc);
+            return P[slot][c][c0 + dx + KXH * dy];
+        };
+        if (inside) {
+            float L[6];
+            ksb_operator<true>(V, v0, vh, K.sO, L);
+            const float h = 0.5f * K.dt;
+            if (FIRST) {
+                const float fpdt = 4.f * 3.14159265358979f * K.dt;
+#pragma unroll
+                for (int c = 0; c < 6; c++) {
+                    float cv = P[sc][c][c0] + h * L[c];
+                    if (c >= EX) cv -= fpdt * K.J[c - EX][i];
+                    K.C[c][i] = cv;
+                    K.Fo[c][i] = cv + h * L[c];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; c++) K.Fo[c][i] = Cv[c] + h * L[c];
+            }
+        }
+        __syncthreads();
+        const int t = sm;
+        sm = sc;
+        sc = sp;
+        sp = t;
+    }
 }
 
 // ------------------------------------------------------------------ utilities
@@ -480,9 +608,22 @@ hipError_t yee_e(const MaxwellDev& M, hipStream_t st)
     yee_e_kernel<<<nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kBlock, 0, st>>>(M);
     return hipGetLastError();
 }
-hipError_t ksb_sweep(const KsbDev& K, hipStream_t st)
+hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
 {
-    ksb_sweep_kernel<<<nblocks((int64_t)K.G.n[0] * K.G.n[1] * K.G.n[2]), kBlock, 0, st>>>(K);
+    if (K.G.dim == 3) {
+        const unsigned grid = (unsigned)(((K.G.n[0] + KX - 1) / KX) * ((K.G.n[1] + KY - 1) / KY) *
+                                         ((K.G.n[2] + KZ - 1) / KZ));
+        if (first)
+            ksb_sweep3_kernel<true><<<grid, KX * KY, 0, st>>>(K);
+        else
+            ksb_sweep3_kernel<false><<<grid, KX * KY, 0, st>>>(K);
+    } else {
+        const unsigned nb = nblocks((int64_t)K.G.n[0] * K.G.n[1] * K.G.n[2]);
+        if (first)
+            ksb_sweep_kernel<true><<<nb, kBlock, 0, st>>>(K);
+        else
+            ksb_sweep_kernel<false><<<nb, kBlock, 0, st>>>(K);
+    }
     return hipGetLastError();
 }
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st)

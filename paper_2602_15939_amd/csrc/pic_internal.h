@@ -154,12 +154,13 @@ struct MaxwellDev {
     float fin[3], fout[3], gf[3];
 };
 
-// One fixed-point sweep of the shearing-box implicit midpoint rule.
+// One fixed-point sweep of the shearing-box implicit midpoint rule: Fo = C + dt/2 L(Fk); the
+// first sweep of a step (Fk = F^n) also writes C = F^n + dt/2 L(F^n) - 4 pi dt J'.
 struct KsbDev {
     GridDev G;
-    const float* Fn[6];  // Bx By Bz Ex Ey Ez at t^n
-    const float* Fk[6];  // current iterate
-    float* Fo[6];        // next iterate
+    const float* Fk[6];  // iterate, Bx By Bz Ex Ey Ez (guard cells filled)
+    float* C[6];         // constant part of the step (written by the first sweep)
+    float* Fo[6];        // next iterate (interior)
     const float* J[3];
     float dt, sO, half_nx;
 };
@@ -220,7 +221,7 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, in
                         double sO, double dt, double dys_half, hipStream_t st);
 hipError_t yee_b(const MaxwellDev& M, hipStream_t st);
 hipError_t yee_e(const MaxwellDev& M, hipStream_t st);
-hipError_t ksb_sweep(const KsbDev& K, hipStream_t st);
+hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st);
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st);
 hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense,
                          hipStream_t st);

@@ -53,32 +53,15 @@ def measured_traffic(workload: str):
 
 
 def workload_shear3d(n=256, ppc=8):
-    from paper_2602_15939_amd import synth
+    from paper_2602_15939_amd import workloads
 
-    wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.05)
-    return dict(name=f"shear3d_{n}^3_ppc{ppc}", dim=3, n=(n, n, n), ppc=ppc, theta=0.3, q=q,
-                B0=B0, shear_s=1.5, omega0=0.05 * B0, dt=0.45, maxwell_iters=8)
+    return workloads.shear3d(n, ppc)
 
 
 def make_box(w, seed, device="cuda"):
-    import torch
+    from paper_2602_15939_amd import workloads
 
-    from paper_2602_15939_amd import _lib as L
-    from paper_2602_15939_amd import synth
-    from paper_2602_15939_amd.box import Box
-
-    count = w["ppc"] * math.prod(w["n"])
-    box = Box(w["dim"], w["n"], dt=w["dt"], frame=L.FRAME_SHEAR,
-              species=[(-1.0, -w["q"], count), (1.0, w["q"], count)], shear_s=w["shear_s"],
-              shear_omega0=w["omega0"], seed=seed, maxwell_iters=w["maxwell_iters"])
-    E, B = synth.uniform_field(w["n"], 2, w["B0"])
-    box.set_fields(torch.from_numpy(E).float(), torch.from_numpy(B).float())
-    parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], seed, device=device)
-    for s, p in enumerate(parts):
-        box.set_particles(s, p["cell"], p["off"], p["u"])
-    del parts
-    torch.cuda.synchronize()
-    return box, 2 * count
+    return workloads.make_box(w, seed, device=device)
 
 
 def algorithmic_bytes(w, nparticles):

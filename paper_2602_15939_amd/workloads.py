@@ -1,0 +1,82 @@
+"""Synthetic full-size workloads shaped like the paper's setups (input recipes only; none of the
+method's arithmetic).  Code units c = 1, dx = 1; skin depth 4 cells; |q|/m = 1 per species.
+
+  shear3d   3D shearing box, 256^3 cells, 8 ppc per species, Maxwell-Juttner theta = 0.3,
+            B0 along z with sigma = 0.05, Keplerian s = 1.5, Omega0 = 0.05 omega_c, dt = 0.45
+  expand3d  3D expanding box, 128 x 128 x 512 cells, 16 ppc per species, theta = 0.05,
+            B0 along the long axis (z) with sigma = 0.05 plus random-phase transverse
+            fluctuations B = curl(psi e_z), |dB_k| ~ |k|^(-11/6) on 1 <= |n| <= 8,
+            rms dB/B0 = 0.5; l_x = l_y = 1 + adot t, adot = 1e-3 omega_p
+  leaky2d   2D leaky box, 2048^2 cells, 32 ppc per species, theta = 0.3, B0 along z with
+            sigma = 1, in-plane fluctuations with a flat spectrum on |n| <= 128 (|k| <= k_max/8),
+            rms dB/B0 = 1; probabilistic escape above gamma = 10 with t_esc = 10 L/c
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import synth
+
+
+def shear3d(n=256, ppc=8):
+    wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.05)
+    return dict(name=f"shear3d_{n}^3_ppc{ppc}", kind="shear", dim=3, n=(n, n, n), ppc=ppc,
+                theta=0.3, q=q, B0=B0, shear_s=1.5, omega0=0.05 * B0, dt=0.45, maxwell_iters=8)
+
+
+def expand3d(nxy=128, nz=512, ppc=16):
+    wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.05)
+    return dict(name=f"expand3d_{nxy}x{nxy}x{nz}_ppc{ppc}", kind="expand", dim=3, n=(nxy, nxy, nz),
+                ppc=ppc, theta=0.05, q=q, B0=B0, adot=1e-3 * wp, axis_mask=0b011, dB=0.5,
+                kmax_index=8, slope=-11.0 / 6.0, dt=0.45, maxwell_iters=8)
+
+
+def leaky2d(n=2048, ppc=32):
+    wp, q, B0 = synth.plasma_params(ppc, 4.0, 1.0)
+    return dict(name=f"leaky2d_{n}^2_ppc{ppc}", kind="leaky", dim=2, n=(n, n), ppc=ppc, theta=0.3,
+                q=q, B0=B0, dB=1.0, kmax_index=n / 16, slope=0.0, t_esc=10.0 * n, gamma_thr=10.0,
+                dt=0.45, maxwell_iters=8)
+
+
+WORKLOADS = {"shear3d": shear3d, "expand3d": expand3d, "leaky2d": leaky2d}
+
+
+def fields(w, seed):
+    """(E, B) float64 arrays (3, nz, ny, nx): E = 0, B = B0 e_z (+ fluctuations)."""
+    E, B = synth.uniform_field(w["n"], 2, w["B0"])
+    if "dB" in w:
+        B += synth.fluctuation_field(w["n"], w["dB"], w["B0"], w["kmax_index"], w["slope"], seed)
+    return E, B
+
+
+def make_box(w, seed, device="cuda", track_ids=False):
+    """The box on the GPU with its synthetic plasma; returns (box, particle count)."""
+    import torch
+
+    from . import _lib as L
+    from .box import Box
+
+    count = w["ppc"] * math.prod(w["n"])
+    species = [(-1.0, -w["q"], count), (1.0, w["q"], count)]
+    kw = dict(dt=w["dt"], species=species, seed=seed, maxwell_iters=w["maxwell_iters"],
+              track_ids=track_ids)
+    if w["kind"] == "shear":
+        box = Box(w["dim"], w["n"], frame=L.FRAME_SHEAR, shear_s=w["shear_s"],
+                  shear_omega0=w["omega0"], **kw)
+    elif w["kind"] == "expand":
+        box = Box(w["dim"], w["n"], frame=L.FRAME_EXPAND, expand_adot=w["adot"],
+                  expand_axis_mask=w["axis_mask"], **kw)
+    else:
+        box = Box(w["dim"], w["n"], frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_PROBABILISTIC,
+                  leaky_t_esc=w["t_esc"], leaky_gamma_thr=w["gamma_thr"], **kw)
+    E, B = fields(w, seed)
+    box.set_fields(torch.from_numpy(E).float(), torch.from_numpy(B).float())
+    del E, B
+    parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], seed, device=device)
+    for s, p in enumerate(parts):
+        box.set_particles(s, p["cell"], p["off"], p["u"])
+    del parts
+    torch.cuda.synchronize()
+    return box, 2 * count

@@ -51,6 +51,8 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 /* pic_shear_remap selection */
 #define PIC_REMAP_FIELDS 1u
 #define PIC_REMAP_CURRENT 2u
+/* pic_step flags */
+#define PIC_STEP_BATCHED 1u /* one launch per kernel for all boxes (box-descriptor tables) */
 /* pic_box_desc.flags */
 #define PIC_BOX_TRACK_IDS 1u /* carry particle ids through the sort (always on for LEAKY) */
 
@@ -58,6 +60,8 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell */
 #define PIC_DERR_NAN 2u      /* non-finite momentum */
 #define PIC_DERR_ORDER 4u    /* a particle outside its tile: handled on the slow path */
+#define PIC_DERR_CELL 8u     /* pic_set_particles met a cell index outside the grid */
+#define PIC_DERR_SORT 16u    /* a batched sort found a particle beyond the neighbouring tiles */
 
 typedef struct pic_box_desc {
     int32_t dim;         /* 2 or 3 */
@@ -181,7 +185,16 @@ int32_t pic_maxwell_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
    by the probabilistic escape, and the survivor count (read with pic_box_get). */
 int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags);
 
-/* One whole step: sort, fused gather-push-deposit, current fold, Maxwell, field guards. */
+/* One whole step: sort, fused gather-push-deposit, current fold, Maxwell, field guards.
+   Without flags the boxes are stepped one after another.  With PIC_STEP_BATCHED every stage
+   runs as one launch per kernel over all nb boxes (independent boxes of any frame and size,
+   sharing one stream; 2D tiles 16x16 or 8x8, 3D 8x8x8): per-box argument tables are staged in
+   pinned host memory, copied once per step, and each launch maps its workgroups to boxes
+   through a prefix table.  The sorts of a batched step use the neighbour-migration counting
+   sort only; a particle found beyond the neighbouring tiles latches PIC_DERR_SORT on its box
+   (that box's sort is then not valid).  Results equal the unbatched step's up to the order of
+   the FP32 additions of the tile-halo current.  PIC_EINVAL if the boxes do not share one
+   stream, appear twice or have an unsupported tile shape. */
 int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
 
 /* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */

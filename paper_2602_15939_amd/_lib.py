@@ -17,7 +17,8 @@ LEAKY_DISPLACEMENT, LEAKY_PROBABILISTIC = 0, 1
 FUSE_DEPOSIT = 1
 REMAP_FIELDS, REMAP_CURRENT = 1, 2
 BOX_TRACK_IDS = 1
-DERR_CFL, DERR_NAN, DERR_ORDER = 1, 2, 4
+DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT = 1, 2, 4, 8, 16
+STEP_BATCHED = 1
 
 
 class pic_box_desc(C.Structure):

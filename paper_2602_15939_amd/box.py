@@ -144,3 +144,9 @@ class Box:
 
     def info(self) -> L.pic_box_info:
         return L.pic_box_get(self.h)
+
+
+def step_many(boxes, batched=True):
+    """One whole step of several boxes sharing a stream: batched (one launch per kernel for all
+    boxes, through box-descriptor tables) or one box after another."""
+    L.pic_step([b.h for b in boxes], L.STEP_BATCHED if batched else 0)

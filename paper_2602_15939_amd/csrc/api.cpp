@@ -7,7 +7,10 @@
 
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "pic_internal.h"
@@ -70,6 +73,14 @@ struct pic_box {
     double* red_out = nullptr;
     int64_t step = 0;
     int64_t n_migrations = 0;
+    // staging of the descriptor tables of batched steps led by this box (two, alternating)
+    struct Staging {
+        void* host = nullptr;  // pinned
+        void* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t copied = nullptr;  // the last transfer out of host has completed
+    } stage[2];
+    int stage_cur = 0;
     bool sorted = false;
     bool deposit_pending = false;
     bool track_ids = false;
@@ -469,6 +480,385 @@ int32_t maxwell_box(pic_box* b)
     return PIC_OK;
 }
 
+// ---------------------------------------------------------------- batched step
+// pic_step over many boxes: every stage of the step (sort, current zeroing, push, fold, Maxwell,
+// guard fill) is one launch per kernel for all boxes, driven by tables of per-box arguments.
+// The tables of a whole step are staged on the host, copied to the device in one transfer and
+// then launched stage by stage on the shared stream.
+struct BatchPlan {
+    hipStream_t st = nullptr;
+    std::vector<char> buf;
+    std::vector<std::function<hipError_t(const char*)>> launches;
+
+    size_t put(const void* p, size_t bytes)
+    {
+        const size_t off = (buf.size() + 255) & ~(size_t)255;
+        buf.resize(off + bytes);
+        std::memcpy(buf.data() + off, p, bytes);
+        return off;
+    }
+    // one table + prefix; returns false if the stage has no blocks
+    template <class Args>
+    bool stage(const std::vector<Args>& a, const std::vector<uint32_t>& blocks, size_t& to,
+               size_t& po, int& total)
+    {
+        if (a.empty()) return false;
+        std::vector<uint32_t> prefix(a.size() + 1, 0);
+        for (size_t i = 0; i < a.size(); i++) prefix[i + 1] = prefix[i] + blocks[i];
+        if (prefix.back() == 0) return false;
+        to = put(a.data(), sizeof(Args) * a.size());
+        po = put(prefix.data(), sizeof(uint32_t) * prefix.size());
+        total = (int)prefix.back();
+        return true;
+    }
+    template <class Args>
+    void grid(GridBatchKind k, const std::vector<Args>& a, const std::vector<uint32_t>& blocks, int ydim)
+    {
+        size_t to, po;
+        int total;
+        if (!stage(a, blocks, to, po, total)) return;
+        const int nu = (int)a.size();
+        hipStream_t s = st;
+        launches.push_back([=](const char* d) {
+            return grid_batch(k, d + to, UnitMap{reinterpret_cast<const uint32_t*>(d + po), nu}, total,
+                              ydim, s);
+        });
+    }
+    template <class Args>
+    void sort(SortBatchKind k, const std::vector<Args>& a, const std::vector<uint32_t>& blocks)
+    {
+        size_t to, po;
+        int total;
+        if (!stage(a, blocks, to, po, total)) return;
+        const int nu = (int)a.size();
+        hipStream_t s = st;
+        launches.push_back([=](const char* d) {
+            return sort_batch(k, d + to, UnitMap{reinterpret_cast<const uint32_t*>(d + po), nu}, total, s);
+        });
+    }
+    void push(const std::vector<StepDev>& a, const std::vector<uint32_t>& blocks, int dim,
+              const int tile[3], int frame)
+    {
+        size_t to, po;
+        int total;
+        if (!stage(a, blocks, to, po, total)) return;
+        const int nu = (int)a.size();
+        const int t[3] = {tile[0], tile[1], tile[2]};
+        hipStream_t s = st;
+        launches.push_back([=](const char* d) {
+            return launch_gather_push_batch(reinterpret_cast<const StepDev*>(d + to),
+                                            UnitMap{reinterpret_cast<const uint32_t*>(d + po), nu},
+                                            total, dim, t, frame, s);
+        });
+    }
+};
+
+// guard fill of ncomp arrays as batched units (one per slab kind)
+void plan_fill(std::vector<FillArgs>& a, std::vector<uint32_t>& blk, const GridDev& G,
+               float* const* comps, int ncomp, int shear, double dys)
+{
+    Comp6 A{};
+    for (int c = 0; c < ncomp; c++) A.p[c] = comps[c];
+    const double fl = std::floor(dys);
+    const int di = (int)fl;
+    const float w = (float)(dys - fl);
+    const int NYg = G.n[1] + 2 * G.g[1], NZg = G.n[2] + 2 * G.g[2];
+    a.push_back(FillArgs{G, A, 0, shear, di, w});
+    blk.push_back(grid_blocks((int64_t)2 * G.g[0] * NYg * NZg));
+    a.push_back(FillArgs{G, A, 1, shear, di, w});
+    blk.push_back(grid_blocks((int64_t)G.n[0] * 2 * G.g[1] * NZg));
+    if (G.g[2] > 0) {
+        a.push_back(FillArgs{G, A, 2, shear, di, w});
+        blk.push_back(grid_blocks((int64_t)G.n[0] * G.n[1] * 2 * G.g[2]));
+    }
+}
+
+int32_t step_batched(pic_box* const* boxes, int nb)
+{
+    hipStream_t st = boxes[0]->st;
+    for (int i = 0; i < nb; i++) {
+        pic_box* b = boxes[i];
+        if (b->st != st || b->deposit_pending) return b->st != st ? PIC_EINVAL : PIC_ESTATE;
+        if (!batch_tile_supported(b->dim, b->tile)) return PIC_EINVAL;
+        for (int j = 0; j < i; j++)
+            if (boxes[j] == b) return PIC_EINVAL;
+    }
+    BatchPlan plan;
+    plan.st = st;
+
+    // ---- a1: tile sort (migration sort in the batch; radix per box where it does not apply)
+    {
+        std::vector<ZeroArgs> zf;
+        std::vector<uint32_t> zfb;
+        std::vector<MigCountArgs> mc;
+        std::vector<MigOffArgs> mo;
+        std::vector<ScanArgs> sc;
+        std::vector<MigScatterArgs> ms;
+        std::vector<uint32_t> mcb, mob, scb, msb;
+        std::vector<int> radix_boxes;
+        for (int i = 0; i < nb; i++) {
+            pic_box* b = boxes[i];
+            bool all_grouped = b->mig_ok;
+            for (int s = 0; s < b->nsp; s++) all_grouped = all_grouped && b->sp[s].grouped;
+            if (!all_grouped) {
+                radix_boxes.push_back(i);
+                continue;
+            }
+            const int nt = b->tl.n_tiles;
+            for (int s = 0; s < b->nsp; s++) {
+                Species& S = b->sp[s];
+                const int nxt = S.toff_cur ^ 1;
+                const Gate g{S.sb.fallback, 0};
+                S.which = sort_result_buffer(b->tl);
+                zf.push_back(ZeroArgs{reinterpret_cast<uint32_t*>(S.sb.fallback), 1});
+                zfb.push_back(1);
+                mc.push_back(MigCountArgs{S.cell[S.cur], S.toff[S.toff_cur], b->cc, b->mg, S.sb.mcnt,
+                                          S.sb.fallback, b->err});
+                mcb.push_back((uint32_t)nt);
+                mo.push_back(MigOffArgs{S.sb.mcnt, b->mg, S.sb.mpre, S.sb.tot, S.sb.dcnt, g});
+                mob.push_back((uint32_t)((nt + kBlock / 64 - 1) / (kBlock / 64)));
+                sc.push_back(ScanArgs{S.sb.tot, S.sb.start, nt + 1, g});
+                scb.push_back(1);
+                sc.push_back(ScanArgs{S.sb.dcnt, S.sb.dpre, nt + 1, g});
+                scb.push_back(1);
+                ms.push_back(MigScatterArgs{S.cell[S.cur], S.toff[S.toff_cur], S.n_upper, b->cc, b->mg,
+                                            S.sb.mpre, S.sb.start, S.sb.dpre, S.sb.vals[S.which],
+                                            S.toff[nxt], S.n_live, g});
+                msb.push_back((uint32_t)(nt + 1));
+                S.toff_cur = nxt;
+                S.grouped = false;
+                b->n_migrations++;
+            }
+            b->sorted = true;
+        }
+        // boxes the migration sort does not apply to are sorted now, on their own launches,
+        // ahead of the batch on the shared stream
+        for (int i : radix_boxes)
+            if (sort_box(boxes[i])) return PIC_EDEVICE;
+        plan.grid(kBatchZero, zf, zfb, 1);
+        plan.sort(kBatchMigCount, mc, mcb);
+        plan.sort(kBatchMigOffsets, mo, mob);
+        plan.sort(kBatchScan, sc, scb);
+        plan.sort(kBatchMigScatter, ms, msb);
+    }
+
+    // ---- current zeroing and the fused push (a2-a6, a8)
+    {
+        std::vector<ZeroArgs> z;
+        std::vector<uint32_t> zb;
+        std::map<std::tuple<int, int, int, int, int>, std::pair<std::vector<StepDev>, std::vector<uint32_t>>> groups;
+        for (int i = 0; i < nb; i++) {
+            pic_box* b = boxes[i];
+            for (int c = 0; c < 3; c++) {
+                z.push_back(ZeroArgs{reinterpret_cast<uint32_t*>(b->J[c] - b->origin), b->comp_elems});
+                zb.push_back(grid_blocks(b->comp_elems));
+            }
+            auto& gr = groups[std::make_tuple(b->dim, b->tile[0], b->tile[1], b->tile[2], b->d.frame)];
+            StepDev P = make_step(b);
+            gr.first.push_back(P);
+            gr.second.push_back((uint32_t)b->tl.n_tiles);
+            set_migration_shift(b, P.dys_int);
+            for (int s = 0; s < b->nsp; s++) {
+                b->sp[s].cur ^= 1;
+                b->sp[s].grouped = true;
+            }
+            b->sorted = false;
+        }
+        plan.grid(kBatchZero, z, zb, 1);
+        for (auto& kv : groups) {
+            const int tile[3] = {std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first)};
+            plan.push(kv.second.first, kv.second.second, std::get<0>(kv.first), tile, std::get<4>(kv.first));
+        }
+    }
+
+    // ---- a7: current fold (z, y periodic; J' transport and shearing-periodic x, or periodic x)
+    {
+        std::vector<FoldPArgs> fz, fy;
+        std::vector<AdvArgs> adv;
+        std::vector<FoldXArgs> fx;
+        std::vector<uint32_t> fzb, fyb, advb, fxb;
+        for (int i = 0; i < nb; i++) {
+            pic_box* b = boxes[i];
+            const GridDev& G = b->G;
+            const Comp3 Jc{{b->J[0], b->J[1], b->J[2]}};
+            const int NXg = G.n[0] + 2 * G.g[0], NYg = G.n[1] + 2 * G.g[1];
+            if (G.g[2] > 0) {
+                const int nl = G.n[2] < 2 * G.g[2] ? G.n[2] : 2 * G.g[2];
+                fz.push_back(FoldPArgs{G, Jc, 2});
+                fzb.push_back(grid_blocks((int64_t)NXg * NYg * nl));
+            }
+            const int nly = G.n[1] < 2 * G.g[1] ? G.n[1] : 2 * G.g[1];
+            fy.push_back(FoldPArgs{G, Jc, 1});
+            fyb.push_back(grid_blocks((int64_t)NXg * nly * G.n[2]));
+            const double th = time_of(b, b->step) + 0.5 * b->d.dt;
+            if (b->d.frame == PIC_FRAME_SHEAR) {
+                const double dh = shear_offset(b, th), fl = std::floor(dh);
+                const Comp3 Tc{{b->Jt[0], b->Jt[1], b->Jt[2]}};
+                adv.push_back(AdvArgs{G, Jc, Tc, (float)(b->d.shear_s * b->d.shear_omega0 * b->d.dt / 2.0),
+                                      0.5f * G.n[0]});
+                advb.push_back(grid_blocks((int64_t)NXg * G.n[1] * G.n[2]));
+                fx.push_back(FoldXArgs{G, Tc, Jc, 1, 1, (int)fl, (float)(dh - fl)});
+                fxb.push_back(grid_blocks((int64_t)G.n[0] * G.n[1] * G.n[2]));
+            } else {
+                const int nlx = G.n[0] < 2 * G.g[0] ? G.n[0] : 2 * G.g[0];
+                fx.push_back(FoldXArgs{G, Jc, Jc, 0, 0, 0, 0.f});
+                fxb.push_back(grid_blocks((int64_t)nlx * G.n[1] * G.n[2]));
+            }
+        }
+        plan.grid(kBatchFoldP, fz, fzb, 3);
+        plan.grid(kBatchFoldP, fy, fyb, 3);
+        plan.grid(kBatchAdvect, adv, advb, 3);
+        plan.grid(kBatchFoldX, fx, fxb, 3);
+    }
+
+    // ---- a9: Maxwell (Yee with the expanding-box factors; shearing-box fixed-point sweeps)
+    {
+        std::vector<MaxwellDev> yb1, ye, yb2;
+        std::vector<uint32_t> yb1b, yeb, yb2b;
+        std::vector<FillArgs> fb1, fe, fb2, fend;
+        std::vector<uint32_t> fb1b, feb, fb2b, fendb;
+        int kmax = 0;
+        for (int i = 0; i < nb; i++) {
+            pic_box* b = boxes[i];
+            if (b->d.frame == PIC_FRAME_SHEAR) {
+                kmax = std::max(kmax, b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8);
+                continue;
+            }
+            const double dt = b->d.dt, tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
+            double ln[3], lh[3], l1[3];
+            for (int k = 0; k < 3; k++) {
+                ln[k] = scale_of(b, k, tn);
+                lh[k] = scale_of(b, k, th);
+                l1[k] = scale_of(b, k, t1);
+            }
+            const double elln = ln[0] * ln[1] * ln[2], ellh = lh[0] * lh[1] * lh[2],
+                         ell1 = l1[0] * l1[1] * l1[2];
+            MaxwellDev M{};
+            M.G = b->G;
+            for (int c = 0; c < 3; c++) {
+                M.E[c] = b->E(c);
+                M.B[c] = b->B(c);
+                M.J[c] = b->J[c];
+            }
+            M.dt = (float)dt;
+            const uint32_t nbk = grid_blocks((int64_t)b->n[0] * b->n[1] * b->n[2]);
+            float* Bp[3] = {b->B(0), b->B(1), b->B(2)};
+            float* Ep[3] = {b->E(0), b->E(1), b->E(2)};
+            for (int c = 0; c < 3; c++) {
+                M.fin[c] = (float)(elln / ln[c]);
+                M.fout[c] = (float)(lh[c] / ellh);
+                M.gf[c] = (float)ln[c];
+            }
+            yb1.push_back(M);
+            yb1b.push_back(nbk);
+            plan_fill(fb1, fb1b, b->G, Bp, 3, 0, 0.0);
+            for (int c = 0; c < 3; c++) {
+                M.fin[c] = (float)(elln / ln[c]);
+                M.fout[c] = (float)(l1[c] / ell1);
+                M.gf[c] = (float)lh[c];
+            }
+            ye.push_back(M);
+            yeb.push_back(nbk);
+            plan_fill(fe, feb, b->G, Ep, 3, 0, 0.0);
+            for (int c = 0; c < 3; c++) {
+                M.fin[c] = (float)(ellh / lh[c]);
+                M.fout[c] = (float)(l1[c] / ell1);
+                M.gf[c] = (float)l1[c];
+            }
+            yb2.push_back(M);
+            yb2b.push_back(nbk);
+            plan_fill(fb2, fb2b, b->G, Bp, 3, 0, 0.0);
+        }
+        plan.grid(kBatchYeeB, yb1, yb1b, 1);
+        plan.grid(kBatchFill, fb1, fb1b, 3);
+        plan.grid(kBatchYeeE, ye, yeb, 1);
+        plan.grid(kBatchFill, fe, feb, 3);
+        plan.grid(kBatchYeeB, yb2, yb2b, 1);
+        plan.grid(kBatchFill, fb2, fb2b, 3);
+        // shearing boxes: sweep k of every box with at least k+1 sweeps in one launch
+        struct Rot {
+            int sn, sc, sb2, sk, so;
+        };
+        std::vector<Rot> rot(nb);
+        for (int i = 0; i < nb; i++) {
+            pic_box* b = boxes[i];
+            const int sn = b->cur_set;
+            rot[i] = Rot{sn, (sn + 1) % 3, (sn + 2) % 3, sn, (sn + 2) % 3};
+        }
+        for (int k = 0; k < kmax; k++) {
+            std::vector<KsbDev> ks;
+            std::vector<uint32_t> ksb;
+            std::vector<FillArgs> kf;
+            std::vector<uint32_t> kfb;
+            for (int i = 0; i < nb; i++) {
+                pic_box* b = boxes[i];
+                if (b->d.frame != PIC_FRAME_SHEAR) continue;
+                const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
+                if (k >= K) continue;
+                Rot& r = rot[i];
+                KsbDev Kd{};
+                Kd.G = b->G;
+                for (int c = 0; c < 6; c++) {
+                    Kd.Fk[c] = b->set[r.sk][c];
+                    Kd.C[c] = b->set[r.sc][c];
+                    Kd.Fo[c] = b->set[r.so][c];
+                }
+                for (int c = 0; c < 3; c++) Kd.J[c] = b->J[c];
+                Kd.dt = (float)b->d.dt;
+                Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
+                Kd.half_nx = 0.5f * (float)b->n[0];
+                ks.push_back(Kd);
+                ksb.push_back(grid_blocks((int64_t)b->n[0] * b->n[1] * b->n[2]));
+                const double t1 = time_of(b, b->step) + b->d.dt;
+                plan_fill(kf, kfb, b->G, b->set[r.so], 6, 1, shear_offset(b, t1));
+                r.sk = r.so;
+                r.so = r.so == r.sb2 ? r.sn : r.sb2;
+                if (k == K - 1) b->cur_set = r.sk;
+            }
+            plan.grid(k == 0 ? kBatchKsbFirst : kBatchKsbNext, ks, ksb, 1);
+            plan.grid(kBatchFill, kf, kfb, 6);
+        }
+        // time advance; guard cells of the non-shear fields at t^{n+1}
+        for (int i = 0; i < nb; i++) {
+            pic_box* b = boxes[i];
+            b->step += 1;
+            if (b->d.frame != PIC_FRAME_SHEAR) plan_fill(fend, fendb, b->G, field_ptrs(b), 6, 0, 0.0);
+        }
+        plan.grid(kBatchFill, fend, fendb, 6);
+    }
+
+    // ---- stage the tables, one transfer, then the launches in order
+    pic_box* b0 = boxes[0];
+    auto& sg = b0->stage[b0->stage_cur];
+    b0->stage_cur ^= 1;
+    const size_t bytes = plan.buf.size();
+    if (bytes > sg.cap) {
+        if (sg.copied && hipEventSynchronize(sg.copied) != hipSuccess) return PIC_EDEVICE;
+        if (hipStreamSynchronize(st) != hipSuccess) return PIC_EDEVICE;  // the old tables may be in use
+        if (sg.host) hipHostFree(sg.host);
+        if (sg.dev) hipFree(sg.dev);
+        sg.host = sg.dev = nullptr;
+        sg.cap = 0;
+        const size_t cap = std::max(bytes * 2, (size_t)1 << 20);
+        if (hipHostMalloc(&sg.host, cap) != hipSuccess) return PIC_ENOMEM;
+        if (hipMalloc(&sg.dev, cap) != hipSuccess) return PIC_ENOMEM;
+        sg.cap = cap;
+        if (!sg.copied && hipEventCreateWithFlags(&sg.copied, hipEventDisableTiming) != hipSuccess)
+            return PIC_EDEVICE;
+    } else if (sg.copied && hipEventSynchronize(sg.copied) != hipSuccess) {
+        return PIC_EDEVICE;
+    }
+    if (bytes) {
+        std::memcpy(sg.host, plan.buf.data(), bytes);
+        if (hipMemcpyAsync(sg.dev, sg.host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return PIC_EDEVICE;
+        if (hipEventRecord(sg.copied, st) != hipSuccess) return PIC_EDEVICE;
+    }
+    const char* dev = static_cast<const char*>(sg.dev);
+    for (auto& f : plan.launches)
+        if (f(dev) != hipSuccess) return PIC_EDEVICE;
+    return PIC_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -500,6 +890,11 @@ int32_t pic_box_destroy(pic_box* b)
 {
     if (!b) return PIC_OK;
     hipStreamSynchronize(b->st);
+    for (auto& sg : b->stage) {
+        if (sg.host) hipHostFree(sg.host);
+        if (sg.dev) hipFree(sg.dev);
+        if (sg.copied) hipEventDestroy(sg.copied);
+    }
     for (void* p : b->allocs) hipFree(p);
     delete b;
     return PIC_OK;
@@ -827,9 +1222,10 @@ int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags)
     return pic_tile_sort(boxes, nb, flags);
 }
 
-int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t)
+int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
 {
     int32_t r = check_boxes(boxes, nb);
+    if (!r && (flags & PIC_STEP_BATCHED)) return step_batched(boxes, nb);
     for (int i = 0; i < nb && !r; i++) {
         pic_box* b = boxes[i];
         r = sort_box(b);

@@ -341,14 +341,15 @@ __device__ inline float fixed_to_float(unsigned long long a, float unit)
 }
 
 template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
-__global__ __launch_bounds__(NT) void gpd_kernel(StepDev P, int fuse)
+__device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P, int blk, int nblk,
+                                                                int fuse)
 {
     using G = Geo<DIM, TX, TY, TZ>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[G::LDS_BYTES];
     float* const F = reinterpret_cast<float*>(lds);                                   // E, B
     unsigned long long* const Jl = reinterpret_cast<unsigned long long*>(lds + 6 * G::FS * 4);  // J
 
-    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int tile = xcd_contiguous(blk, nblk);
     int t0[3], ext[3];
     tile_origin<DIM>(P, tile, t0, ext);
     const int tid = threadIdx.x;
@@ -553,6 +554,21 @@ __global__ __launch_bounds__(NT) void gpd_kernel(StepDev P, int fuse)
     }
 }
 
+template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
+__global__ __launch_bounds__(NT) void gpd_kernel(StepDev P, int fuse)
+{
+    gpd_body<DIM, TX, TY, TZ, FRAME, NT>(P, (int)blockIdx.x, (int)gridDim.x, fuse);
+}
+
+// Many boxes in one launch: the blocks of unit u (one box's tiles) take its descriptor.
+template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
+__global__ __launch_bounds__(NT) void gpd_batch(const StepDev* __restrict__ t, UnitMap m)
+{
+    const int u = unit_of(m, (int)blockIdx.x);
+    gpd_body<DIM, TX, TY, TZ, FRAME, NT>(t[u], (int)blockIdx.x - (int)m.prefix[u],
+                                         (int)(m.prefix[u + 1] - m.prefix[u]), 1);
+}
+
 // Unfused deposit: the same Esirkepov tile accumulation from the positions and deposit
 // displacements saved by an unfused push (in sorted slot order).
 template <int DIM, int TX, int TY, int TZ, int NT>
@@ -653,6 +669,35 @@ bool tile_shape_supported(int dim, const int t[3])
     if (dim == 3) return (t[0] == 8 && t[1] == 8 && t[2] == 8) || (t[0] == 4 && t[1] == 4 && t[2] == 4);
     return t[2] == 1 && ((t[0] == 16 && t[1] == 16) || (t[0] == 32 && t[1] == 32) ||
                          (t[0] == 8 && t[1] == 8) || (t[0] == 32 && t[1] == 16));
+}
+
+template <int DIM, int TX, int TY, int TZ>
+static hipError_t launch_batch_shape(const StepDev* table, UnitMap m, int blocks, int frame,
+                                     hipStream_t st)
+{
+    constexpr int NT = threads_for<DIM>();
+    switch (frame) {
+    case kShear: gpd_batch<DIM, TX, TY, TZ, kShear, NT><<<blocks, NT, 0, st>>>(table, m); break;
+    case kExpand: gpd_batch<DIM, TX, TY, TZ, kExpand, NT><<<blocks, NT, 0, st>>>(table, m); break;
+    case kLeaky: gpd_batch<DIM, TX, TY, TZ, kLeaky, NT><<<blocks, NT, 0, st>>>(table, m); break;
+    default: gpd_batch<DIM, TX, TY, TZ, kPlain, NT><<<blocks, NT, 0, st>>>(table, m); break;
+    }
+    return hipGetLastError();
+}
+
+bool batch_tile_supported(int dim, const int t[3])
+{
+    if (dim == 3) return t[0] == 8 && t[1] == 8 && t[2] == 8;
+    return t[2] == 1 && ((t[0] == 16 && t[1] == 16) || (t[0] == 8 && t[1] == 8));
+}
+
+hipError_t launch_gather_push_batch(const StepDev* table, UnitMap m, int blocks, int dim,
+                                    const int t[3], int frame, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    if (dim == 3) return launch_batch_shape<3, 8, 8, 8>(table, m, blocks, frame, st);
+    if (t[0] == 16) return launch_batch_shape<2, 16, 16, 1>(table, m, blocks, frame, st);
+    return launch_batch_shape<2, 8, 8, 1>(table, m, blocks, frame, st);
 }
 
 hipError_t launch_gather_push(const StepDev& P, const int t[3], int fuse, hipStream_t st)

@@ -24,16 +24,14 @@ __device__ inline int wrapn(int i, int n)
 // Every guard cell takes its value from interior cells: y, z periodic; x periodic, or for the
 // shearing box F(x_o + m, y) = F(x_i + m, y + dys) and F(x_i - m, y) = F(x_o - m, y - dys)
 // with a fractional dys applied by linear interpolation along y.
-struct Comp6 {
-    float* p[6];
-};
 
-__global__ __launch_bounds__(kBlock) void fill_guards_kernel(GridDev G, Comp6 A, int slab,
-                                                             int shear, int dys_int, float dys_w)
+__device__ __attribute__((always_inline)) inline void fill_guards_body(const FillArgs& a, int blk, int, int c)
 {
-    const int c = blockIdx.y;
-    float* F = A.p[c];
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const GridDev& G = a.G;
+    const int slab = a.slab, shear = a.shear, dys_int = a.dys_int;
+    const float dys_w = a.dys_w;
+    float* F = a.A.p[c];
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
     const int NYg = G.n[1] + 2 * gy, NZg = G.n[2] + 2 * gz;
     int x, y, z;
@@ -89,18 +87,18 @@ __global__ __launch_bounds__(kBlock) void fill_guards_kernel(GridDev G, Comp6 A,
     }
     F[gidx(G, x, y, z)] = v;
 }
+PIC_BATCHED_KERNEL(fill_guards, FillArgs, kBlock)
 
 // ------------------------------------------------------------------ current fold
-struct Comp3 {
-    float* p[3];
-};
 
 // Periodic fold along axis a (1 = y, 2 = z) over the whole guarded extent of the axes before
 // it (x and, for z, y) and the interior of the others.
-__global__ __launch_bounds__(kBlock) void fold_periodic_kernel(GridDev G, Comp3 J, int a)
+__device__ __attribute__((always_inline)) inline void fold_periodic_body(const FoldPArgs& args, int blk, int, int c)
 {
-    float* F = J.p[blockIdx.y];
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const GridDev& G = args.G;
+    const int a = args.axis;
+    float* F = args.J.p[c];
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     const int gx = G.g[0], gy = G.g[1];
     const int NXg = G.n[0] + 2 * gx, NYg = G.n[1] + 2 * gy;
     const int na = G.n[a], ga = G.g[a];
@@ -132,14 +130,17 @@ __global__ __launch_bounds__(kBlock) void fold_periodic_kernel(GridDev G, Comp3 
     if (i >= na - ga) v += F[self - (int64_t)na * (a == 2 ? G.sz : G.sy)];
     F[self] += v;
 }
+PIC_BATCHED_KERNEL(fold_periodic, FoldPArgs, kBlock)
 
 // J' transport along y by d = v_{s,y}(x) dt/2, v_{s,y} = -s Omega0 x at each component's x
 // (Sec. 2.2), as J(y - d) by linear interpolation, over the guarded x range; out = in moved.
-__global__ __launch_bounds__(kBlock) void shear_advect_kernel(GridDev G, Comp3 Jin, Comp3 Jout,
-                                                              float sO_hdt, float half_nx)
+__device__ __attribute__((always_inline)) inline void shear_advect_body(const AdvArgs& a, int blk, int, int c)
 {
-    const int c = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const GridDev& G = a.G;
+    const Comp3& Jin = a.in;
+    const Comp3& Jout = a.out;
+    const float sO_hdt = a.sO_hdt, half_nx = a.half_nx;
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     const int gx = G.g[0];
     const int NXg = G.n[0] + 2 * gx;
     const int64_t tot = (int64_t)NXg * G.n[1] * G.n[2];
@@ -154,20 +155,23 @@ __global__ __launch_bounds__(kBlock) void shear_advect_kernel(GridDev G, Comp3 J
     const int m = (int)fl;
     const float w = d - fl;
     const float* F = Jin.p[c];
-    const float a = F[gidx(G, x, wrapn(y - m, G.n[1]), z)];
-    const float b = F[gidx(G, x, wrapn(y - m - 1, G.n[1]), z)];
-    Jout.p[c][gidx(G, x, y, z)] = (1.f - w) * a + w * b;
+    const float fa = F[gidx(G, x, wrapn(y - m, G.n[1]), z)];
+    const float fb = F[gidx(G, x, wrapn(y - m - 1, G.n[1]), z)];
+    Jout.p[c][gidx(G, x, y, z)] = (1.f - w) * fa + w * fb;
 }
+PIC_BATCHED_KERNEL(shear_advect, AdvArgs, kBlock)
 
 // x fold as a gather into interior cells: out(i) = in(i) plus the x guard columns that map
 // to i (periodic, or shearing-periodic at dys as the transpose of the guard interpolation).
 // Runs over all interior cells when in != out, else over the boundary layers only.
-__global__ __launch_bounds__(kBlock) void fold_x_kernel(GridDev G, Comp3 Jin, Comp3 Jout,
-                                                        int all, int shear, int dys_int,
-                                                        float dys_w)
+__device__ __attribute__((always_inline)) inline void fold_x_body(const FoldXArgs& a, int blk, int, int c)
 {
-    const int c = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const GridDev& G = a.G;
+    const Comp3& Jin = a.in;
+    const Comp3& Jout = a.out;
+    const int all = a.all, shear = a.shear, dys_int = a.dys_int;
+    const float dys_w = a.dys_w;
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     const int nx = G.n[0], ga = G.g[0];
     const int nl = all ? nx : (nx < 2 * ga ? nx : 2 * ga);
     const int64_t tot = (int64_t)nl * G.n[1] * G.n[2];
@@ -211,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void fold_x_kernel(GridDev G, Comp3 Jin, Co
     }
     Jout.p[c][gidx(G, x, y, z)] = v;
 }
+PIC_BATCHED_KERNEL(fold_x, FoldXArgs, kBlock)
 
 // ------------------------------------------------------------------ Maxwell
 // Yee curls (c = 1, dx = 1).  E_j and B_j enter multiplied by ge[j], gb[j] (the l_j of the
@@ -225,10 +230,10 @@ __device__ inline void cell_of(const GridDev& G, int64_t t, int& x, int& y, int&
 }
 
 // B_i <- fout_i (fin_i B_i - dt/2 curl(g E)_i)
-__global__ __launch_bounds__(kBlock) void yee_b_kernel(MaxwellDev M)
+__device__ __attribute__((always_inline)) inline void yee_b_body(const MaxwellDev& M, int blk, int, int)
 {
     const GridDev& G = M.G;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
     int x, y, z;
     cell_of(G, t, x, y, z);
@@ -247,12 +252,13 @@ __global__ __launch_bounds__(kBlock) void yee_b_kernel(MaxwellDev M)
     M.B[1][i] = M.fout[1] * (M.fin[1] * M.B[1][i] - h * cy);
     M.B[2][i] = M.fout[2] * (M.fin[2] * M.B[2][i] - h * cz);
 }
+PIC_BATCHED_KERNEL(yee_b, MaxwellDev, kBlock)
 
 // E_i <- fout_i (fin_i E_i + dt curl(g B)_i - 4 pi dt J_i)
-__global__ __launch_bounds__(kBlock) void yee_e_kernel(MaxwellDev M)
+__device__ __attribute__((always_inline)) inline void yee_e_body(const MaxwellDev& M, int blk, int, int)
 {
     const GridDev& G = M.G;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
     int x, y, z;
     cell_of(G, t, x, y, z);
@@ -271,6 +277,7 @@ __global__ __launch_bounds__(kBlock) void yee_e_kernel(MaxwellDev M)
     M.E[1][i] = M.fout[1] * (M.fin[1] * M.E[1][i] + M.dt * cy - fp * M.J[1][i]);
     M.E[2][i] = M.fout[2] * (M.fin[2] * M.E[2][i] + M.dt * cz - fp * M.J[2][i]);
 }
+PIC_BATCHED_KERNEL(yee_e, MaxwellDev, kBlock)
 
 // Shearing box, fixed-point sweeps of the implicit midpoint rule (Sec. 2.2):
 //   F^{k+1} = F^n + dt RHS((F^n + F^k)/2, J'),
@@ -337,10 +344,10 @@ __device__ inline void ksb_store(const KsbDev& K, int64_t i, const float L[6], c
 
 // 2D (and any size): one thread per cell, neighbours straight from memory
 template <bool FIRST>
-__global__ __launch_bounds__(kBlock) void ksb_sweep_kernel(KsbDev K)
+__device__ __attribute__((always_inline)) inline void ksb_sweep_body(const KsbDev& K, int blk, int, int)
 {
     const GridDev& G = K.G;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
     int x, y, z;
     cell_of(G, t, x, y, z);
@@ -359,6 +366,10 @@ __global__ __launch_bounds__(kBlock) void ksb_sweep_kernel(KsbDev K)
     for (int c = 0; c < 6; c++) Fn[c] = F[c][i];
     ksb_store<FIRST>(K, i, L, Fn);
 }
+__device__ __attribute__((always_inline)) inline void ksb_first_body(const KsbDev& K, int blk, int n, int y) { ksb_sweep_body<true>(K, blk, n, y); }
+__device__ __attribute__((always_inline)) inline void ksb_next_body(const KsbDev& K, int blk, int n, int y) { ksb_sweep_body<false>(K, blk, n, y); }
+PIC_BATCHED_KERNEL(ksb_first, KsbDev, kBlock)
+PIC_BATCHED_KERNEL(ksb_next, KsbDev, kBlock)
 
 // 3D: a workgroup owns a KX x KY column tile and marches over a chunk of KZ planes; three
 // consecutive planes of the iterate (tile plus a one-cell halo) sit in LDS.
@@ -461,11 +472,12 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
 }
 
 // ------------------------------------------------------------------ utilities
-__global__ __launch_bounds__(kBlock) void zero_kernel(float* p, int64_t n)
+__device__ __attribute__((always_inline)) inline void zero_body(const ZeroArgs& a, int blk, int, int)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) p[i] = 0.f;
+    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
+    if (i < a.n) a.p[i] = 0u;
 }
+PIC_BATCHED_KERNEL(zero, ZeroArgs, kBlock)
 
 // interior <-> dense copies: dense index x + n0*(y + n1*z)
 __global__ __launch_bounds__(kBlock) void interior_copy_kernel(GridDev G, float* guarded,
@@ -557,12 +569,12 @@ hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int she
     const float w = (float)(dys - fl);
     const int NYg = G.n[1] + 2 * G.g[1], NZg = G.n[2] + 2 * G.g[2];
     fill_guards_kernel<<<dim3(nblocks((int64_t)2 * G.g[0] * NYg * NZg), ncomp), kBlock, 0, st>>>(
-        G, A, 0, shear, di, w);
+        FillArgs{G, A, 0, shear, di, w});
     fill_guards_kernel<<<dim3(nblocks((int64_t)G.n[0] * 2 * G.g[1] * NZg), ncomp), kBlock, 0, st>>>(
-        G, A, 1, shear, di, w);
+        FillArgs{G, A, 1, shear, di, w});
     if (G.g[2] > 0)
         fill_guards_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * 2 * G.g[2]), ncomp), kBlock, 0,
-                             st>>>(G, A, 2, shear, di, w);
+                             st>>>(FillArgs{G, A, 2, shear, di, w});
     return hipGetLastError();
 }
 
@@ -575,11 +587,13 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, in
     const int NXg = G.n[0] + 2 * G.g[0], NYg = G.n[1] + 2 * G.g[1];
     if (G.g[2] > 0) {
         const int nl = G.n[2] < 2 * G.g[2] ? G.n[2] : 2 * G.g[2];
-        fold_periodic_kernel<<<dim3(nblocks((int64_t)NXg * NYg * nl), 3), kBlock, 0, st>>>(G, Jc, 2);
+        fold_periodic_kernel<<<dim3(nblocks((int64_t)NXg * NYg * nl), 3), kBlock, 0, st>>>(
+            FoldPArgs{G, Jc, 2});
     }
     {
         const int nl = G.n[1] < 2 * G.g[1] ? G.n[1] : 2 * G.g[1];
-        fold_periodic_kernel<<<dim3(nblocks((int64_t)NXg * nl * G.n[2]), 3), kBlock, 0, st>>>(G, Jc, 1);
+        fold_periodic_kernel<<<dim3(nblocks((int64_t)NXg * nl * G.n[2]), 3), kBlock, 0, st>>>(
+            FoldPArgs{G, Jc, 1});
     }
     const double fl = floor(dys_half);
     const int di = (int)fl;
@@ -587,13 +601,13 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, in
     if (shear) {
         Comp3 Tc{{tmp[0], tmp[1], tmp[2]}};
         shear_advect_kernel<<<dim3(nblocks((int64_t)NXg * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
-            G, Jc, Tc, (float)(sO * dt / 2.0), 0.5f * G.n[0]);
+            AdvArgs{G, Jc, Tc, (float)(sO * dt / 2.0), 0.5f * G.n[0]});
         fold_x_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
-            G, Tc, Jc, 1, 1, di, w);
+            FoldXArgs{G, Tc, Jc, 1, 1, di, w});
     } else {
         const int nl = G.n[0] < 2 * G.g[0] ? G.n[0] : 2 * G.g[0];
         fold_x_kernel<<<dim3(nblocks((int64_t)nl * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
-            G, Jc, Jc, 0, 0, 0, 0.f);
+            FoldXArgs{G, Jc, Jc, 0, 0, 0, 0.f});
     }
     return hipGetLastError();
 }
@@ -620,15 +634,44 @@ hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
     } else {
         const unsigned nb = nblocks((int64_t)K.G.n[0] * K.G.n[1] * K.G.n[2]);
         if (first)
-            ksb_sweep_kernel<true><<<nb, kBlock, 0, st>>>(K);
+            ksb_first_kernel<<<nb, kBlock, 0, st>>>(K);
         else
-            ksb_sweep_kernel<false><<<nb, kBlock, 0, st>>>(K);
+            ksb_next_kernel<<<nb, kBlock, 0, st>>>(K);
     }
     return hipGetLastError();
 }
+hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks, int ydim,
+                      hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks, (unsigned)ydim);
+    switch (k) {
+    case kBatchZero: zero_batch<<<grid, kBlock, 0, st>>>(static_cast<const ZeroArgs*>(table), m); break;
+    case kBatchFill:
+        fill_guards_batch<<<grid, kBlock, 0, st>>>(static_cast<const FillArgs*>(table), m);
+        break;
+    case kBatchFoldP:
+        fold_periodic_batch<<<grid, kBlock, 0, st>>>(static_cast<const FoldPArgs*>(table), m);
+        break;
+    case kBatchAdvect:
+        shear_advect_batch<<<grid, kBlock, 0, st>>>(static_cast<const AdvArgs*>(table), m);
+        break;
+    case kBatchFoldX: fold_x_batch<<<grid, kBlock, 0, st>>>(static_cast<const FoldXArgs*>(table), m); break;
+    case kBatchYeeB: yee_b_batch<<<grid, kBlock, 0, st>>>(static_cast<const MaxwellDev*>(table), m); break;
+    case kBatchYeeE: yee_e_batch<<<grid, kBlock, 0, st>>>(static_cast<const MaxwellDev*>(table), m); break;
+    case kBatchKsbFirst:
+        ksb_first_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbDev*>(table), m);
+        break;
+    case kBatchKsbNext: ksb_next_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbDev*>(table), m); break;
+    }
+    return hipGetLastError();
+}
+
+unsigned grid_blocks(int64_t items) { return nblocks(items); }
+
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st)
 {
-    if (n > 0) zero_kernel<<<nblocks(n), kBlock, 0, st>>>(p, n);
+    if (n > 0) zero_kernel<<<nblocks(n), kBlock, 0, st>>>(ZeroArgs{reinterpret_cast<uint32_t*>(p), n});
     return hipGetLastError();
 }
 hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense, hipStream_t st)

@@ -136,6 +136,39 @@ __device__ inline int xcd_contiguous(int b, int nblk)
     return x * full + (x < rem ? x : rem) + local;
 }
 
+// ---- batched launches
+// One launch runs the blocks of many independent work units (boxes, or parts of boxes):
+// prefix[u] is the first block of unit u, prefix[nu] the total.  A kernel body takes its unit's
+// arguments, its block index inside the unit, the unit's block count and blockIdx.y.
+struct UnitMap {
+    const uint32_t* prefix;
+    int nu;
+};
+__device__ inline int unit_of(const UnitMap& m, int b)  // the unit owning block b
+{
+    int lo = 0, hi = m.nu;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)m.prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads stay scalar
+}
+// name##_kernel(Args): one unit, arguments by value; name##_batch(table, map): many units.
+#define PIC_BATCHED_KERNEL(name, Args, NT)                                                       \
+    __global__ __launch_bounds__(NT) void name##_kernel(Args a)                                  \
+    {                                                                                            \
+        name##_body(a, (int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y);                        \
+    }                                                                                            \
+    __global__ __launch_bounds__(NT) void name##_batch(const Args* __restrict__ t, UnitMap m)   \
+    {                                                                                            \
+        const int u = unit_of(m, (int)blockIdx.x);                                               \
+        name##_body(t[u], (int)blockIdx.x - (int)m.prefix[u], (int)(m.prefix[u + 1] - m.prefix[u]), \
+                    (int)blockIdx.y);                                                            \
+    }
+
 // Geometry of a guarded grid array.
 struct GridDev {
     int dim;
@@ -152,6 +185,40 @@ struct MaxwellDev {
     const float* J[3];
     float dt;
     float fin[3], fout[3], gf[3];
+};
+
+// Arguments of the grid kernels (one unit each; batched launches take tables of them).
+struct Comp6 {
+    float* p[6];
+};
+struct Comp3 {
+    float* p[3];
+};
+struct FillArgs {  // guard fill of one slab kind (0: x, 1: y, 2: z) of ncomp = gridDim.y arrays
+    GridDev G;
+    Comp6 A;
+    int slab, shear, dys_int;
+    float dys_w;
+};
+struct FoldPArgs {  // periodic current fold along axis 1 (y) or 2 (z)
+    GridDev G;
+    Comp3 J;
+    int axis;
+};
+struct AdvArgs {  // J' transport along y (shearing box)
+    GridDev G;
+    Comp3 in, out;
+    float sO_hdt, half_nx;
+};
+struct FoldXArgs {  // x fold (periodic or shearing-periodic)
+    GridDev G;
+    Comp3 in, out;
+    int all, shear, dys_int;
+    float dys_w;
+};
+struct ZeroArgs {  // n 32-bit words set to zero
+    uint32_t* p;
+    int64_t n;
 };
 
 // One fixed-point sweep of the shearing-box implicit midpoint rule: Fo = C + dt/2 L(Fk); the
@@ -194,10 +261,59 @@ struct MigGeo {
     int cy_out, cy_in;
 };
 
+// A launch gated on a device flag runs only when *flag == want (flag == nullptr: always), so
+// that a fallback path can be queued behind a test without a host round trip.
+struct Gate {
+    const int32_t* flag;
+    int want;
+    __device__ inline bool off() const { return flag && *flag != want; }
+};
+
+constexpr uint32_t kErrSort = 16u;  // a batched sort met a particle beyond the neighbour tiles
+
+struct MigCountArgs {
+    const int32_t* cell;
+    const int32_t* toff_prev;
+    CellCode cc;
+    MigGeo g;
+    uint32_t* mcnt;
+    int32_t* fallback;
+    uint32_t* err;  // batched sorts (no radix fallback behind them) latch kErrSort here
+};
+struct MigOffArgs {
+    const uint32_t* mcnt;
+    MigGeo g;
+    uint32_t *mpre, *tot, *dcnt;
+    Gate gate;
+};
+struct MigScatterArgs {
+    const int32_t* cell;
+    const int32_t* toff_prev;
+    int n_upper;
+    CellCode cc;
+    MigGeo g;
+    const uint32_t *mpre, *start, *dpre;
+    uint32_t* perm;
+    int32_t* toff;
+    int32_t* n_live;
+    Gate gate;
+};
+struct ScanArgs {  // exclusive scan of n words by one workgroup
+    const uint32_t* in;
+    uint32_t* out;
+    int n;
+    Gate gate;
+};
+
 // ---- launchers (gpd.hip, sort.hip, grid.hip, xfer.hip)
 bool tile_shape_supported(int dim, const int t[3]);
 hipError_t launch_gather_push(const StepDev& P, const int t[3], int fuse, hipStream_t st);
 hipError_t launch_deposit(const StepDev& P, const int t[3], hipStream_t st);
+// fused push of many boxes of one dimension, tile shape and frame (table: one StepDev per box,
+// m.prefix: first block of each box = its first tile)
+bool batch_tile_supported(int dim, const int t[3]);
+hipError_t launch_gather_push_batch(const StepDev* table, UnitMap m, int blocks, int dim,
+                                    const int t[3], int frame, hipStream_t st);
 
 size_t scan_scratch_words(int64_t n);
 size_t sort_hist_words(int64_t n);
@@ -214,6 +330,18 @@ hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upp
                         Tiles tl, const MigGeo& mg, SortBufs& sb, int32_t* toff,
                         int32_t* n_live_out, int& which, unsigned long long* n_fallback,
                         hipStream_t st);
+
+// batched launches of the grid and sort kernels (tables of per-unit arguments on the device)
+enum GridBatchKind {
+    kBatchZero, kBatchFill, kBatchFoldP, kBatchAdvect, kBatchFoldX, kBatchYeeB, kBatchYeeE,
+    kBatchKsbFirst, kBatchKsbNext
+};
+hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks, int ydim,
+                      hipStream_t st);
+unsigned grid_blocks(int64_t items);  // workgroups of kBlock threads for one item per thread
+enum SortBatchKind { kBatchMigCount, kBatchMigOffsets, kBatchScan, kBatchMigScatter };
+hipError_t sort_batch(SortBatchKind k, const void* table, UnitMap m, int blocks, hipStream_t st);
+int sort_result_buffer(const Tiles& tl);  // sort buffer holding the sorted pairs
 
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
                        hipStream_t st);

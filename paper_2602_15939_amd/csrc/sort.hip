@@ -13,13 +13,6 @@ namespace pic {
 constexpr int kItems = 16;                // items per thread per chunk
 constexpr int kChunk = kBlock * kItems;   // 4096 items per block
 
-// A launch gated on a device flag runs only when *flag == want (flag == nullptr: always), so
-// that a fallback path can be queued behind a test without a host round trip.
-struct Gate {
-    const int32_t* flag;
-    int want;
-    __device__ inline bool off() const { return flag && *flag != want; }
-};
 
 __global__ __launch_bounds__(kBlock) void make_keys_kernel(const int32_t* __restrict__ cell,
                                                            const int32_t* __restrict__ n_live,
@@ -393,14 +386,14 @@ __device__ inline int mig_src(const MigGeo& g, int tx, int ty, int tz, int dx, i
 
 constexpr int kMigItems = 4;  // particles per thread per round of the migration kernels
 
-__global__ __launch_bounds__(kBlock) void mig_count_kernel(const int32_t* __restrict__ cell,
-                                                           const int32_t* __restrict__ toff_prev,
-                                                           CellCode cc, MigGeo g,
-                                                           uint32_t* __restrict__ mcnt,
-                                                           int32_t* __restrict__ fallback)
+__device__ __attribute__((always_inline)) inline void mig_count_body(const MigCountArgs& a, int blk, int, int)
 {
+    const int32_t* __restrict__ cell = a.cell;
+    const int32_t* __restrict__ toff_prev = a.toff_prev;
+    const CellCode& cc = a.cc;
+    const MigGeo& g = a.g;
     __shared__ uint32_t cnt[kMigDirs];
-    const int s = blockIdx.x, tid = threadIdx.x;
+    const int s = blk, tid = threadIdx.x;
     if (tid < kMigDirs) cnt[tid] = 0;
     __syncthreads();
     int sx, sy, sz;
@@ -430,20 +423,26 @@ __global__ __launch_bounds__(kBlock) void mig_count_kernel(const int32_t* __rest
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) stay += __shfl_xor(stay, o, 64);
     if ((tid & 63) == 0 && stay) atomicAdd(&cnt[13], stay);
-    if (bad) *fallback = 1;
+    if (bad) {
+        *a.fallback = 1;
+        if (a.err) atomicOr(a.err, kErrSort);
+    }
     __syncthreads();
-    if (tid < kMigDirs) mcnt[(size_t)s * kMigDirs + tid] = cnt[tid];
+    if (tid < kMigDirs) a.mcnt[(size_t)s * kMigDirs + tid] = cnt[tid];
 }
+PIC_BATCHED_KERNEL(mig_count, MigCountArgs, kBlock)
 
 // one wave per destination tile
-__global__ __launch_bounds__(kBlock) void mig_offsets_kernel(const uint32_t* __restrict__ mcnt,
-                                                             MigGeo g, uint32_t* __restrict__ mpre,
-                                                             uint32_t* __restrict__ tot,
-                                                             uint32_t* __restrict__ dcnt, Gate gate)
+__device__ __attribute__((always_inline)) inline void mig_offsets_body(const MigOffArgs& a, int blk, int, int)
 {
-    if (gate.off()) return;
+    if (a.gate.off()) return;
+    const uint32_t* __restrict__ mcnt = a.mcnt;
+    const MigGeo& g = a.g;
+    uint32_t* __restrict__ mpre = a.mpre;
+    uint32_t* __restrict__ tot = a.tot;
+    uint32_t* __restrict__ dcnt = a.dcnt;
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int t = blk * (kBlock / 64) + (threadIdx.x >> 6);
     if (t == 0 && lane == 0) {
         tot[g.n_tiles] = 0;
         dcnt[g.n_tiles] = 0;
@@ -475,18 +474,26 @@ __global__ __launch_bounds__(kBlock) void mig_offsets_kernel(const uint32_t* __r
         dcnt[t] = mcnt[(size_t)t * kMigDirs + kMigDead];
     }
 }
+PIC_BATCHED_KERNEL(mig_offsets, MigOffArgs, kBlock)
 
 // block s < n_tiles: the particles of source tile s; block n_tiles: the previous dead bin
-__global__ __launch_bounds__(kBlock) void mig_scatter_kernel(
-    const int32_t* __restrict__ cell, const int32_t* __restrict__ toff_prev, int n_upper,
-    CellCode cc, MigGeo g, const uint32_t* __restrict__ mpre, const uint32_t* __restrict__ start,
-    const uint32_t* __restrict__ dpre, uint32_t* __restrict__ perm, int32_t* __restrict__ toff,
-    int32_t* __restrict__ n_live, Gate gate)
+__device__ __attribute__((always_inline)) inline void mig_scatter_body(const MigScatterArgs& a, int blk, int, int)
 {
-    if (gate.off()) return;
+    if (a.gate.off()) return;
+    const int32_t* __restrict__ cell = a.cell;
+    const int32_t* __restrict__ toff_prev = a.toff_prev;
+    const int n_upper = a.n_upper;
+    const CellCode& cc = a.cc;
+    const MigGeo& g = a.g;
+    const uint32_t* __restrict__ mpre = a.mpre;
+    const uint32_t* __restrict__ start = a.start;
+    const uint32_t* __restrict__ dpre = a.dpre;
+    uint32_t* __restrict__ perm = a.perm;
+    int32_t* __restrict__ toff = a.toff;
+    int32_t* __restrict__ n_live = a.n_live;
     __shared__ uint32_t run[2][kMigDirs];
     __shared__ uint32_t wc[kMigItems][kBlock / 64][kMigDirs];
-    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int s = blk, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t live = start[g.n_tiles];
     if (s == g.n_tiles) {
         const int beg = toff_prev[g.n_tiles];
@@ -567,11 +574,62 @@ __global__ __launch_bounds__(kBlock) void mig_scatter_kernel(
         p ^= 1;
     }
 }
+PIC_BATCHED_KERNEL(mig_scatter, MigScatterArgs, kBlock)
+
+// Exclusive scan of n words by one workgroup (the per-tile arrays of a small box).
+__device__ __attribute__((always_inline)) inline void scan_small_body(const ScanArgs& a, int, int, int)
+{
+    if (a.gate.off()) return;
+    __shared__ uint32_t ws[kBlock / 64];
+    __shared__ uint32_t carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < a.n; base += kBlock) {
+        const int i = base + tid;
+        const uint32_t v = i < a.n ? a.in[i] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) ws[w] = inc;
+        __syncthreads();
+        uint32_t pre = carry;
+        for (int k = 0; k < w; k++) pre += ws[k];
+        if (i < a.n) a.out[i] = pre + inc - v;
+        __syncthreads();
+        if (tid == kBlock - 1) carry = pre + inc;
+        __syncthreads();
+    }
+}
+PIC_BATCHED_KERNEL(scan_small, ScanArgs, kBlock)
 
 __global__ void count_fallback_kernel(unsigned long long* ctr, Gate g)
 {
     if (!g.off()) ctr[0] += 1ull;
 }
+
+hipError_t sort_batch(SortBatchKind k, const void* table, UnitMap m, int blocks, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    switch (k) {
+    case kBatchMigCount:
+        mig_count_batch<<<blocks, kBlock, 0, st>>>(static_cast<const MigCountArgs*>(table), m);
+        break;
+    case kBatchMigOffsets:
+        mig_offsets_batch<<<blocks, kBlock, 0, st>>>(static_cast<const MigOffArgs*>(table), m);
+        break;
+    case kBatchScan: scan_small_batch<<<blocks, kBlock, 0, st>>>(static_cast<const ScanArgs*>(table), m); break;
+    case kBatchMigScatter:
+        mig_scatter_batch<<<blocks, kBlock, 0, st>>>(static_cast<const MigScatterArgs*>(table), m);
+        break;
+    }
+    return hipGetLastError();
+}
+
+int sort_result_buffer(const Tiles& tl) { return radix_passes(tl) & 1; }
 
 size_t migrate_scratch_words(int n_tiles) { return scan_scratch_words((int64_t)n_tiles + 1); }
 
@@ -584,15 +642,16 @@ hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upp
     const Gate mig{sb.fallback, 0}, radix{sb.fallback, 1};
     which = radix_passes(tl) & 1;  // where the radix fallback leaves its result
     if (hipMemsetAsync(sb.fallback, 0, sizeof(int32_t), st) != hipSuccess) return hipGetLastError();
-    mig_count_kernel<<<nt, kBlock, 0, st>>>(cell, toff_prev, cc, mg, sb.mcnt, sb.fallback);
+    mig_count_kernel<<<nt, kBlock, 0, st>>>(
+        MigCountArgs{cell, toff_prev, cc, mg, sb.mcnt, sb.fallback, nullptr});
     mig_offsets_kernel<<<(nt + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, st>>>(
-        sb.mcnt, mg, sb.mpre, sb.tot, sb.dcnt, mig);
+        MigOffArgs{sb.mcnt, mg, sb.mpre, sb.tot, sb.dcnt, mig});
     hipError_t e = scan_exclusive(sb.tot, sb.start, nt + 1, sb.mscratch, st, mig);
     if (e == hipSuccess) e = scan_exclusive(sb.dcnt, sb.dpre, nt + 1, sb.mscratch, st, mig);
     if (e != hipSuccess) return e;
-    mig_scatter_kernel<<<nt + 1, kBlock, 0, st>>>(cell, toff_prev, n_upper, cc, mg, sb.mpre,
-                                                   sb.start, sb.dpre, sb.vals[which], toff,
-                                                   n_live_out, mig);
+    mig_scatter_kernel<<<nt + 1, kBlock, 0, st>>>(
+        MigScatterArgs{cell, toff_prev, n_upper, cc, mg, sb.mpre, sb.start, sb.dpre, sb.vals[which],
+                       toff, n_live_out, mig});
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     int w2 = 0;

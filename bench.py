@@ -112,6 +112,73 @@ def cpu_baseline(seconds=12.0):
                        f"steps in {el:.1f} s, OpenMP over particles")
 
 
+def serve_bench(args):
+    """The served batch: 512 independent 2D box runs of 500 steps (see serve.py for the
+    recipe).  (1) capacity: all runs queued at t = 0, admitted by HBM footprint, stepped together
+    by the batched step; (2) Poisson arrivals at 0.8 x capacity: p50/p99 run latency and
+    aggregate particle-steps/s; (3) one box at a time (per-box launches) on the first runs of the
+    same list; (4) runs sampled from the mix re-run alone: final energies within 1%."""
+    import numpy as np
+    import torch
+
+    from paper_2602_15939_amd import serve
+
+    budget = int(args.budget_gb * 2**30)
+    # warm-up (module loads, allocator pools): a few runs each way, not timed
+    warm = serve.make_specs(6, 5, seed=1)
+    serve.serve(warm, budget, batched=True)
+    serve.serve(warm[:2], 0, batched=False)
+    specs = serve.make_specs(args.runs, args.run_steps)
+    print(f"[serve] capacity run: {len(specs)} runs queued at t=0", file=sys.stderr, flush=True)
+    res, wall = serve.serve(specs, budget, batched=True)
+    cap = serve.summarize(res, wall)
+    rate = 0.8 * cap["runs_per_s"]
+    specs = serve.poisson_arrivals(serve.make_specs(args.runs, args.run_steps), rate)
+    print(f"[serve] Poisson run at {rate:.2f} runs/s", file=sys.stderr, flush=True)
+    res, wall = serve.serve(specs, budget, batched=True, keep_energies=True)
+    mix = serve.summarize(res, wall)
+    base_specs = serve.make_specs(args.runs, args.run_steps)[: args.baseline_runs]
+    print(f"[serve] one box at a time: {len(base_specs)} runs", file=sys.stderr, flush=True)
+    bres, bwall = serve.serve(base_specs, 0, batched=False)
+    base = serve.summarize(bres, bwall)
+    # consistency: sampled runs alone vs in the mix
+    rng = np.random.default_rng(3)
+    by_id = {r.spec.rid: r for r in res}
+    sample = [by_id[int(i)] for i in rng.choice(sorted(by_id), size=min(16, len(by_id)), replace=False)]
+    worst = 0.0
+    for r in sample:
+        sp = serve.RunSpec(**{k: getattr(r.spec, k) for k in ("rid", "n", "ppc", "kind", "theta",
+                                                                "param", "steps", "seed")})
+        alone, _ = serve.serve([sp], 0, batched=False, keep_energies=True)
+        ef_m, ek_m, n_m = r.energies
+        ef_a, ek_a, n_a = alone[0].energies
+        worst = max(worst, abs(ef_m - ef_a) / abs(ef_a), abs(ek_m - ek_a) / abs(ek_a))
+        assert n_m == n_a, (r.spec.rid, n_m, n_a)
+    torch.cuda.synchronize()
+    out = {
+        "metric": "served batch: aggregate particle-steps/s (batched) & p50/p99 run latency",
+        "value": mix["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.run_steps,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"served_2d_{args.runs}runs_{args.run_steps}steps",
+                   "runs": args.runs, "steps_per_run": args.run_steps,
+                   "budget_gb": args.budget_gb, "arrival_rate_runs_per_s": rate,
+                   "capacity": cap, "poisson": mix, "one_at_a_time": base,
+                   "batched_over_one_at_a_time": mix["particle_steps_per_s"] / base["particle_steps_per_s"],
+                   "capacity_over_one_at_a_time": cap["particle_steps_per_s"] / base["particle_steps_per_s"],
+                   "alone_vs_mix_max_rel_energy_diff": worst, "alone_vs_mix_runs": len(sample)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,11 +189,20 @@ def main():
     ap.add_argument("--seed", type=int, default=20260216)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for profiles)")
+    ap.add_argument("--serve", action="store_true",
+                    help="the served batch of independent 2D boxes instead of the 3D box")
+    ap.add_argument("--runs", type=int, default=512)
+    ap.add_argument("--run-steps", type=int, default=500)
+    ap.add_argument("--baseline-runs", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=160.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: every box of this build lives on a single MI355X; "
               "--gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
     import torch
 
     from paper_2602_15939_amd import _lib as L

@@ -115,9 +115,9 @@ typedef struct pic_box_info {
 } pic_box_info;
 
 /* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard
-   cells, the ping-pong particle arrays of the given capacities and the sort workspace
-   (PIC_ENOMEM).  Fields start at zero and the box holds no particles.  *out is set only
-   on success. */
+   cells, the ping-pong particle arrays of the given capacities and the sort workspace in one
+   device allocation (PIC_ENOMEM).  Fields start at zero (cleared on the box stream) and the
+   box holds no particles.  *out is set only on success. */
 int32_t pic_box_create(const pic_box_desc* desc, pic_box** out);
 
 /* Free the box and its device memory (synchronises the box stream).  NULL is accepted. */
@@ -131,8 +131,10 @@ int32_t pic_get_fields(pic_box* box, float* E_dev, float* B_dev);
    after the guard fold and (shearing box) the J' transport of Sec. 2.2 */
 int32_t pic_get_current(pic_box* box, float* J_dev);
 
-/* Load n particles of one species (layout above; id_dev NULL -> ids 0..n-1, dr_dev NULL -> 0)
-   and tile-sort them.  PIC_ECAP if n exceeds the capacity, PIC_EINVAL on a bad species. */
+/* Load n particles of one species (layout above; id_dev NULL -> ids 0..n-1, dr_dev NULL -> 0);
+   the next pic_tile_sort (or pic_step) sorts them.  Asynchronous on the box stream: the input
+   buffers must stay valid until the stream has passed this call.  PIC_ECAP if n exceeds the
+   capacity, PIC_EINVAL on a bad species. */
 int32_t pic_set_particles(pic_box* box, int32_t species, int64_t n, const int32_t* cell_dev,
                           const float* off_dev, const float* u_dev, const uint32_t* id_dev,
                           const float* dr_dev);

@@ -45,6 +45,21 @@ class Box:
         self.nsp = len(species)
         self.h = L.pic_box_create(d)
 
+    # ---- stream ordering of caller buffers
+    def _wait_for_torch(self):
+        """Inputs made on torch's current stream must be ready before the box stream reads
+        them (nothing to do when that is the box stream)."""
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _keep_until_stream(self, *tensors):
+        """The library reads caller buffers asynchronously on the box stream: tell torch's
+        allocator not to reuse them before that stream has passed this point."""
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
     # ---- lifetime
     def close(self):
         if getattr(self, "h", None):
@@ -64,8 +79,9 @@ class Box:
     def set_fields(self, E, B):
         E = torch.as_tensor(E, dtype=torch.float32).cuda().contiguous()
         B = torch.as_tensor(B, dtype=torch.float32).cuda().contiguous()
+        self._wait_for_torch()
         L.pic_set_fields(self.h, E.data_ptr(), B.data_ptr())
-        self.stream.synchronize()
+        self._keep_until_stream(E, B)
 
     def get_fields(self):
         E, B = self._grid(), self._grid()
@@ -91,8 +107,9 @@ class Box:
             dr = torch.as_tensor(dr, dtype=torch.float32).cuda().contiguous()
             assert dr.shape == (3, n)
             dp = dr.data_ptr()
-        self.stream.synchronize()
+        self._wait_for_torch()
         L.pic_set_particles(self.h, species, n, cell.data_ptr(), off.data_ptr(), u.data_ptr(), ip, dp)
+        self._keep_until_stream(cell, off, u, ids, dr)
 
     def count(self, species=0) -> int:
         return int(self.info().n_particles[species])

@@ -85,6 +85,11 @@ struct pic_box {
     bool deposit_pending = false;
     bool track_ids = false;
     std::vector<void*> allocs;
+    // pic_box_create takes all of the box's device memory in one allocation: a first pass over
+    // the buffer list measures it, a second carves it
+    int alloc_pass = 0;  // 0: separate allocations, 1: measuring, 2: carving
+    char* arena = nullptr;
+    size_t arena_off = 0;
 
     float* E(int c) const { return set[cur_set][3 + c]; }
     float* B(int c) const { return set[cur_set][c]; }
@@ -100,9 +105,20 @@ int32_t hip_fail(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EDEVICE; 
 template <class T>
 int32_t dalloc(pic_box* b, T*& p, size_t count)
 {
-    void* q = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return PIC_ENOMEM;
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (b->alloc_pass == 1) {  // measuring
+        b->arena_off += bytes;
+        p = nullptr;
+        return PIC_OK;
+    }
+    if (b->alloc_pass == 2) {  // carving
+        p = reinterpret_cast<T*>(b->arena + b->arena_off);
+        b->arena_off += bytes;
+        return PIC_OK;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return PIC_ENOMEM;
     b->allocs.push_back(q);
     p = static_cast<T*>(q);
     return PIC_OK;
@@ -981,10 +997,13 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         float* q = nullptr;
         int32_t rr = dalloc(b, q, (size_t)b->comp_elems);
         if (rr) return rr;
+        if (b->alloc_pass == 1) return PIC_OK;
         if (hipMemsetAsync(q, 0, sizeof(float) * b->comp_elems, b->st) != hipSuccess) return PIC_EDEVICE;
         p = q + b->origin;
         return PIC_OK;
     };
+    auto alloc_all = [&]() -> int32_t {
+    int32_t r = PIC_OK;
     b->nsets = d->frame == PIC_FRAME_SHEAR ? 3 : 1;
     for (int s = 0; s < b->nsets && !r; s++)
         for (int c = 0; c < 6 && !r; c++) r = grid_alloc(b->set[s][c]);
@@ -1022,22 +1041,43 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         if (!r) r = dalloc(b, S.sb.mscratch, migrate_scratch_words(b->tl.n_tiles));
         if (!r) r = dalloc(b, S.sb.fallback, 1);
         if (!r) r = dalloc(b, S.n_live, 2);
-        if (!r && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
+        if (!r && b->alloc_pass != 1 && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess)
+            r = PIC_EDEVICE;
     }
     if (!r) r = dalloc(b, b->err, 4);
     if (!r) r = dalloc(b, b->ctr, 4);
     if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
     if (!r) r = dalloc(b, b->red_out, 16);
+    if (!r && d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
+        r = dalloc(b, b->mj, (size_t)kMjBins + kMjTail);
+    if (b->alloc_pass == 1) return r;
     if (!r && hipMemsetAsync(b->err, 0, 4 * sizeof(uint32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
     if (!r && hipMemsetAsync(b->ctr, 0, 4 * sizeof(unsigned long long), b->st) != hipSuccess) r = PIC_EDEVICE;
-    if (!r && d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT) {
+    if (!r && b->mj) {
         std::vector<float> tab;
         build_mj_table(d->leaky_theta_inj, tab);
-        r = dalloc(b, b->mj, tab.size());
-        if (!r && hipMemcpy(b->mj, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        // synchronous copy from the host vector (it is freed on return)
+        if (hipMemcpy(b->mj, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
             r = PIC_EDEVICE;
     }
-    if (!r && hipStreamSynchronize(b->st) != hipSuccess) r = PIC_EDEVICE;
+    return r;
+    };
+    b->alloc_pass = 1;
+    b->arena_off = 0;
+    r = alloc_all();
+    if (!r) {
+        void* q = nullptr;
+        if (hipMalloc(&q, b->arena_off) != hipSuccess) {
+            r = PIC_ENOMEM;
+        } else {
+            b->allocs.push_back(q);
+            b->arena = static_cast<char*>(q);
+            b->alloc_pass = 2;
+            b->arena_off = 0;
+            r = alloc_all();
+        }
+    }
+    b->alloc_pass = 0;
     if (r) {
         pic_box_destroy(b);
         return r;
@@ -1113,10 +1153,7 @@ int32_t pic_set_particles(pic_box* b, int32_t s, int64_t n, const int32_t* cell,
             }
         }
     }
-    const int32_t nn = (int32_t)n;
-    if (hipMemcpyAsync(S.n_live, &nn, sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
-        return PIC_EDEVICE;
-    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EDEVICE;
+    if (set_i32(S.n_live, (int32_t)n, st) != hipSuccess) return PIC_EDEVICE;
     S.n_upper = (int)n;
     S.grouped = false;
     b->sorted = false;

@@ -364,5 +364,6 @@ hipError_t cells_packed_to_linear(const int32_t* packed, int32_t* lin, int64_t n
                                   CellCode cc, hipStream_t st);
 hipError_t device_copy16(void* dst, const void* src, int64_t nwords, hipStream_t st);
 hipError_t iota_u32(uint32_t* p, int64_t n, hipStream_t st);
+hipError_t set_i32(int32_t* p, int32_t v, hipStream_t st);
 
 }  // namespace pic

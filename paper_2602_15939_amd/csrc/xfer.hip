@@ -52,6 +52,8 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(uint4* __restrict__ dst,
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+__global__ void set_i32_kernel(int32_t* p, int32_t v) { *p = v; }
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n, const int nn[3],
@@ -77,6 +79,12 @@ hipError_t device_copy16(void* dst, const void* src, int64_t nwords, hipStream_t
         copy_kernel<<<grid, kBlock, 0, st>>>(static_cast<uint4*>(dst), static_cast<const uint4*>(src),
                                              nwords);
     }
+    return hipGetLastError();
+}
+
+hipError_t set_i32(int32_t* p, int32_t v, hipStream_t st)
+{
+    set_i32_kernel<<<1, 1, 0, st>>>(p, v);
     return hipGetLastError();
 }
 

@@ -1,0 +1,195 @@
+"""Served mode: a request loop that keeps many independent 2D box runs resident on the GPU and
+advances all of them together with the batched step (one launch per kernel for every active box,
+box-descriptor tables).  Runs arrive over time; each is admitted as soon as its HBM footprint
+fits the budget, stepped until it has done its steps, and retired (its memory freed for the next
+arrivals).  Completion is timed after the GPU has finished the run's last step.
+
+Workload of a served batch (seeded): box sizes uniform over {32^2, 64^2, 128^2, 256^2} cells,
+particles per cell per species uniform in [4, 32], variant uniform over shearing box
+(s uniform in [0, 1.5]), expanding box (adot uniform in [1e-4, 1e-3] omega_p) and leaky box
+(t_esc uniform in [5, 50] L/c, probabilistic escape above gamma = 10), Maxwell-Juttner
+theta uniform in [0.05, 0.5], skin depth 4 cells, sigma = 0.1.
+Readings: B0 along z (shearing and leaky boxes) and along x for the expanding box, which
+expands in y and z (l_y = l_z = a(t), the expansion perpendicular to B0); Omega0 = 0.1 omega_c,
+reduced on boxes wider than 64 cells so that the shear flow stays at most 0.38 c at the x faces
+(s Omega0 L/2 <= 1.5 * 0.1 * 0.079 * 32).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import synth
+from .box import Box, step_many
+
+SIZES = (32, 64, 128, 256)
+KINDS = ("shear", "expand", "leaky")
+
+
+@dataclass
+class RunSpec:
+    rid: int
+    n: int
+    ppc: int
+    kind: str
+    theta: float
+    param: float  # s (shear), adot (expand), t_esc in units of L/c (leaky)
+    steps: int
+    seed: int
+    arrival: float = 0.0
+
+    @property
+    def particles(self) -> int:
+        return 2 * self.ppc * self.n * self.n
+
+
+def make_specs(n_runs=512, steps=500, seed=20260217):
+    rng = np.random.default_rng(seed)
+    wp = 0.25
+    out = []
+    for r in range(n_runs):
+        kind = KINDS[int(rng.integers(0, 3))]
+        if kind == "shear":
+            param = float(rng.uniform(0.0, 1.5))
+        elif kind == "expand":
+            param = float(rng.uniform(1e-4, 1e-3)) * wp
+        else:
+            param = float(rng.uniform(5.0, 50.0))
+        out.append(RunSpec(r, int(SIZES[int(rng.integers(0, 4))]), int(rng.integers(4, 33)), kind,
+                           float(rng.uniform(0.05, 0.5)), param, steps, seed * 1000 + r))
+    return out
+
+
+def poisson_arrivals(specs, rate, seed=7):
+    """Arrival times of a Poisson process of the given rate (runs per second), in order."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, len(specs)))
+    for s, a in zip(specs, t):
+        s.arrival = float(a)
+    return specs
+
+
+def tile_for(n: int):
+    """Tile rule (from tile_sweep on the GPU): 8x8 tiles for 32^2 boxes (the migration sort
+    needs at least three tiles per axis), 16x16 otherwise."""
+    return (8, 8, 1) if n < 64 else (16, 16, 1)
+
+
+def footprint(spec: RunSpec) -> int:
+    """Device bytes of one run: particle state double-buffered with ids and sort workspace
+    (~96 B per particle), 3 field sets + current + transport buffer with padded rows."""
+    cells = (spec.n + 64) * (spec.n + 4)
+    return spec.particles * 96 + cells * 4 * 30 + (1 << 20)
+
+
+def build_box(spec: RunSpec) -> Box:
+    wp, q, B0 = synth.plasma_params(spec.ppc, 4.0, 0.1)
+    n = (spec.n, spec.n)
+    count = spec.ppc * spec.n * spec.n
+    species = [(-1.0, -q, count), (1.0, q, count)]
+    common = dict(dt=0.45, species=species, seed=spec.seed, box_id=spec.rid,
+                  tile=tile_for(spec.n), maxwell_iters=4)
+    axis = 2
+    if spec.kind == "shear":
+        omega0 = 0.1 * B0 * min(1.0, 64.0 / spec.n)
+        box = Box(2, n, frame=L.FRAME_SHEAR, shear_s=spec.param, shear_omega0=omega0, **common)
+    elif spec.kind == "expand":
+        box = Box(2, n, frame=L.FRAME_EXPAND, expand_adot=spec.param, expand_axis_mask=0b110,
+                  **common)
+        axis = 0
+    else:
+        box = Box(2, n, frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_PROBABILISTIC,
+                  leaky_t_esc=spec.param * spec.n, leaky_gamma_thr=10.0, **common)
+    E, B = synth.uniform_field(n, axis, B0)
+    box.set_fields(torch.from_numpy(E).float(), torch.from_numpy(B).float())
+    for s, p in enumerate(synth.pair_plasma(n, spec.ppc, spec.theta, spec.seed, device="cuda")):
+        box.set_particles(s, p["cell"], p["off"], p["u"])
+    return box
+
+
+@dataclass
+class RunResult:
+    spec: RunSpec
+    admitted: float
+    done: float
+    energies: tuple = field(default_factory=tuple)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.spec.arrival
+
+
+def _energies(box: Box):
+    info = box.info()
+    assert info.errors & ~L.DERR_ORDER == 0, f"device error bits {info.errors}"
+    return (sum(info.field_energy_E) + sum(info.field_energy_B), info.kinetic_energy,
+            int(info.n_particles[0] + info.n_particles[1]))
+
+
+ADMIT_PER_STEP = 8  # runs built per loop turn: building overlaps the GPU's steps
+
+
+def serve(specs, budget_bytes, batched=True, keep_energies=False, clock=time.perf_counter):
+    """Run every spec (arrival times relative to the call) and return the results in
+    completion order.  batched=False steps the active boxes one at a time (per-box launches);
+    with admission of one run at a time that is the one-box-at-a-time baseline."""
+    pending = sorted(specs, key=lambda s: s.arrival)
+    active = []  # [spec, box, steps_done, admitted]
+    used = 0
+    out = []
+    serve.build_s = serve.step_s = 0.0
+    t0 = clock()
+    i = 0
+    while i < len(pending) or active:
+        now = clock() - t0
+        admitted = 0
+        while i < len(pending) and pending[i].arrival <= now and admitted < ADMIT_PER_STEP and (
+                not active or used + footprint(pending[i]) <= budget_bytes):
+            admitted += 1
+            sp = pending[i]
+            tb = clock()
+            active.append([sp, build_box(sp), 0, now])
+            serve.build_s += clock() - tb
+            used += footprint(sp)
+            i += 1
+            now = clock() - t0
+        if not active:
+            time.sleep(max(0.0, min(pending[i].arrival - now, 0.01)))
+            continue
+        boxes = [a[1] for a in active]
+        ts = clock()
+        if batched:
+            step_many(boxes, batched=True)
+        else:
+            for b in boxes:
+                step_many([b], batched=False)
+        serve.step_s += clock() - ts
+        for a in active:
+            a[2] += 1
+        finished = [a for a in active if a[2] >= a[0].steps]
+        if finished:
+            torch.cuda.synchronize()
+            t = clock() - t0
+            for a in finished:
+                e = _energies(a[1]) if keep_energies else ()
+                out.append(RunResult(a[0], a[3], t, e))
+                a[1].close()
+                used -= footprint(a[0])
+            active = [a for a in active if a[2] < a[0].steps]
+    return out, clock() - t0
+
+
+def summarize(results, wall):
+    lat = np.array([r.latency for r in results])
+    ps = sum(r.spec.particles * r.spec.steps for r in results)
+    return dict(runs=len(results), wall_s=wall, particle_steps=ps,
+                host_build_s=serve.build_s, host_step_enqueue_s=serve.step_s,
+                particle_steps_per_s=ps / wall if wall > 0 else math.nan,
+                p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else math.nan,
+                p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else math.nan,
+                runs_per_s=len(results) / wall if wall > 0 else math.nan)

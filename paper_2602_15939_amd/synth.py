@@ -30,7 +30,7 @@ def plasma_params(ppc_per_species: int, skin_depth: float = 4.0, sigma: float = 
     return wp, q, wp * math.sqrt(sigma)
 
 
-def _mj_cdf(theta: float, npts: int = 200001):
+def _mj_cdf(theta: float, npts: int = 20001):
     gmax = 1.0 + 50.0 * theta
     umax = math.sqrt(gmax * gmax - 1.0)
     u = np.linspace(0.0, umax, npts)

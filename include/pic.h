@@ -84,7 +84,7 @@ typedef struct pic_box_desc {
     int32_t n_species;       /* 1 or 2 */
     double q_over_m[2];      /* charge-to-mass ratio (sign included) */
     double q_macro[2];       /* macro-particle charge (sign included) */
-    int64_t capacity[2];     /* maximum particle count per species */
+    int64_t capacity[2];     /* maximum particle count per species (below 2^30) */
     uint64_t seed;           /* Philox4x32-10 key */
     uint32_t box_id;         /* fourth Philox counter word */
     int32_t tile[3];         /* tile shape in cells (0 = default: 8^3 in 3D, 16x16 in 2D) */

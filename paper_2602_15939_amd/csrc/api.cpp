@@ -945,7 +945,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     for (int k = 0; k < 3; k++) bits[k] = ceil_log2(n[k]);
     if (bits[0] + bits[1] + bits[2] > 31) return PIC_EINVAL;
     for (int s = 0; s < d->n_species; s++)
-        if (d->capacity[s] < 0 || d->capacity[s] >= (1ll << 31) - 4096) return PIC_EINVAL;
+        if (d->capacity[s] < 0 || d->capacity[s] >= (1ll << 30)) return PIC_EINVAL;  // 32-bit byte offsets
 
     pic_box* b = new (std::nothrow) pic_box();
     if (!b) return PIC_ENOMEM;

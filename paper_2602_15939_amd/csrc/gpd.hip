@@ -2,8 +2,9 @@
 // Boris-like push, position update with the boundary conditions, leaky-box escape and the
 // charge-conserving (Esirkepov) current deposit, fused in one kernel per tile.
 //
-// One workgroup owns one tile: it stages E and B of the tile plus one guard cell per side in
-// LDS, accumulates the tile's current (plus the deposit halo) in LDS as 64-bit fixed point, and
+// One workgroup owns one tile: it stages E and B of the tile plus the guard layers the gather
+// reaches in LDS (one region per Yee component, sized for that component's lattice),
+// accumulates the tile's current (plus the deposit halo) in LDS as 64-bit fixed point, and
 // flushes it once to HBM with float atomics (only the halo overlaps a neighbour tile).
 // Particles are read through the sort permutation and written in sorted slot order, so the
 // tile sort's scatter is fused into this pass.  A particle found outside its tile (only
@@ -29,6 +30,20 @@ __device__ inline f3 cross(f3 a, f3 b)
 // the correctly rounded division and square-root sequences.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Particle arrays are indexed with 32-bit byte offsets (capacity below 2^30 per species), so
+// the loads and stores take a scalar base and one shared vector offset.
+template <class T>
+__device__ inline T ld_at(const T* __restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                       (size_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ inline void st_at(T* __restrict__ base, uint32_t i, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (size_t)(i * (uint32_t)sizeof(T))) = v;
+}
 
 // ------------------------------------------------------------------ interpolation
 // Linear (CIC) interpolation of one component on its own staggered lattice (base index and
@@ -153,24 +168,14 @@ __device__ inline f3 push_expand(f3 u, f3 E, f3 B, float qm_hdt, const float lam
 
 // ------------------------------------------------------------------ positions
 // In-cell offset renormalisation after s = off + delta (|delta| < 1), in FP32:
-// s >= 1 -> (+1, s-1) exact; s < 0 -> t = s+1, (-1, t) if t < 1 else (0, 0).
+// s >= 1 -> (+1, s-1) exact; s < 0 -> t = s+1, (-1, t) if t < 1 else (0, 0).  Written with
+// selects only (no divergent branches).
 __device__ inline float renorm(float s, int& dc)
 {
-    if (s >= 1.f) {
-        dc = 1;
-        return __fsub_rn(s, 1.f);
-    }
-    if (s < 0.f) {
-        const float t = __fadd_rn(s, 1.f);
-        if (t < 1.f) {
-            dc = -1;
-            return t;
-        }
-        dc = 0;
-        return 0.f;
-    }
-    dc = 0;
-    return s;
+    const float sm = __fsub_rn(s, 1.f), sp = __fadd_rn(s, 1.f);
+    const bool ge = s >= 1.f, lt = s < 0.f, lt_ok = lt && sp < 1.f;
+    dc = ge ? 1 : (lt_ok ? -1 : 0);
+    return ge ? sm : (lt ? (lt_ok ? sp : 0.f) : s);
 }
 
 // ------------------------------------------------------------------ Esirkepov deposit
@@ -272,19 +277,53 @@ __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, con
     }
 }
 
-// LDS accumulator: (JX, JY, JZ) region per component, origin at the tile origin minus one.
-// The tile current is summed in 64-bit fixed point: a contribution arrives pre-scaled so that
-// the largest possible single contribution is 2^30 units, is truncated to int32 and added with
-// ds_add_u64 (integer LDS atomics cost a few cycles per wave instruction, while FP32 LDS
-// atomics are serialised per lane).  Integer sums are exact and independent of the order.
-template <int JX, int JY, int JZ>
+// ------------------------------------------------------------------ tile regions in LDS
+// Field component f (0..2 = Ex, Ey, Ez; 3..5 = Bx, By, Bz) lies on the half-shifted lattice
+// along the axes of its Yee offset: Ex x, Ey y, Ez z, Bx y and z, By x and z, Bz x and y.
+__host__ __device__ constexpr bool yee_half(int f, int a) { return f < 3 ? f == a : f - 3 != a; }
+
+template <int DIM, int TX, int TY, int TZ>
+struct Geo {
+    static constexpr int T(int a) { return a == 0 ? TX : (a == 1 ? TY : TZ); }
+    // Staged field component f: along a half-lattice axis the values at global indices
+    // t0-1 .. t0+T (T+2), along an integer axis t0 .. t0+T (T+1): what CIC needs for a
+    // particle in the tile.
+    static constexpr int fdim(int f, int a)
+    {
+        return (DIM == 2 && a == 2) ? 1 : T(a) + (yee_half(f, a) ? 2 : 1);
+    }
+    static constexpr int fsize(int f) { return fdim(f, 0) * fdim(f, 1) * fdim(f, 2); }
+    static constexpr int foff(int f) { return f == 0 ? 0 : foff(f - 1) + fsize(f - 1); }
+    // Current component c, origin at global index t0-1 on every axis: along its own axis the
+    // edges t0-1 .. t0+T (T+2), across it the nodes t0-1 .. t0+T+1 (T+3); the deposit of a
+    // particle of the tile stays inside.  2D: J_z has nodes along x and y.
+    static constexpr int jdim(int c, int a)
+    {
+        return (DIM == 2 && a == 2) ? 1 : T(a) + (a == c ? 2 : 3);
+    }
+    static constexpr int jsize(int c) { return jdim(c, 0) * jdim(c, 1) * jdim(c, 2); }
+    static constexpr int joff(int c) { return c == 0 ? 0 : joff(c - 1) + jsize(c - 1); }
+    static constexpr int JTOT = joff(2) + jsize(2);
+    static constexpr int FTOT = foff(5) + fsize(5);
+    static constexpr int FBYTES = (4 * FTOT + 15) & ~15;   // E, B first, then J (8-byte words)
+    static constexpr int LDS_BYTES = FBYTES + 8 * JTOT;
+};
+
+// LDS accumulator: one region per current component (Geo::jdim).  The tile current is summed in
+// 64-bit fixed point: a contribution arrives pre-scaled so that the largest possible single
+// contribution is 2^30 units, is truncated to int32 and added with ds_add_u64 (integer LDS
+// atomics cost a few cycles per wave instruction, while FP32 LDS atomics are serialised per
+// lane).  Integer sums are exact and independent of the order.
+template <class G>
 struct LdsAcc {
     unsigned long long* J;
-    int base;  // index of (nearest node - 1) per axis in the region
+    int base[3];  // per component: region index of (nearest node - 1) on every axis
     __device__ inline void add(int c, int x, int y, int z, float v, bool on)
     {
         const long long q = (long long)(int)v;  // v_cvt_i32_f32: truncates, saturates
-        if (on) atomicAdd(&J[c * (JX * JY * JZ) + base + x + JX * (y + JY * z)], (unsigned long long)q);
+        if (on)
+            atomicAdd(&J[G::joff(c) + base[c] + x + G::jdim(c, 0) * (y + G::jdim(c, 1) * z)],
+                      (unsigned long long)q);
     }
 };
 
@@ -299,16 +338,75 @@ struct GlobalAcc {
     }
 };
 
-// ------------------------------------------------------------------ the fused kernel
-template <int DIM, int TX, int TY, int TZ>
-struct Geo {
-    static constexpr int FX = TX + 2, FY = TY + 2, FZ = DIM == 3 ? TZ + 2 : 1;
-    static constexpr int FS = FX * FY * FZ;
-    static constexpr int JX = TX + 3, JY = TY + 3, JZ = DIM == 3 ? TZ + 3 : 1;
-    static constexpr int JS = JX * JY * JZ;
-    static constexpr int LDS_BYTES = 6 * FS * 4 + 3 * JS * 8;
-};
+// CIC interpolation of staged component F: (ia, ib, ic) is the region index of the lower
+// corner, (wa, wb, wc) the weights of the upper corner.  The eight corners are fixed offsets
+// from one LDS address.
+template <class G, int DIM, int F>
+__device__ inline float interp_lds(const float* __restrict__ Fl, int ia, int ib, int ic, float wa,
+                                   float wb, float wc)
+{
+    constexpr unsigned X = G::fdim(F, 0), XY = X * G::fdim(F, 1);
+    // 24-bit multiply-adds (full rate); the index is non-negative and below 2^16
+    const unsigned idx = (unsigned)G::foff(F) + (unsigned)ia + __umul24((unsigned)ib, X) +
+                         (DIM == 3 ? __umul24((unsigned)ic, XY) : 0u);
+    unsigned ad = idx;
+    // opaque to constant reassociation: the corner offsets then fold into the ds_read2
+    // immediates of one address register
+    asm("" : "+v"(ad));
+    const float* p = Fl + ad;
+    const float a = p[0] + wa * (p[1] - p[0]);
+    const float b = p[X] + wa * (p[X + 1] - p[X]);
+    float r = a + wb * (b - a);
+    if (DIM == 3) {
+        const float* q = p + XY;
+        const float c = q[0] + wa * (q[1] - q[0]);
+        const float d = q[X] + wa * (q[X + 1] - q[X]);
+        const float r2 = c + wb * (d - c);
+        r = r + wc * (r2 - r);
+    }
+    return r;
+}
 
+// Gather from the staged tile: (rx, ry, rz) = cell - tile origin.  On a half-shifted axis the
+// lower node is the one at cell - 1/2 below the cell centre and cell + 1/2 above it.
+template <class G, int DIM>
+__device__ inline void gather_lds(const float* __restrict__ Fl, int rx, int ry, int rz, float ox,
+                                  float oy, float oz, f3& E, f3& B)
+{
+    const bool lx = ox < 0.5f, ly = oy < 0.5f, lz = oz < 0.5f;
+    const float hx = ox + (lx ? 0.5f : -0.5f), hy = oy + (ly ? 0.5f : -0.5f);
+    const float hz = oz + (lz ? 0.5f : -0.5f);
+    const int ix = rx + (lx ? 0 : 1), iy = ry + (ly ? 0 : 1), iz = rz + (lz ? 0 : 1);
+    E.x = interp_lds<G, DIM, 0>(Fl, ix, ry, rz, hx, oy, oz);
+    E.y = interp_lds<G, DIM, 1>(Fl, rx, iy, rz, ox, hy, oz);
+    E.z = interp_lds<G, DIM, 2>(Fl, rx, ry, iz, ox, oy, hz);
+    B.x = interp_lds<G, DIM, 3>(Fl, rx, iy, iz, ox, hy, hz);
+    B.y = interp_lds<G, DIM, 4>(Fl, ix, ry, iz, hx, oy, hz);
+    B.z = interp_lds<G, DIM, 5>(Fl, ix, iy, rz, hx, hy, oz);
+}
+
+// Stage field component F (and the ones after it) of the tile into its LDS region.
+template <class G, int DIM, int F, int NT>
+__device__ inline void stage_fields(float* __restrict__ Fl, const StepDev& P, const int t0[3],
+                                    const int ext[3], int tid)
+{
+    constexpr int X = G::fdim(F, 0), Y = G::fdim(F, 1), Z = G::fdim(F, 2);
+    constexpr int hx = yee_half(F, 0), hy = yee_half(F, 1), hz = DIM == 3 && yee_half(F, 2);
+    const float* src = F < 3 ? P.E[F] : P.B[F - 3];
+    for (int e = tid; e < X * Y * Z; e += NT) {
+        const int lx = e % X, ly = (e / X) % Y, lz = e / (X * Y);
+        float v = 0.f;
+        if (lx < ext[0] + 1 + hx && ly < ext[1] + 1 + hy && (DIM == 2 || lz < ext[2] + 1 + hz)) {
+            const int64_t g = (int64_t)(t0[0] - hx + lx) + (int64_t)P.sy * (t0[1] - hy + ly) +
+                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - hz + lz) : 0);
+            v = src[g];
+        }
+        Fl[G::foff(F) + e] = v;
+    }
+    if constexpr (F < 5) stage_fields<G, DIM, F + 1, NT>(Fl, P, t0, ext, tid);
+}
+
+// ------------------------------------------------------------------ the fused kernel
 template <int DIM>
 __device__ inline void tile_origin(const StepDev& P, int tile, int t0[3], int ext[3])
 {
@@ -340,58 +438,80 @@ __device__ inline float fixed_to_float(unsigned long long a, float unit)
     return (float)(((double)hi * 4294967296.0 + (double)lo) * (double)unit);
 }
 
+// Flush the tile current (interior + deposit halo) to the global arrays with float atomics.
+template <class G, int DIM, int NT>
+__device__ inline void flush_current(const unsigned long long* __restrict__ Jl, const StepDev& P,
+                                     const int t0[3], const int ext[3], int tid)
+{
+    for (int e = tid; e < G::JTOT; e += NT) {
+        const unsigned long long a = Jl[e];
+        if (a == 0ull) continue;
+        const int c = (e >= G::joff(1)) + (e >= G::joff(2));
+        const int r = e - (c == 0 ? 0 : (c == 1 ? G::joff(1) : G::joff(2)));
+        const int X = c == 0 ? G::jdim(0, 0) : (c == 1 ? G::jdim(1, 0) : G::jdim(2, 0));
+        const int Y = c == 0 ? G::jdim(0, 1) : (c == 1 ? G::jdim(1, 1) : G::jdim(2, 1));
+        const int lx = r % X, ly = (r / X) % Y, lz = r / (X * Y);
+        if (lx < ext[0] + (c == 0 ? 2 : 3) && ly < ext[1] + (c == 1 ? 2 : 3) &&
+            (DIM == 2 || lz < ext[2] + (c == 2 ? 2 : 3))) {
+            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
+                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
+            unsafeAtomicAdd(&P.J[c][g], fixed_to_float(a, P.junit));
+        }
+    }
+}
+
+template <class G, int DIM>
+__device__ inline LdsAcc<G> lds_acc(unsigned long long* Jl, int bx, int by, int bz)
+{
+    LdsAcc<G> acc;
+    acc.J = Jl;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        // 24-bit multiply-adds; region indices are non-negative
+        unsigned b = (unsigned)bx + __umul24((unsigned)G::jdim(c, 0), (unsigned)by) +
+                     (DIM == 3 ? __umul24((unsigned)(G::jdim(c, 0) * G::jdim(c, 1)), (unsigned)bz) : 0u);
+        acc.base[c] = (int)b;
+    }
+    return acc;
+}
+
 template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
 __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P, int blk, int nblk,
                                                                 int fuse)
 {
     using G = Geo<DIM, TX, TY, TZ>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[G::LDS_BYTES];
-    float* const F = reinterpret_cast<float*>(lds);                                   // E, B
-    unsigned long long* const Jl = reinterpret_cast<unsigned long long*>(lds + 6 * G::FS * 4);  // J
+    float* const Fl = reinterpret_cast<float*>(lds);                                      // E, B
+    unsigned long long* const Jl = reinterpret_cast<unsigned long long*>(lds + G::FBYTES);  // J
 
     const int tile = xcd_contiguous(blk, nblk);
     int t0[3], ext[3];
     tile_origin<DIM>(P, tile, t0, ext);
     const int tid = threadIdx.x;
 
-    // stage E, B of the tile and one guard cell per side
-    for (int e = tid; e < 6 * G::FS; e += NT) {
-        const int comp = e / G::FS;
-        const int r = e - comp * G::FS;
-        const int lx = r % G::FX, ly = (r / G::FX) % G::FY, lz = r / (G::FX * G::FY);
-        float v = 0.f;
-        if (lx < ext[0] + 2 && ly < ext[1] + 2 && (DIM == 2 || lz < ext[2] + 2)) {
-            const float* src = comp < 3 ? P.E[comp] : P.B[comp - 3];
-            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
-                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
-            v = src[g];
-        }
-        F[e] = v;
-    }
+    stage_fields<G, DIM, 0, NT>(Fl, P, t0, ext, tid);
     if (fuse)
-        for (int e = tid; e < 3 * G::JS; e += NT) Jl[e] = 0ull;
+        for (int e = tid; e < G::JTOT; e += NT) Jl[e] = 0ull;
     __syncthreads();
 
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     for (int s = 0; s < P.nsp; s++) {
         const SpeciesDev& S = P.sp[s];
-        const int beg = S.toff[tile], end = S.toff[tile + 1];
-        for (int slot = beg + tid; slot < end; slot += NT) {
-            const int src = S.perm[slot];
+        const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
+        for (uint32_t slot = beg + tid; slot < end; slot += NT) {
+            const uint32_t src = (uint32_t)ld_at(S.perm, slot);
             int cx, cy, cz;
-            P.cc.decode(S.cell_in[src], cx, cy, cz);
-            const float ox = S.off_in[0][src], oy = S.off_in[1][src];
-            const float oz = DIM == 3 ? S.off_in[2][src] : 0.f;
-            f3 u = mk(S.u_in[0][src], S.u_in[1][src], S.u_in[2][src]);
+            P.cc.decode(ld_at(S.cell_in, src), cx, cy, cz);
+            const float ox = ld_at(S.off_in[0], src), oy = ld_at(S.off_in[1], src);
+            const float oz = DIM == 3 ? ld_at(S.off_in[2], src) : 0.f;
+            f3 u = mk(ld_at(S.u_in[0], src), ld_at(S.u_in[1], src), ld_at(S.u_in[2], src));
 
-            const int lx = cx - t0[0] + 1, ly = cy - t0[1] + 1, lz = DIM == 3 ? cz - t0[2] + 1 : 0;
-            const bool in_tile = (unsigned)(lx - 1) < (unsigned)ext[0] &&
-                                 (unsigned)(ly - 1) < (unsigned)ext[1] &&
-                                 (DIM == 2 || (unsigned)(lz - 1) < (unsigned)ext[2]);
+            const int rx = cx - t0[0], ry = cy - t0[1], rz = DIM == 3 ? cz - t0[2] : 0;
+            const bool in_tile = (unsigned)rx < (unsigned)ext[0] && (unsigned)ry < (unsigned)ext[1] &&
+                                 (DIM == 2 || (unsigned)rz < (unsigned)ext[2]);
             f3 E, B;
             if (in_tile) {
-                auto fa = [&](int c) -> const float* { return F + c * G::FS; };
-                gather<DIM>(fa, G::FX, G::FX * G::FY, lx, ly, lz, ox, oy, oz, E, B);
+                gather_lds<G, DIM>(Fl, rx, ry, rz, ox, oy, oz, E, B);
             } else {
                 auto fa = [&](int c) -> const float* { return c < 3 ? P.E[c] : P.B[c - 3]; };
                 gather<DIM>(fa, P.sy, P.sz, cx, cy, cz, ox, oy, oz, E, B);
@@ -425,8 +545,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 const Shape3 SX = shape3(x0, x0 + D.x), SY = shape3(y0, y0 + D.y);
                 const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}};
                 if (in_tile) {
-                    LdsAcc<G::JX, G::JY, G::JZ> acc{
-                        Jl, (lx + hx - 1) + G::JX * ((ly + hy - 1) + G::JY * (DIM == 3 ? lz + hz - 1 : 0))};
+                    LdsAcc<G> acc = lds_acc<G, DIM>(Jl, rx + hx, ry + hy, rz + hz);
                     esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt * P.jscale, D.z);
                 } else {
                     GlobalAcc acc{P.J, (int64_t)(cx + hx - 1) + (int64_t)P.sy * (cy + hy - 1) +
@@ -435,13 +554,13 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                     esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
                 }
             } else {
-                S.ws_cell[slot] = P.cc.encode(cx, cy, cz);
-                S.ws_off[0][slot] = ox;
-                S.ws_off[1][slot] = oy;
-                if (DIM == 3) S.ws_off[2][slot] = oz;
-                S.ws_disp[0][slot] = D.x;
-                S.ws_disp[1][slot] = D.y;
-                S.ws_disp[2][slot] = D.z;
+                st_at(S.ws_cell, slot, P.cc.encode(cx, cy, cz));
+                st_at(S.ws_off[0], slot, ox);
+                st_at(S.ws_off[1], slot, oy);
+                if (DIM == 3) st_at(S.ws_off[2], slot, oz);
+                st_at(S.ws_disp[0], slot, D.x);
+                st_at(S.ws_disp[1], slot, D.y);
+                st_at(S.ws_disp[2], slot, D.z);
             }
 
             // ---- new position: x' = x^n + D, then (shearing box) the shear move
@@ -449,9 +568,9 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             float dyt = D.y;
             if (FRAME == kShear) dyt = D.y - P.sO * P.dt * (xr + 0.5f * D.x);
             int dcx, dcy, dcz = 0;
-            float nox = renorm(__fadd_rn(ox, D.x), dcx);
+            const float nox = renorm(__fadd_rn(ox, D.x), dcx);
             float noy = renorm(__fadd_rn(oy, dyt), dcy);
-            float noz = DIM == 3 ? renorm(__fadd_rn(oz, D.z), dcz) : 0.f;
+            const float noz = DIM == 3 ? renorm(__fadd_rn(oz, D.z), dcz) : 0.f;
             int ncx = cx + dcx, ncy = cy + dcy, ncz = cz + dcz;
             if (ncx >= nx || ncx < 0) {
                 // shearing-periodic x (Sec. 2.1): leaving through x_o re-enters at x_i with
@@ -461,8 +580,9 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 if (FRAME == kShear) {
                     int d2;
                     noy = renorm(__fadd_rn(noy, out ? P.dys_frac : -P.dys_frac), d2);
+                    // ncy in [-1, ny], dys_int in [0, ny): the sum lies in (-ny-2, 2ny+1)
                     ncy += (out ? P.dys_int : -P.dys_int) + d2;
-                    ncy %= ny;
+                    if (ncy >= ny) ncy -= ny;
                     if (ncy < 0) ncy += ny;
                 }
             }
@@ -476,10 +596,10 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
 
             // ---- leaky box (Sec. 4.1)
             if (FRAME == kLeaky) {
-                const uint32_t pid = S.id_in[src];
+                const uint32_t pid = ld_at(S.id_in, src);
                 if (P.leaky_mode == 0) {
-                    float rx = S.dr_in[0][src] + D.x, ry = S.dr_in[1][src] + D.y;
-                    float rz = S.dr_in[2][src] + D.z;
+                    float rx = ld_at(S.dr_in[0], src) + D.x, ry = ld_at(S.dr_in[1], src) + D.y;
+                    float rz = ld_at(S.dr_in[2], src) + D.z;
                     float m = fmaxf(fabsf(rx), fabsf(ry));
                     if (P.use_3vec) m = fmaxf(m, fabsf(rz));
                     if (m >= P.l_esc) {
@@ -508,9 +628,9 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                         u = mk(um * st * cp, um * st * sp, um * mu);
                         rx = ry = rz = 0.f;
                     }
-                    S.dr_out[0][slot] = rx;
-                    S.dr_out[1][slot] = ry;
-                    S.dr_out[2][slot] = rz;
+                    st_at(S.dr_out[0], slot, rx);
+                    st_at(S.dr_out[1], slot, ry);
+                    st_at(S.dr_out[2], slot, rz);
                 } else {
                     const double g2m1 = ((double)u.x * (double)u.x + (double)u.y * (double)u.y) +
                                         (double)u.z * (double)u.z;
@@ -525,44 +645,35 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 }
             }
 
-            S.cell_out[slot] = ncell;
-            S.off_out[0][slot] = nox;
-            S.off_out[1][slot] = noy;
-            if (DIM == 3) S.off_out[2][slot] = noz;
-            S.u_out[0][slot] = u.x;
-            S.u_out[1][slot] = u.y;
-            S.u_out[2][slot] = u.z;
-            if (P.track_ids) S.id_out[slot] = S.id_in[src];
+            st_at(S.cell_out, slot, ncell);
+            st_at(S.off_out[0], slot, nox);
+            st_at(S.off_out[1], slot, noy);
+            if (DIM == 3) st_at(S.off_out[2], slot, noz);
+            st_at(S.u_out[0], slot, u.x);
+            st_at(S.u_out[1], slot, u.y);
+            st_at(S.u_out[2], slot, u.z);
+            if (P.track_ids) st_at(S.id_out, slot, ld_at(S.id_in, src));
         }
     }
 
     if (!fuse) return;
     __syncthreads();
-    // flush the tile current (interior + deposit halo) with float atomics
-    for (int e = tid; e < 3 * G::JS; e += NT) {
-        const unsigned long long a = Jl[e];
-        if (a == 0ull) continue;
-        const float v = fixed_to_float(a, P.junit);
-        const int comp = e / G::JS;
-        const int r = e - comp * G::JS;
-        const int lx = r % G::JX, ly = (r / G::JX) % G::JY, lz = r / (G::JX * G::JY);
-        if (lx < ext[0] + 3 && ly < ext[1] + 3 && (DIM == 2 || lz < ext[2] + 3)) {
-            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
-                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
-            unsafeAtomicAdd(&P.J[comp][g], v);
-        }
-    }
+    flush_current<G, DIM, NT>(Jl, P, t0, ext, tid);
 }
 
+// 3D tiles: compact regions (48.4 KB of LDS for 8^3) let three workgroups share a CU, so the
+// register budget is set for 6 waves per SIMD.
 template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
-__global__ __launch_bounds__(NT) void gpd_kernel(StepDev P, int fuse)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 1)))
+void gpd_kernel(StepDev P, int fuse)
 {
     gpd_body<DIM, TX, TY, TZ, FRAME, NT>(P, (int)blockIdx.x, (int)gridDim.x, fuse);
 }
 
 // Many boxes in one launch: the blocks of unit u (one box's tiles) take its descriptor.
 template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
-__global__ __launch_bounds__(NT) void gpd_batch(const StepDev* __restrict__ t, UnitMap m)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 1)))
+void gpd_batch(const StepDev* __restrict__ t, UnitMap m)
 {
     const int u = unit_of(m, (int)blockIdx.x);
     gpd_body<DIM, TX, TY, TZ, FRAME, NT>(t[u], (int)blockIdx.x - (int)m.prefix[u],
@@ -575,33 +686,32 @@ template <int DIM, int TX, int TY, int TZ, int NT>
 __global__ __launch_bounds__(NT) void deposit_kernel(StepDev P)
 {
     using G = Geo<DIM, TX, TY, TZ>;
-    __shared__ unsigned long long Jl[3 * G::JS];
+    __shared__ unsigned long long Jl[G::JTOT];
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
     int t0[3], ext[3];
     tile_origin<DIM>(P, tile, t0, ext);
     const int tid = threadIdx.x;
-    for (int e = tid; e < 3 * G::JS; e += NT) Jl[e] = 0ull;
+    for (int e = tid; e < G::JTOT; e += NT) Jl[e] = 0ull;
     __syncthreads();
     for (int s = 0; s < P.nsp; s++) {
         const SpeciesDev& S = P.sp[s];
-        const int beg = S.toff[tile], end = S.toff[tile + 1];
-        for (int slot = beg + tid; slot < end; slot += NT) {
+        const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
+        for (uint32_t slot = beg + tid; slot < end; slot += NT) {
             int cx, cy, cz;
-            P.cc.decode(S.ws_cell[slot], cx, cy, cz);
-            const float ox = S.ws_off[0][slot], oy = S.ws_off[1][slot];
-            const float oz = DIM == 3 ? S.ws_off[2][slot] : 0.f;
-            const f3 D = mk(S.ws_disp[0][slot], S.ws_disp[1][slot], S.ws_disp[2][slot]);
-            const int lx = cx - t0[0] + 1, ly = cy - t0[1] + 1, lz = DIM == 3 ? cz - t0[2] + 1 : 0;
-            const bool in_tile = (unsigned)(lx - 1) < (unsigned)ext[0] &&
-                                 (unsigned)(ly - 1) < (unsigned)ext[1] &&
-                                 (DIM == 2 || (unsigned)(lz - 1) < (unsigned)ext[2]);
+            P.cc.decode(ld_at(S.ws_cell, slot), cx, cy, cz);
+            const float ox = ld_at(S.ws_off[0], slot), oy = ld_at(S.ws_off[1], slot);
+            const float oz = DIM == 3 ? ld_at(S.ws_off[2], slot) : 0.f;
+            const f3 D = mk(ld_at(S.ws_disp[0], slot), ld_at(S.ws_disp[1], slot),
+                            ld_at(S.ws_disp[2], slot));
+            const int rx = cx - t0[0], ry = cy - t0[1], rz = DIM == 3 ? cz - t0[2] : 0;
+            const bool in_tile = (unsigned)rx < (unsigned)ext[0] && (unsigned)ry < (unsigned)ext[1] &&
+                                 (DIM == 2 || (unsigned)rz < (unsigned)ext[2]);
             const int hx = ox >= 0.5f, hy = oy >= 0.5f, hz = DIM == 3 ? (oz >= 0.5f) : 0;
             const float x0 = ox - (float)hx, y0 = oy - (float)hy, z0 = oz - (float)hz;
             const Shape3 SX = shape3(x0, x0 + D.x), SY = shape3(y0, y0 + D.y);
             const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}};
             if (in_tile) {
-                LdsAcc<G::JX, G::JY, G::JZ> acc{
-                    Jl, (lx + hx - 1) + G::JX * ((ly + hy - 1) + G::JY * (DIM == 3 ? lz + hz - 1 : 0))};
+                LdsAcc<G> acc = lds_acc<G, DIM>(Jl, rx + hx, ry + hy, rz + hz);
                 esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt * P.jscale, D.z);
             } else {
                 GlobalAcc acc{P.J, (int64_t)(cx + hx - 1) + (int64_t)P.sy * (cy + hy - 1) +
@@ -612,19 +722,7 @@ __global__ __launch_bounds__(NT) void deposit_kernel(StepDev P)
         }
     }
     __syncthreads();
-    for (int e = tid; e < 3 * G::JS; e += NT) {
-        const unsigned long long a = Jl[e];
-        if (a == 0ull) continue;
-        const float v = fixed_to_float(a, P.junit);
-        const int comp = e / G::JS;
-        const int r = e - comp * G::JS;
-        const int lx = r % G::JX, ly = (r / G::JX) % G::JY, lz = r / (G::JX * G::JY);
-        if (lx < ext[0] + 3 && ly < ext[1] + 3 && (DIM == 2 || lz < ext[2] + 3)) {
-            const int64_t g = (int64_t)(t0[0] - 1 + lx) + (int64_t)P.sy * (t0[1] - 1 + ly) +
-                              (DIM == 3 ? (int64_t)P.sz * (t0[2] - 1 + lz) : 0);
-            unsafeAtomicAdd(&P.J[comp][g], v);
-        }
-    }
+    flush_current<G, DIM, NT>(Jl, P, t0, ext, tid);
 }
 
 // ------------------------------------------------------------------ launchers

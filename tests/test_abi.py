@@ -91,6 +91,7 @@ def _desc(**kw):
     dict(tile=(3, 3, 3)),
     dict(capacity=-1),
     dict(capacity=1 << 31),
+    dict(capacity=1 << 30),            # particle arrays use 32-bit byte offsets
     dict(n=(2048, 2048, 2048)),        # packed cell code needs 33 bits
     dict(dim=2, n=(64, 64, 5)),
 ])

@@ -115,9 +115,10 @@ def cpu_baseline(seconds=12.0):
 def serve_bench(args):
     """The served batch: 512 independent 2D box runs of 500 steps (see serve.py for the
     recipe).  (1) capacity: all runs queued at t = 0, admitted by HBM footprint, stepped together
-    by the batched step; (2) Poisson arrivals at 0.8 x capacity: p50/p99 run latency and
-    aggregate particle-steps/s; (3) one box at a time (per-box launches) on the first runs of the
-    same list; (4) runs sampled from the mix re-run alone: final energies within 1%."""
+    by the batched step, eagerly and replayed as HIP graphs (the faster mode serves the rest);
+    (2) Poisson arrivals at 0.8 x capacity: p50/p99 run latency and aggregate particle-steps/s;
+    (3) one box at a time (per-box launches) on the first runs of the same list; (4) runs sampled
+    from the mix re-run alone: final energies within 1%."""
     import numpy as np
     import torch
 
@@ -127,15 +128,21 @@ def serve_bench(args):
     # warm-up (module loads, allocator pools): a few runs each way, not timed
     warm = serve.make_specs(6, 5, seed=1)
     serve.serve(warm, budget, batched=True)
+    serve.serve(warm, budget, batched=True, graph=True)
     serve.serve(warm[:2], 0, batched=False)
     specs = serve.make_specs(args.runs, args.run_steps)
     print(f"[serve] capacity run: {len(specs)} runs queued at t=0", file=sys.stderr, flush=True)
     res, wall = serve.serve(specs, budget, batched=True)
-    cap = serve.summarize(res, wall)
+    cap_eager = serve.summarize(res, wall)
+    print("[serve] capacity run, batched step replayed as HIP graphs", file=sys.stderr, flush=True)
+    res, wall = serve.serve(serve.make_specs(args.runs, args.run_steps), budget, batched=True, graph=True)
+    cap_graph = serve.summarize(res, wall)
+    graph = cap_graph["particle_steps_per_s"] > cap_eager["particle_steps_per_s"]
+    cap = cap_graph if graph else cap_eager
     rate = 0.8 * cap["runs_per_s"]
     specs = serve.poisson_arrivals(serve.make_specs(args.runs, args.run_steps), rate)
-    print(f"[serve] Poisson run at {rate:.2f} runs/s", file=sys.stderr, flush=True)
-    res, wall = serve.serve(specs, budget, batched=True, keep_energies=True)
+    print(f"[serve] Poisson run at {rate:.2f} runs/s (graph={graph})", file=sys.stderr, flush=True)
+    res, wall = serve.serve(specs, budget, batched=True, keep_energies=True, graph=graph)
     mix = serve.summarize(res, wall)
     base_specs = serve.make_specs(args.runs, args.run_steps)[: args.baseline_runs]
     print(f"[serve] one box at a time: {len(base_specs)} runs", file=sys.stderr, flush=True)
@@ -171,7 +178,9 @@ def serve_bench(args):
         "config": {"workload": f"served_2d_{args.runs}runs_{args.run_steps}steps",
                    "runs": args.runs, "steps_per_run": args.run_steps,
                    "budget_gb": args.budget_gb, "arrival_rate_runs_per_s": rate,
-                   "capacity": cap, "poisson": mix, "one_at_a_time": base,
+                   "capacity": cap, "capacity_eager_batched": cap_eager,
+                   "capacity_graph_batched": cap_graph, "graph": graph,
+                   "poisson": mix, "one_at_a_time": base,
                    "batched_over_one_at_a_time": mix["particle_steps_per_s"] / base["particle_steps_per_s"],
                    "capacity_over_one_at_a_time": cap["particle_steps_per_s"] / base["particle_steps_per_s"],
                    "alone_vs_mix_max_rel_energy_diff": worst, "alone_vs_mix_runs": len(sample)},

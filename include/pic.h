@@ -53,6 +53,8 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_REMAP_CURRENT 2u
 /* pic_step flags */
 #define PIC_STEP_BATCHED 1u /* one launch per kernel for all boxes (box-descriptor tables) */
+#define PIC_STEP_GRAPH 2u   /* the batched step as a captured HIP graph, replayed while the box
+                               set and its launch shapes stay the same (implies BATCHED) */
 /* pic_box_desc.flags */
 #define PIC_BOX_TRACK_IDS 1u /* carry particle ids through the sort (always on for LEAKY) */
 
@@ -196,7 +198,13 @@ int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags);
    sort only; a particle found beyond the neighbouring tiles latches PIC_DERR_SORT on its box
    (that box's sort is then not valid).  Results equal the unbatched step's up to the order of
    the FP32 additions of the tile-halo current.  PIC_EINVAL if the boxes do not share one
-   stream, appear twice or have an unsupported tile shape. */
+   stream, appear twice or have an unsupported tile shape.
+   With PIC_STEP_GRAPH the table transfer and the launches of the batched step are captured
+   once as a HIP graph (stream capture on the shared stream, which must not be the null
+   stream) and replayed on later steps of the same box set with the same launch shapes: the
+   graph's copy node reads the tables the host has just written, so every replay runs that
+   step's arguments.  The first box holds up to 8 graphs (least recently used evicted); they are
+   freed with it.  Results are identical to the batched step without graphs. */
 int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
 
 /* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */

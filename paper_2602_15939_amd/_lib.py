@@ -19,6 +19,7 @@ REMAP_FIELDS, REMAP_CURRENT = 1, 2
 BOX_TRACK_IDS = 1
 DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT = 1, 2, 4, 8, 16
 STEP_BATCHED = 1
+STEP_GRAPH = 2
 
 
 class pic_box_desc(C.Structure):

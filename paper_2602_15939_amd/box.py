@@ -163,7 +163,9 @@ class Box:
         return L.pic_box_get(self.h)
 
 
-def step_many(boxes, batched=True):
+def step_many(boxes, batched=True, graph=False):
     """One whole step of several boxes sharing a stream: batched (one launch per kernel for all
-    boxes, through box-descriptor tables) or one box after another."""
-    L.pic_step([b.h for b in boxes], L.STEP_BATCHED if batched else 0)
+    boxes, through box-descriptor tables; graph=True replays it as a captured HIP graph) or one
+    box after another."""
+    flags = (L.STEP_BATCHED if batched else 0) | (L.STEP_GRAPH if graph else 0)
+    L.pic_step([b.h for b in boxes], flags)

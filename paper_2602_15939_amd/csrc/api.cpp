@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -81,6 +83,14 @@ struct pic_box {
         hipEvent_t copied = nullptr;  // the last transfer out of host has completed
     } stage[2];
     int stage_cur = 0;
+    // executable graphs of batched steps led by this box, keyed by the box set, the staging
+    // buffer and the launch sequence (grid sizes and table offsets); least recently used last
+    struct StepGraph {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<StepGraph> graphs;
+    uint64_t uid = 0;  // unique over the process lifetime (graph keys)
     bool sorted = false;
     bool deposit_pending = false;
     bool track_ids = false;
@@ -505,6 +515,11 @@ struct BatchPlan {
     hipStream_t st = nullptr;
     std::vector<char> buf;
     std::vector<std::function<hipError_t(const char*)>> launches;
+    std::vector<uint64_t> sig;  // launch sequence: kind, table offsets, units, blocks, shape
+    void note(uint64_t kind, size_t to, size_t po, int nu, int total, uint64_t extra)
+    {
+        sig.insert(sig.end(), {kind, (uint64_t)to, (uint64_t)po, (uint64_t)nu, (uint64_t)total, extra});
+    }
 
     size_t put(const void* p, size_t bytes)
     {
@@ -534,6 +549,7 @@ struct BatchPlan {
         int total;
         if (!stage(a, blocks, to, po, total)) return;
         const int nu = (int)a.size();
+        note(100 + (uint64_t)k, to, po, nu, total, (uint64_t)ydim);
         hipStream_t s = st;
         launches.push_back([=](const char* d) {
             return grid_batch(k, d + to, UnitMap{reinterpret_cast<const uint32_t*>(d + po), nu}, total,
@@ -547,6 +563,7 @@ struct BatchPlan {
         int total;
         if (!stage(a, blocks, to, po, total)) return;
         const int nu = (int)a.size();
+        note(200 + (uint64_t)k, to, po, nu, total, 0);
         hipStream_t s = st;
         launches.push_back([=](const char* d) {
             return sort_batch(k, d + to, UnitMap{reinterpret_cast<const uint32_t*>(d + po), nu}, total, s);
@@ -560,6 +577,9 @@ struct BatchPlan {
         if (!stage(a, blocks, to, po, total)) return;
         const int nu = (int)a.size();
         const int t[3] = {tile[0], tile[1], tile[2]};
+        note(300, to, po, nu, total,
+             (uint64_t)dim | (uint64_t)tile[0] << 8 | (uint64_t)tile[1] << 16 | (uint64_t)tile[2] << 24 |
+                 (uint64_t)frame << 32);
         hipStream_t s = st;
         launches.push_back([=](const char* d) {
             return launch_gather_push_batch(reinterpret_cast<const StepDev*>(d + to),
@@ -589,7 +609,7 @@ void plan_fill(std::vector<FillArgs>& a, std::vector<uint32_t>& blk, const GridD
     }
 }
 
-int32_t step_batched(pic_box* const* boxes, int nb)
+int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
 {
     hipStream_t st = boxes[0]->st;
     for (int i = 0; i < nb; i++) {
@@ -845,7 +865,8 @@ int32_t step_batched(pic_box* const* boxes, int nb)
 
     // ---- stage the tables, one transfer, then the launches in order
     pic_box* b0 = boxes[0];
-    auto& sg = b0->stage[b0->stage_cur];
+    const int sidx = b0->stage_cur;
+    auto& sg = b0->stage[sidx];
     b0->stage_cur ^= 1;
     const size_t bytes = plan.buf.size();
     if (bytes > sg.cap) {
@@ -854,6 +875,8 @@ int32_t step_batched(pic_box* const* boxes, int nb)
         if (sg.host) hipHostFree(sg.host);
         if (sg.dev) hipFree(sg.dev);
         sg.host = sg.dev = nullptr;
+        for (auto& g : b0->graphs) hipGraphExecDestroy(g.exec);  // they read the old buffer
+        b0->graphs.clear();
         sg.cap = 0;
         const size_t cap = std::max(bytes * 2, (size_t)1 << 20);
         if (hipHostMalloc(&sg.host, cap) != hipSuccess) return PIC_ENOMEM;
@@ -864,14 +887,63 @@ int32_t step_batched(pic_box* const* boxes, int nb)
     } else if (sg.copied && hipEventSynchronize(sg.copied) != hipSuccess) {
         return PIC_EDEVICE;
     }
-    if (bytes) {
-        std::memcpy(sg.host, plan.buf.data(), bytes);
-        if (hipMemcpyAsync(sg.dev, sg.host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return PIC_EDEVICE;
-        if (hipEventRecord(sg.copied, st) != hipSuccess) return PIC_EDEVICE;
-    }
+    if (bytes) std::memcpy(sg.host, plan.buf.data(), bytes);
     const char* dev = static_cast<const char*>(sg.dev);
-    for (auto& f : plan.launches)
-        if (f(dev) != hipSuccess) return PIC_EDEVICE;
+    auto enqueue = [&]() -> int32_t {
+        if (bytes && hipMemcpyAsync(sg.dev, sg.host, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+        for (auto& f : plan.launches)
+            if (f(dev) != hipSuccess) return PIC_EDEVICE;
+        return PIC_OK;
+    };
+    if (!graph || !bytes) {
+        if (enqueue()) return PIC_EDEVICE;
+        if (bytes && hipEventRecord(sg.copied, st) != hipSuccess) return PIC_EDEVICE;
+        return PIC_OK;
+    }
+    // graph mode: the step's transfer and launches form one graph, captured the first time this
+    // box set and launch sequence meet this staging buffer and replayed afterwards (the memcpy
+    // node reads the tables the host has just written to the pinned buffer)
+    std::vector<uint64_t> key;
+    key.reserve(plan.sig.size() + nb + 4);
+    key.push_back((uint64_t)sidx);
+    key.push_back((uint64_t)(uintptr_t)sg.dev);
+    key.push_back((uint64_t)bytes);
+    for (int i = 0; i < nb; i++) key.push_back(boxes[i]->uid);
+    key.insert(key.end(), plan.sig.begin(), plan.sig.end());
+    auto& cache = b0->graphs;
+    size_t hit = cache.size();
+    for (size_t i = 0; i < cache.size(); i++)
+        if (cache[i].key == key) {
+            hit = i;
+            break;
+        }
+    if (hit == cache.size()) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EDEVICE;
+        const int32_t er = enqueue();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        if (er || ec != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            return PIC_EDEVICE;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ei != hipSuccess) return PIC_EDEVICE;
+        constexpr size_t kMaxGraphs = 8;
+        if (cache.size() >= kMaxGraphs) {
+            hipGraphExecDestroy(cache.back().exec);
+            cache.pop_back();
+        }
+        cache.insert(cache.begin(), pic_box::StepGraph{std::move(key), ex});
+        hit = 0;
+    } else if (hit != 0) {
+        std::rotate(cache.begin(), cache.begin() + hit, cache.begin() + hit + 1);
+        hit = 0;
+    }
+    if (hipGraphLaunch(cache[hit].exec, st) != hipSuccess) return PIC_EDEVICE;
+    if (hipEventRecord(sg.copied, st) != hipSuccess) return PIC_EDEVICE;
     return PIC_OK;
 }
 
@@ -906,6 +978,7 @@ int32_t pic_box_destroy(pic_box* b)
 {
     if (!b) return PIC_OK;
     hipStreamSynchronize(b->st);
+    for (auto& g : b->graphs) hipGraphExecDestroy(g.exec);
     for (auto& sg : b->stage) {
         if (sg.host) hipHostFree(sg.host);
         if (sg.dev) hipFree(sg.dev);
@@ -948,6 +1021,8 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         if (d->capacity[s] < 0 || d->capacity[s] >= (1ll << 30)) return PIC_EINVAL;  // 32-bit byte offsets
 
     pic_box* b = new (std::nothrow) pic_box();
+    static std::atomic<uint64_t> next_uid{0};
+    if (b) b->uid = ++next_uid;
     if (!b) return PIC_ENOMEM;
     b->d = *d;
     b->st = static_cast<hipStream_t>(d->stream);
@@ -1262,7 +1337,8 @@ int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags)
 int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
 {
     int32_t r = check_boxes(boxes, nb);
-    if (!r && (flags & PIC_STEP_BATCHED)) return step_batched(boxes, nb);
+    if (!r && (flags & (PIC_STEP_BATCHED | PIC_STEP_GRAPH)))
+        return step_batched(boxes, nb, (flags & PIC_STEP_GRAPH) != 0);
     for (int i = 0; i < nb && !r; i++) {
         pic_box* b = boxes[i];
         r = sort_box(b);

@@ -224,33 +224,33 @@ __device__ inline void esirkepov(Acc& acc, const Shape3& X, const Shape3& Y, con
     const Use3 UX = use3(X), UY = use3(Y);
     if (DIM == 3) {
         const Use3 UZ = use3(Z);
+        // transverse factors with the charge factor q/dt folded in, so that every term is one
+        // product of a DS value and a factor
+        const float qh = 0.5f * q_dt, qt = (1.f / 3.f) * q_dt;
         float z1[3], z2[3], y1[3], y2[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            z1[c] = Z.s0[c] + 0.5f * Z.ds[c];
-            z2[c] = 0.5f * Z.s0[c] + (1.f / 3.f) * Z.ds[c];
-            y1[c] = Y.s0[c] + 0.5f * Y.ds[c];
-            y2[c] = 0.5f * Y.s0[c] + (1.f / 3.f) * Y.ds[c];
+            z1[c] = q_dt * Z.s0[c] + qh * Z.ds[c];
+            z2[c] = qh * Z.s0[c] + qt * Z.ds[c];
+            y1[c] = q_dt * Y.s0[c] + qh * Y.ds[c];
+            y2[c] = qh * Y.s0[c] + qt * Y.ds[c];
         }
-        const float xl = -q_dt * X.ds[0], xh = q_dt * X.ds[2];
-        const float yl = -q_dt * Y.ds[0], yh = q_dt * Y.ds[2];
-        const float zl = -q_dt * Z.ds[0], zh = q_dt * Z.ds[2];
 #pragma unroll
         for (int b = 0; b < 3; b++)
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 const bool yz = used(UY, b) && used(UZ, c);
                 const float Pyz = Y.s0[b] * z1[c] + Y.ds[b] * z2[c];
-                acc.add(0, 0, b, c, xl * Pyz, UX.e0 && yz);
-                acc.add(0, 1, b, c, xh * Pyz, UX.e2 && yz);
+                acc.add(0, 0, b, c, -X.ds[0] * Pyz, UX.e0 && yz);
+                acc.add(0, 1, b, c, X.ds[2] * Pyz, UX.e2 && yz);
                 const bool xz = used(UX, b) && used(UZ, c);
                 const float Pxz = X.s0[b] * z1[c] + X.ds[b] * z2[c];
-                acc.add(1, b, 0, c, yl * Pxz, UY.e0 && xz);
-                acc.add(1, b, 1, c, yh * Pxz, UY.e2 && xz);
+                acc.add(1, b, 0, c, -Y.ds[0] * Pxz, UY.e0 && xz);
+                acc.add(1, b, 1, c, Y.ds[2] * Pxz, UY.e2 && xz);
                 const bool xy = used(UX, b) && used(UY, c);
                 const float Pxy = X.s0[b] * y1[c] + X.ds[b] * y2[c];
-                acc.add(2, b, c, 0, zl * Pxy, UZ.e0 && xy);
-                acc.add(2, b, c, 1, zh * Pxy, UZ.e2 && xy);
+                acc.add(2, b, c, 0, -Z.ds[0] * Pxy, UZ.e0 && xy);
+                acc.add(2, b, c, 1, Z.ds[2] * Pxy, UZ.e2 && xy);
             }
     } else {
         const float xl = -q_dt * X.ds[0], xh = q_dt * X.ds[2];
@@ -499,6 +499,8 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
         const SpeciesDev& S = P.sp[s];
         const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
         for (uint32_t slot = beg + tid; slot < end; slot += NT) {
+            uint32_t so = slot;
+            asm("" : "+v"(so));  // keeps the 32-bit offset form (scalar base) for the stores
             const uint32_t src = (uint32_t)ld_at(S.perm, slot);
             int cx, cy, cz;
             P.cc.decode(ld_at(S.cell_in, src), cx, cy, cz);
@@ -554,13 +556,13 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                     esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt, D.z);
                 }
             } else {
-                st_at(S.ws_cell, slot, P.cc.encode(cx, cy, cz));
-                st_at(S.ws_off[0], slot, ox);
-                st_at(S.ws_off[1], slot, oy);
-                if (DIM == 3) st_at(S.ws_off[2], slot, oz);
-                st_at(S.ws_disp[0], slot, D.x);
-                st_at(S.ws_disp[1], slot, D.y);
-                st_at(S.ws_disp[2], slot, D.z);
+                st_at(S.ws_cell, so, P.cc.encode(cx, cy, cz));
+                st_at(S.ws_off[0], so, ox);
+                st_at(S.ws_off[1], so, oy);
+                if (DIM == 3) st_at(S.ws_off[2], so, oz);
+                st_at(S.ws_disp[0], so, D.x);
+                st_at(S.ws_disp[1], so, D.y);
+                st_at(S.ws_disp[2], so, D.z);
             }
 
             // ---- new position: x' = x^n + D, then (shearing box) the shear move
@@ -628,9 +630,9 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                         u = mk(um * st * cp, um * st * sp, um * mu);
                         rx = ry = rz = 0.f;
                     }
-                    st_at(S.dr_out[0], slot, rx);
-                    st_at(S.dr_out[1], slot, ry);
-                    st_at(S.dr_out[2], slot, rz);
+                    st_at(S.dr_out[0], so, rx);
+                    st_at(S.dr_out[1], so, ry);
+                    st_at(S.dr_out[2], so, rz);
                 } else {
                     const double g2m1 = ((double)u.x * (double)u.x + (double)u.y * (double)u.y) +
                                         (double)u.z * (double)u.z;
@@ -645,14 +647,14 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 }
             }
 
-            st_at(S.cell_out, slot, ncell);
-            st_at(S.off_out[0], slot, nox);
-            st_at(S.off_out[1], slot, noy);
-            if (DIM == 3) st_at(S.off_out[2], slot, noz);
-            st_at(S.u_out[0], slot, u.x);
-            st_at(S.u_out[1], slot, u.y);
-            st_at(S.u_out[2], slot, u.z);
-            if (P.track_ids) st_at(S.id_out, slot, ld_at(S.id_in, src));
+            st_at(S.cell_out, so, ncell);
+            st_at(S.off_out[0], so, nox);
+            st_at(S.off_out[1], so, noy);
+            if (DIM == 3) st_at(S.off_out[2], so, noz);
+            st_at(S.u_out[0], so, u.x);
+            st_at(S.u_out[1], so, u.y);
+            st_at(S.u_out[2], so, u.z);
+            if (P.track_ids) st_at(S.id_out, so, ld_at(S.id_in, src));
         }
     }
 

@@ -134,10 +134,21 @@ def _energies(box: Box):
 ADMIT_PER_STEP = 8  # runs built per loop turn: building overlaps the GPU's steps
 
 
-def serve(specs, budget_bytes, batched=True, keep_energies=False, clock=time.perf_counter):
+def serve(specs, budget_bytes, batched=True, keep_energies=False, graph=False,
+          clock=time.perf_counter):
     """Run every spec (arrival times relative to the call) and return the results in
     completion order.  batched=False steps the active boxes one at a time (per-box launches);
-    with admission of one run at a time that is the one-box-at-a-time baseline."""
+    with admission of one run at a time that is the one-box-at-a-time baseline.  graph=True
+    replays the batched step as a captured HIP graph while the set of active boxes is unchanged
+    (newly admitted runs take their first step, whose sort differs, before joining the set)."""
+    if graph:
+        st = torch.cuda.Stream()  # graph capture needs a stream other than the null stream
+        with torch.cuda.stream(st):
+            return _serve(specs, budget_bytes, batched, keep_energies, True, clock)
+    return _serve(specs, budget_bytes, batched, keep_energies, False, clock)
+
+
+def _serve(specs, budget_bytes, batched, keep_energies, graph, clock):
     pending = sorted(specs, key=lambda s: s.arrival)
     active = []  # [spec, box, steps_done, admitted]
     used = 0
@@ -147,30 +158,39 @@ def serve(specs, budget_bytes, batched=True, keep_energies=False, clock=time.per
     i = 0
     while i < len(pending) or active:
         now = clock() - t0
-        admitted = 0
-        while i < len(pending) and pending[i].arrival <= now and admitted < ADMIT_PER_STEP and (
-                not active or used + footprint(pending[i]) <= budget_bytes):
-            admitted += 1
+        admitted = []
+        while i < len(pending) and pending[i].arrival <= now and len(admitted) < ADMIT_PER_STEP and (
+                not (active or admitted) or used + footprint(pending[i]) <= budget_bytes):
             sp = pending[i]
             tb = clock()
-            active.append([sp, build_box(sp), 0, now])
+            admitted.append([sp, build_box(sp), 0, now])
             serve.build_s += clock() - tb
             used += footprint(sp)
             i += 1
             now = clock() - t0
-        if not active:
+        if not active and not admitted:
             time.sleep(max(0.0, min(pending[i].arrival - now, 0.01)))
             continue
-        boxes = [a[1] for a in active]
         ts = clock()
         if batched:
-            step_many(boxes, batched=True)
+            if graph and admitted:
+                step_many([a[1] for a in admitted], batched=True)
+                for a in admitted:
+                    a[2] += 1
+            elif admitted:
+                active.extend(admitted)
+                admitted = []
+            if active:
+                step_many([a[1] for a in active], batched=True, graph=graph)
+                for a in active:
+                    a[2] += 1
+            active.extend(admitted)
         else:
-            for b in boxes:
-                step_many([b], batched=False)
+            active.extend(admitted)
+            for a in active:
+                step_many([a[1]], batched=False)
+                a[2] += 1
         serve.step_s += clock() - ts
-        for a in active:
-            a[2] += 1
         finished = [a for a in active if a[2] >= a[0].steps]
         if finished:
             torch.cuda.synchronize()

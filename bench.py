@@ -125,6 +125,7 @@ def serve_bench(args):
     from paper_2602_15939_amd import serve
 
     budget = int(args.budget_gb * 2**30)
+    tiles = serve.tune_tiles(log=lambda m: print(m, file=sys.stderr, flush=True))
     # warm-up (module loads, allocator pools): a few runs each way, not timed
     warm = serve.make_specs(6, 5, seed=1)
     serve.serve(warm, budget, batched=True)
@@ -178,6 +179,8 @@ def serve_bench(args):
         "config": {"workload": f"served_2d_{args.runs}runs_{args.run_steps}steps",
                    "runs": args.runs, "steps_per_run": args.run_steps,
                    "budget_gb": args.budget_gb, "arrival_rate_runs_per_s": rate,
+                   "tiles": {f"{n}^2 ppc{serve.PPC_CLASSES[k][0]}-{serve.PPC_CLASSES[k][1]}":
+                             "x".join(map(str, t[:2])) for (n, k), t in sorted(tiles.items())},
                    "capacity": cap, "capacity_eager_batched": cap_eager,
                    "capacity_graph_batched": cap_graph, "graph": graph,
                    "poisson": mix, "one_at_a_time": base,
@@ -198,6 +201,8 @@ def main():
     ap.add_argument("--seed", type=int, default=20260216)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for profiles)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shape instead of pic_autotune's choice")
     ap.add_argument("--serve", action="store_true",
                     help="the served batch of independent 2D boxes instead of the 3D box")
     ap.add_argument("--runs", type=int, default=512)
@@ -219,6 +224,11 @@ def main():
     w = workload_shear3d(n=args.n)
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
     box, npart = make_box(w, args.seed)
+    tuned = None
+    if not args.no_autotune:
+        tile, ms = box.autotune(trials=2)
+        tuned = {"tile": list(tile), "fused_kernel_ms": {"x".join(map(str, k)): v for k, v in ms.items()}}
+        print(f"[bench] autotuned tile {tile}: {tuned['fused_kernel_ms']}", file=sys.stderr, flush=True)
     h = [box.h]
     st = torch.cuda.current_stream()
 
@@ -276,7 +286,7 @@ def main():
                    "dt": w["dt"], "maxwell_iters": w["maxwell_iters"],
                    "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": npart / (gpd_ms * 1e-3),
                    "gpd_algorithmic_bytes": nbytes, "slow_path_particles": int(info.n_slow),
-                   "kernel_source_hash": kernel_source_hash()},
+                   "kernel_source_hash": kernel_source_hash(), "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }

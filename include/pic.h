@@ -55,6 +55,8 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_STEP_BATCHED 1u /* one launch per kernel for all boxes (box-descriptor tables) */
 #define PIC_STEP_GRAPH 2u   /* the batched step as a captured HIP graph, replayed while the box
                                set and its launch shapes stay the same (implies BATCHED) */
+/* pic_autotune flags */
+#define PIC_TUNE_BATCHED 1u /* only the tile shapes the batched step supports */
 /* pic_box_desc.flags */
 #define PIC_BOX_TRACK_IDS 1u /* carry particle ids through the sort (always on for LEAKY) */
 
@@ -89,7 +91,9 @@ typedef struct pic_box_desc {
     int64_t capacity[2];     /* maximum particle count per species (below 2^30) */
     uint64_t seed;           /* Philox4x32-10 key */
     uint32_t box_id;         /* fourth Philox counter word */
-    int32_t tile[3];         /* tile shape in cells (0 = default: 8^3 in 3D, 16x16 in 2D) */
+    int32_t tile[3];         /* tile shape in cells (0 = default: 8^3 in 3D, 16x16 in 2D;
+                                supported: 8^3, 4^3; 16x16, 8x8, 32x16, 32x32); pic_autotune
+                                picks one by measurement */
     int32_t maxwell_iters;   /* shearing box: fixed-point iterations per step (0 = 8) */
     uint32_t flags;          /* PIC_BOX_* */
     void* stream;            /* hipStream_t */
@@ -150,6 +154,27 @@ int32_t pic_get_particles(pic_box* box, int32_t species, int64_t* n_out, int32_t
    n_tiles+1 tile offsets.  Synchronises. */
 int32_t pic_get_sort(pic_box* box, int32_t species, int32_t* perm_dev, int32_t* offsets_dev,
                      int32_t* n_tiles_out);
+
+/* Tile-shape autotuner.  For every supported tile shape (PIC_TUNE_BATCHED: those of the batched
+   step) it re-tiles the box, sorts its particles (radix sort) and times the fused
+   gather-push-deposit kernel with HIP events on the box stream, trials + 1 times (the first
+   is a warm-up; the fastest of the rest counts).  The kernel writes into the spare particle
+   buffers and the current array, so the box's particles, fields and time are unchanged; the
+   current array holds no result until the next step, and error bits and counters are
+   restored.  The box keeps the fastest shape among those that admit the neighbour-migration
+   sort (any shape if none does), and its next sort is a radix sort.  tile_out[3] receives
+   the shape; ms_out[i] (i < max_out, may be NULL) the time of candidate i in the order of
+   the supported list; *n_out (may be NULL) the number of candidates.  Synchronises.
+   PIC_ESTATE with no particles loaded or an unfused push awaiting pic_deposit; PIC_EINVAL for
+   trials outside 1..64.  Tile-indexed workspace is sized at pic_box_create for every shape. */
+int32_t pic_autotune(pic_box* box, uint32_t flags, int32_t trials, int32_t* tile_out,
+                     float* ms_out, int32_t max_out, int32_t* n_out);
+
+/* The supported tile shapes of a dimension (PIC_TUNE_BATCHED: those of the batched step), in
+   the order pic_autotune reports them, the default first: shapes_out[3*i + k] (host memory,
+   room for max_out shapes) receives edge k of shape i.  Returns the number of shapes (it may
+   exceed max_out), or PIC_EINVAL for a dimension other than 2 or 3. */
+int32_t pic_tile_candidates(int32_t dim, uint32_t flags, int32_t* shapes_out, int32_t max_out);
 
 /* ---- the hot path (each call acts on nb boxes; nb = 1 is the single-box case) ---- */
 

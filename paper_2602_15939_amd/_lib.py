@@ -20,6 +20,7 @@ BOX_TRACK_IDS = 1
 DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT = 1, 2, 4, 8, 16
 STEP_BATCHED = 1
 STEP_GRAPH = 2
+TUNE_BATCHED = 1
 
 
 class pic_box_desc(C.Structure):
@@ -81,6 +82,9 @@ def lib():
             "pic_escape_compact": ([boxes, i32, u32], i32),
             "pic_step": ([boxes, i32, u32], i32),
             "pic_box_get": ([vp, C.POINTER(pic_box_info)], i32),
+            "pic_autotune": ([vp, u32, i32, C.POINTER(i32), C.POINTER(C.c_float), i32,
+                              C.POINTER(i32)], i32),
+            "pic_tile_candidates": ([i32, u32, C.POINTER(i32), i32], i32),
             "pic_status_str": ([i32], C.c_char_p),
             "pic_device_copy": ([vp, vp, i64, vp], i32),
         }
@@ -101,6 +105,24 @@ def check(rc: int, what: str = "") -> None:
 def box_array(handles):
     arr = (C.c_void_p * len(handles))(*handles)
     return C.cast(arr, C.POINTER(C.c_void_p)), arr
+
+
+def pic_autotune(h, flags=0, trials=3):
+    """(chosen tile shape, {candidate shape: ms}) of the tile-shape autotuner."""
+    tile = (C.c_int32 * 3)()
+    ms = (C.c_float * 8)()
+    n = C.c_int32()
+    check(lib().pic_autotune(h, flags, trials, tile, ms, 8, C.byref(n)), "pic_autotune")
+    return tuple(tile), list(ms[: n.value])
+
+
+def pic_tile_candidates(dim, flags=0):
+    """Supported tile shapes, in the order pic_autotune reports its times."""
+    out = (C.c_int32 * 24)()
+    n = lib().pic_tile_candidates(dim, flags, out, 8)
+    if n < 0:
+        check(n, "pic_tile_candidates")
+    return [tuple(out[3 * i: 3 * i + 3]) for i in range(n)]
 
 
 def pic_device_copy(dst_ptr, src_ptr, nbytes, stream_ptr=None):

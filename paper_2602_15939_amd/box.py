@@ -159,6 +159,13 @@ class Box:
     def step(self):
         L.pic_step([self.h])
 
+    def autotune(self, batched=False, trials=3):
+        """Pick the tile shape by timing the fused kernel on this machine's particles for every
+        supported shape; returns (shape, {shape: ms})."""
+        tile, ms = L.pic_autotune(self.h, L.TUNE_BATCHED if batched else 0, trials)
+        shapes = L.pic_tile_candidates(self.dim, L.TUNE_BATCHED if batched else 0)
+        return tile, dict(zip(shapes, ms))
+
     def info(self) -> L.pic_box_info:
         return L.pic_box_get(self.h)
 

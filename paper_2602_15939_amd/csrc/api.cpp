@@ -324,6 +324,41 @@ int32_t check_boxes(pic_box* const* boxes, int32_t nb)
     return PIC_OK;
 }
 
+// Tile decomposition of the box (power-of-two tile edges); the migration sort applies with whole
+// tiles and, on every axis, one tile or at least three (so that the steps -1, 0, +1 reach
+// distinct tiles); the shearing box needs the x crossings visible in the tile index.
+void set_tiling(pic_box* b, const int tile[3])
+{
+    for (int k = 0; k < 3; k++) {
+        b->tile[k] = tile[k];
+        b->tl.lt[k] = ceil_log2(tile[k]);
+        b->tl.nt[k] = (b->n[k] + tile[k] - 1) / tile[k];
+    }
+    b->tl.n_tiles = b->tl.nt[0] * b->tl.nt[1] * b->tl.nt[2];
+    b->mig_ok = true;
+    for (int k = 0; k < 3; k++) {
+        b->mg.nt[k] = b->tl.nt[k];
+        b->mg.lt[k] = b->tl.lt[k];
+        if (b->n[k] % tile[k] != 0 || b->tl.nt[k] == 2) b->mig_ok = false;
+    }
+    if (b->d.frame == PIC_FRAME_SHEAR && b->tl.nt[0] < 3) b->mig_ok = false;
+    b->mg.n_tiles = b->tl.n_tiles;
+}
+
+// the largest tile count over the supported shapes (tile-indexed workspace is sized for it)
+int max_tiles(int dim, const int n[3])
+{
+    int c[8][3];
+    const int nc = tile_candidates(dim, false, c, 8);
+    int m = 1;
+    for (int i = 0; i < nc; i++) {
+        int t = 1;
+        for (int k = 0; k < 3; k++) t *= (n[k] + c[i][k] - 1) / c[i][k];
+        m = std::max(m, t);
+    }
+    return m;
+}
+
 int32_t sort_box(pic_box* b)
 {
     if (b->deposit_pending) return PIC_ESTATE;  // the unfused deposit reads this sort's slots
@@ -1027,30 +1062,13 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     b->d = *d;
     b->st = static_cast<hipStream_t>(d->stream);
     b->dim = d->dim;
-    for (int k = 0; k < 3; k++) {
-        b->n[k] = n[k];
-        b->tile[k] = tile[k];
-    }
+    for (int k = 0; k < 3; k++) b->n[k] = n[k];
     b->cc.b0 = bits[0];
     b->cc.b1 = bits[1];
     b->cc.m0 = (1u << bits[0]) - 1u;
     b->cc.m1 = (1u << bits[1]) - 1u;
-    for (int k = 0; k < 3; k++) {
-        b->tl.lt[k] = ceil_log2(tile[k]);
-        b->tl.nt[k] = (n[k] + tile[k] - 1) / tile[k];
-    }
-    b->tl.n_tiles = b->tl.nt[0] * b->tl.nt[1] * b->tl.nt[2];
-    // migration sort: whole tiles, and on every axis one tile or at least three (so that the
-    // three steps -1, 0, +1 reach distinct tiles); the shearing box needs the x crossings
-    // visible in the tile index
-    b->mig_ok = true;
-    for (int k = 0; k < 3; k++) {
-        b->mg.nt[k] = b->tl.nt[k];
-        b->mg.lt[k] = b->tl.lt[k];
-        if (n[k] % tile[k] != 0 || b->tl.nt[k] == 2) b->mig_ok = false;
-    }
-    if (d->frame == PIC_FRAME_SHEAR && b->tl.nt[0] < 3) b->mig_ok = false;
-    b->mg.n_tiles = b->tl.n_tiles;
+    set_tiling(b, tile);
+    const int tiles_ws = max_tiles(b->dim, n);  // any supported tiling fits the workspace
     GridDev& G = b->G;
     G.dim = b->dim;
     for (int k = 0; k < 3; k++) {
@@ -1105,15 +1123,15 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         }
         if (!r) r = dalloc(b, S.sb.hist, sort_hist_words((int64_t)cap));
         if (!r) r = dalloc(b, S.sb.scratch, scan_scratch_words((int64_t)sort_hist_words((int64_t)cap)));
-        for (int k = 0; k < 2 && !r; k++) r = dalloc(b, S.toff[k], (size_t)b->tl.n_tiles + 2);
-        const size_t nt = (size_t)b->tl.n_tiles;
+        for (int k = 0; k < 2 && !r; k++) r = dalloc(b, S.toff[k], (size_t)tiles_ws + 2);
+        const size_t nt = (size_t)tiles_ws;
         if (!r) r = dalloc(b, S.sb.mcnt, nt * kMigDirs);
         if (!r) r = dalloc(b, S.sb.mpre, nt * kMigDirs);
         if (!r) r = dalloc(b, S.sb.tot, nt + 1);
         if (!r) r = dalloc(b, S.sb.start, nt + 1);
         if (!r) r = dalloc(b, S.sb.dcnt, nt + 1);
         if (!r) r = dalloc(b, S.sb.dpre, nt + 1);
-        if (!r) r = dalloc(b, S.sb.mscratch, migrate_scratch_words(b->tl.n_tiles));
+        if (!r) r = dalloc(b, S.sb.mscratch, migrate_scratch_words(tiles_ws));
         if (!r) r = dalloc(b, S.sb.fallback, 1);
         if (!r) r = dalloc(b, S.n_live, 2);
         if (!r && b->alloc_pass != 1 && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess)
@@ -1332,6 +1350,96 @@ int32_t pic_maxwell_step(pic_box* const* boxes, int32_t nb, uint32_t)
 int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags)
 {
     return pic_tile_sort(boxes, nb, flags);
+}
+
+int32_t pic_tile_candidates(int32_t dim, uint32_t flags, int32_t* shapes_out, int32_t max_out)
+{
+    if ((dim != 2 && dim != 3) || max_out < 0 || (max_out > 0 && !shapes_out)) return PIC_EINVAL;
+    int c[8][3];
+    const int n = tile_candidates(dim, (flags & PIC_TUNE_BATCHED) != 0, c, 8);
+    for (int i = 0; i < n && i < max_out; i++)
+        for (int k = 0; k < 3; k++) shapes_out[3 * i + k] = c[i][k];
+    return n;
+}
+
+int32_t pic_autotune(pic_box* b, uint32_t flags, int32_t trials, int32_t* tile_out, float* ms_out,
+                     int32_t max_out, int32_t* n_out)
+{
+    if (!b || !tile_out || trials < 1 || trials > 64) return PIC_EINVAL;
+    if (b->deposit_pending) return PIC_ESTATE;
+    int64_t live = 0;
+    for (int s = 0; s < b->nsp; s++) live += b->sp[s].n_upper;
+    if (live == 0) return PIC_ESTATE;  // nothing to time
+    int cand[8][3];
+    const int nc = tile_candidates(b->dim, (flags & PIC_TUNE_BATCHED) != 0, cand, 8);
+    hipStream_t st = b->st;
+    // the trials leave nothing the caller sees: error bits, counters and the slot counts the
+    // next sort starts from are restored after
+    uint32_t err[4];
+    unsigned long long ctr[4];
+    int32_t nlive[kMaxSpecies][2];
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(err, b->err, sizeof err, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ctr, b->ctr, sizeof ctr, hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EDEVICE;
+    for (int s = 0; s < b->nsp; s++)
+        if (hipMemcpy(nlive[s], b->sp[s].n_live, sizeof nlive[s], hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_EDEVICE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PIC_EDEVICE;
+    const int tile0[3] = {b->tile[0], b->tile[1], b->tile[2]};
+    int32_t r = PIC_OK;
+    float best_ms = 0.f;
+    int best = -1;
+    bool best_mig = false;
+    for (int i = 0; i < nc && !r; i++) {
+        set_tiling(b, cand[i]);
+        float ms = 0.f;
+        // each trial: a fresh radix sort in this tiling, then the fused push into the spare
+        // particle buffers and the current array (the box state is not advanced); the first
+        // trial warms up, the fastest of the others counts
+        for (int t = 0; t <= trials && !r; t++) {
+            for (int s = 0; s < b->nsp; s++) b->sp[s].grouped = false;
+            r = sort_box(b);
+            if (!r) r = zero_current(b);
+            if (r) break;
+            const StepDev P = make_step(b);
+            if (hipEventRecord(e0, st) != hipSuccess ||
+                launch_gather_push(P, b->tile, 1, st) != hipSuccess ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                r = PIC_EDEVICE;
+                break;
+            }
+            float m = 0.f;
+            if (hipEventElapsedTime(&m, e0, e1) != hipSuccess) r = PIC_EDEVICE;
+            if (t == 1 || (t > 1 && m < ms)) ms = m;
+        }
+        if (r) break;
+        if (ms_out && i < max_out) ms_out[i] = ms;
+        // a tiling that admits the migration sort wins over one that does not (the sort after
+        // every push is then a counting sort over neighbouring tiles instead of a radix sort)
+        if (best < 0 || (b->mig_ok && !best_mig) || (b->mig_ok == best_mig && ms < best_ms)) {
+            best = i;
+            best_ms = ms;
+            best_mig = b->mig_ok;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    set_tiling(b, r ? tile0 : cand[best]);
+    for (int s = 0; s < b->nsp; s++) b->sp[s].grouped = false;
+    b->sorted = false;
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(b->err, err, sizeof err, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->ctr, ctr, sizeof ctr, hipMemcpyHostToDevice) != hipSuccess)
+        r = r ? r : PIC_EDEVICE;
+    for (int s = 0; s < b->nsp; s++)
+        if (hipMemcpy(b->sp[s].n_live, nlive[s], sizeof nlive[s], hipMemcpyHostToDevice) != hipSuccess)
+            r = r ? r : PIC_EDEVICE;
+    if (r) return r;
+    for (int k = 0; k < 3; k++) tile_out[k] = b->tile[k];
+    if (n_out) *n_out = nc;
+    return PIC_OK;
 }
 
 int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)

@@ -763,13 +763,30 @@ static hipError_t launch_dep_shape(const StepDev& P, hipStream_t st)
     return hipGetLastError();
 }
 
-// Supported tile shapes (edges in cells).  Returns false for an unsupported shape.
-bool tile_shape_supported(int dim, const int t[3])
+// Tile shapes (edges in cells) with an instantiated fused kernel, and the subset the batched
+// launch supports.  Returns the number of shapes written (at most max).
+int tile_candidates(int dim, bool batched, int (*out)[3], int max)
 {
-    if (dim == 3) return (t[0] == 8 && t[1] == 8 && t[2] == 8) || (t[0] == 4 && t[1] == 4 && t[2] == 4);
-    return t[2] == 1 && ((t[0] == 16 && t[1] == 16) || (t[0] == 32 && t[1] == 32) ||
-                         (t[0] == 8 && t[1] == 8) || (t[0] == 32 && t[1] == 16));
+    static const int k3[][3] = {{8, 8, 8}, {4, 4, 4}};
+    static const int k2[][3] = {{16, 16, 1}, {8, 8, 1}, {32, 16, 1}, {32, 32, 1}};
+    const int (*list)[3] = dim == 3 ? k3 : k2;
+    const int n = dim == 3 ? (batched ? 1 : 2) : (batched ? 2 : 4);
+    int w = 0;
+    for (int i = 0; i < n && w < max; i++, w++)
+        for (int k = 0; k < 3; k++) out[w][k] = list[i][k];
+    return w;
 }
+
+static bool in_candidates(int dim, bool batched, const int t[3])
+{
+    int c[8][3];
+    const int n = tile_candidates(dim, batched, c, 8);
+    for (int i = 0; i < n; i++)
+        if (c[i][0] == t[0] && c[i][1] == t[1] && c[i][2] == t[2]) return true;
+    return false;
+}
+
+bool tile_shape_supported(int dim, const int t[3]) { return in_candidates(dim, false, t); }
 
 template <int DIM, int TX, int TY, int TZ>
 static hipError_t launch_batch_shape(const StepDev* table, UnitMap m, int blocks, int frame,
@@ -785,11 +802,7 @@ static hipError_t launch_batch_shape(const StepDev* table, UnitMap m, int blocks
     return hipGetLastError();
 }
 
-bool batch_tile_supported(int dim, const int t[3])
-{
-    if (dim == 3) return t[0] == 8 && t[1] == 8 && t[2] == 8;
-    return t[2] == 1 && ((t[0] == 16 && t[1] == 16) || (t[0] == 8 && t[1] == 8));
-}
+bool batch_tile_supported(int dim, const int t[3]) { return in_candidates(dim, true, t); }
 
 hipError_t launch_gather_push_batch(const StepDev* table, UnitMap m, int blocks, int dim,
                                     const int t[3], int frame, hipStream_t st)

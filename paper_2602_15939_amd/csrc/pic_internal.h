@@ -307,6 +307,8 @@ struct ScanArgs {  // exclusive scan of n words by one workgroup
 
 // ---- launchers (gpd.hip, sort.hip, grid.hip, xfer.hip)
 bool tile_shape_supported(int dim, const int t[3]);
+// supported tile shapes (batched: those of the batched launch); the default shape comes first
+int tile_candidates(int dim, bool batched, int (*out)[3], int max);
 hipError_t launch_gather_push(const StepDev& P, const int t[3], int fuse, hipStream_t st);
 hipError_t launch_deposit(const StepDev& P, const int t[3], hipStream_t st);
 // fused push of many boxes of one dimension, tile shape and frame (table: one StepDev per box,

@@ -9,6 +9,8 @@ particles per cell per species uniform in [4, 32], variant uniform over shearing
 (s uniform in [0, 1.5]), expanding box (adot uniform in [1e-4, 1e-3] omega_p) and leaky box
 (t_esc uniform in [5, 50] L/c, probabilistic escape above gamma = 10), Maxwell-Juttner
 theta uniform in [0.05, 0.5], skin depth 4 cells, sigma = 0.1.
+Tile shapes (hence particles per workgroup) come from the library's autotuner, per box size
+and ppc class, measured on proxy boxes before the runs start (tune_tiles).
 Readings: B0 along z (shearing and leaky boxes) and along x for the expanding box, which
 expands in y and z (l_y = l_z = a(t), the expansion perpendicular to B0); Omega0 = 0.1 omega_c,
 reduced on boxes wider than 64 cells so that the shear flow stays at most 0.38 c at the x faces
@@ -74,10 +76,39 @@ def poisson_arrivals(specs, rate, seed=7):
     return specs
 
 
-def tile_for(n: int):
-    """Tile rule (from tile_sweep on the GPU): 8x8 tiles for 32^2 boxes (the migration sort
-    needs at least three tiles per axis), 16x16 otherwise."""
-    return (8, 8, 1) if n < 64 else (16, 16, 1)
+PPC_CLASSES = ((4, 11, 8), (12, 21, 16), (22, 32, 27))  # (low, high, proxy ppc)
+_TILES: dict = {}
+
+
+def ppc_class(ppc: int) -> int:
+    return next(i for i, (lo, hi, _) in enumerate(PPC_CLASSES) if lo <= ppc <= hi)
+
+
+def tune_tiles(sizes=SIZES, log=None):
+    """Tile shape per (box size, ppc class) from the library's autotuner (pic_autotune, batched
+    shapes only) on a proxy box of that size and particle load (a shearing box at theta 0.3);
+    the choice sets the particles per workgroup.  Cached for the process."""
+    for n in sizes:
+        for k, (_, _, ppc) in enumerate(PPC_CLASSES):
+            if (n, k) in _TILES:
+                continue
+            spec = RunSpec(-1, n, ppc, "shear", 0.3, 1.5, 1, 99)
+            box = build_box(spec, tile=(0, 0, 0))
+            box.step()  # one step so that the autotuner times a pushed (sorted) plasma
+            shape, ms = box.autotune(batched=True, trials=2)
+            box.close()
+            _TILES[(n, k)] = shape
+            if log:
+                log(f"[tune] {n}^2 ppc~{ppc}: {shape} " +
+                    " ".join(f"{t[0]}x{t[1]}={v:.3f}ms" for t, v in ms.items()))
+    return dict(_TILES)
+
+
+def tile_for(n: int, ppc: int):
+    """Tile shape of a run: the autotuner's choice for its size and ppc class."""
+    if (n, ppc_class(ppc)) not in _TILES:
+        tune_tiles((n,))
+    return _TILES[(n, ppc_class(ppc))]
 
 
 def footprint(spec: RunSpec) -> int:
@@ -87,13 +118,13 @@ def footprint(spec: RunSpec) -> int:
     return spec.particles * 96 + cells * 4 * 30 + (1 << 20)
 
 
-def build_box(spec: RunSpec) -> Box:
+def build_box(spec: RunSpec, tile=None) -> Box:
     wp, q, B0 = synth.plasma_params(spec.ppc, 4.0, 0.1)
     n = (spec.n, spec.n)
     count = spec.ppc * spec.n * spec.n
     species = [(-1.0, -q, count), (1.0, q, count)]
-    common = dict(dt=0.45, species=species, seed=spec.seed, box_id=spec.rid,
-                  tile=tile_for(spec.n), maxwell_iters=4)
+    common = dict(dt=0.45, species=species, seed=spec.seed, box_id=max(spec.rid, 0),
+                  tile=tile if tile is not None else tile_for(spec.n, spec.ppc), maxwell_iters=4)
     axis = 2
     if spec.kind == "shear":
         omega0 = 0.1 * B0 * min(1.0, 64.0 / spec.n)

@@ -116,3 +116,24 @@ def test_device_copy_argument_checks(lib):
     assert lib.pic_device_copy(a16 + 4, a16, 16, None) == L.PIC_EINVAL  # misaligned
     assert lib.pic_device_copy(None, a16, 16, None) == L.PIC_EINVAL
     assert lib.pic_device_copy(a16, a16, -16, None) == L.PIC_EINVAL
+
+
+def test_tile_candidates_on_the_host(lib):
+    """The supported tile shapes (host-side list, no device call): the default shape first,
+    the batched subset a prefix of the full list, every listed shape accepted by
+    pic_box_create's host checks' tile rule, other dimensions rejected."""
+    assert L.pic_tile_candidates(3) == [(8, 8, 8), (4, 4, 4)]
+    assert L.pic_tile_candidates(3, L.TUNE_BATCHED) == [(8, 8, 8)]
+    full2 = L.pic_tile_candidates(2)
+    assert full2[0] == (16, 16, 1) and len(full2) == 4
+    assert L.pic_tile_candidates(2, L.TUNE_BATCHED) == full2[:2]
+    out = (C.c_int32 * 3)()
+    assert lib.pic_tile_candidates(3, 0, out, 1) == 2  # count even when max_out is smaller
+    assert tuple(out) == (8, 8, 8)
+    assert lib.pic_tile_candidates(1, 0, out, 1) == L.PIC_EINVAL
+    assert lib.pic_tile_candidates(4, 0, None, 0) == L.PIC_EINVAL
+
+
+def test_autotune_argument_checks_on_the_host(lib):
+    tile = (C.c_int32 * 3)()
+    assert lib.pic_autotune(None, 0, 3, tile, None, 0, None) == L.PIC_EINVAL

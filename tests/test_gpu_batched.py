@@ -29,16 +29,22 @@ def make(spec, seed, stream=None):
                 tile=spec["tile"], maxwell_iters=4, stream=stream, **spec["kw"])
 
 
-def assert_same_state(a, b, tag):
+def assert_same_state(a, b, tag, by_id=False):
     """Two copies of one box after the same steps: integer work equal, momenta within 2e-6
     relative, positions within 2e-6 cells, fields within 1e-5 of their maximum (the float
-    atomics of the tile-halo flush add in a run-dependent order)."""
+    atomics of the tile-halo flush add in a run-dependent order).  by_id: the copies may use
+    different tilings, so particles are matched by id instead of slot."""
     ia, ib = a.gpu.info(), b.gpu.info()
     assert ia.errors & ~L.DERR_ORDER == 0 and ib.errors & ~L.DERR_ORDER == 0, tag
     assert ia.step == ib.step, tag
     assert list(ia.n_particles) == list(ib.n_particles), tag
     for s in range(2):
         ga, gb = a.gpu_species(s), b.gpu_species(s)
+        if by_id:
+            ga = {k: (v[..., np.argsort(ga["id"], kind="stable")] if k != "dr" else v)
+                  for k, v in ga.items()}
+            gb = {k: (v[..., np.argsort(gb["id"], kind="stable")] if k != "dr" else v)
+                  for k, v in gb.items()}
         np.testing.assert_array_equal(ga["id"], gb["id"])
         np.testing.assert_array_equal(ga["cell"] >= 0, gb["cell"] >= 0)
         live = gb["cell"] >= 0

@@ -224,3 +224,44 @@ def test_energy_history_config0_200_steps():
         assert np.all(np.abs(hg - ho) <= 0.01 * np.abs(ho)), (hg, ho)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("frame", ["shear", "expand", "leaky"])
+def test_energy_history_1000_steps(frame):
+    """Field and kinetic energy histories within 1% of the FP64 oracle over 1000 steps, sampled
+    every 50 steps, at the size of the parity configuration (64x64 cells, 16 ppc per species,
+    theta 0.1, skin depth 4 cells, sigma 0.1, B0 along z): the shearing box (q = 1.5,
+    Omega0 = 0.1 omega_c), the expanding box (x and y, perpendicular to B0, grow as
+    a = 1 + adot t with adot = 1e-3 omega_p) and the leaky box in the paper's displacement mode
+    (escape at |dr| = L/2, Maxwell-Juttner reinjection at the plasma temperature: every particle
+    crosses that distance many times in 1000 steps).  Live particle counts equal."""
+    import os
+
+    from paper_2602_15939_amd import synth
+    dims = (64, 64)
+    ppc = 16
+    wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.1)
+    E, B = synth.uniform_field(dims, 2, B0)
+    fields = (E.astype(np.float32), B.astype(np.float32))
+    kw = dict(shear=dict(shear_s=1.5, omega0=0.1 * B0, maxwell_iters=8),
+              expand=dict(adot=1e-3 * wp, axis_mask=0b011),
+              leaky=dict(leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=32.0, theta_inj=0.1))[frame]
+    c = Case(2, dims, frame, ppc=ppc, theta=0.1, seed=4051, fields=fields, q=q, **kw)
+    nthreads = min(16, len(os.sched_getaffinity(0)))
+    try:
+        hist_g, hist_o = [], []
+        for step in range(1000):
+            c.gpu.step()
+            c.oracle_step(nthreads=nthreads)
+            if (step + 1) % 50 == 0:
+                info = c.gpu.info()
+                assert info.errors & ~L.DERR_ORDER == 0, info.errors
+                eg = sum(info.field_energy_B) + sum(info.field_energy_E)
+                eo = oracle.energies(c.box, c.E, c.B, c.J, c.sp)
+                hist_g.append((eg, info.kinetic_energy))
+                hist_o.append((eo[0:6].sum(), eo[6]))
+                assert int(info.n_particles[0] + info.n_particles[1]) == int(eo[10])
+        hg, ho = np.array(hist_g), np.array(hist_o)
+        assert np.all(np.abs(hg - ho) <= 0.01 * np.abs(ho)), (frame, np.abs(hg - ho) / np.abs(ho))
+    finally:
+        c.close()

@@ -37,6 +37,7 @@ struct Species {
     int32_t* toff[2] = {};  // tile offsets (n_tiles + 2) of the last two sorts
     int toff_cur = 0;       // toff[toff_cur] belongs to the last sort
     bool grouped = false;   // particle arrays are in the slot order of toff[toff_cur] (a push ran)
+    bool counts_ready = false;  // that push also wrote the migration counts of the next sort
     int32_t* n_live = nullptr;
     int32_t* ws_cell = nullptr;
     float* ws_off[3] = {};
@@ -221,6 +222,8 @@ void build_mj_table(double theta, std::vector<float>& out)
 }
 
 // ---------------------------------------------------------------- descriptor of one push
+void set_migration_shift(pic_box* b, int dys_int);
+
 StepDev make_step(pic_box* b)
 {
     StepDev P{};
@@ -251,6 +254,16 @@ StepDev make_step(pic_box* b)
     if (P.dys_frac >= 1.f) {  // FP32 rounding of a fraction just below 1
         P.dys_frac = 0.f;
         P.dys_int = (P.dys_int + 1) % b->n[1];
+    }
+    // the push counts the migration directions of the next sort (its y shifts of the
+    // shearing-box x crossings follow this step's Delta y_s)
+    set_migration_shift(b, P.dys_int);
+    P.count_mig = b->mig_ok ? 1 : 0;
+    P.mig_latch = 0;
+    P.mg = b->mg;
+    for (int s = 0; s < b->nsp; s++) {
+        P.mcnt[s] = b->sp[s].sb.mcnt;
+        P.mfb[s] = b->sp[s].sb.fallback;
     }
     for (int k = 0; k < 3; k++) {
         const double rate =
@@ -368,7 +381,7 @@ int32_t sort_box(pic_box* b)
         if (b->mig_ok && S.grouped) {
             const int nxt = S.toff_cur ^ 1;
             e = migrate_sort(S.cell[S.cur], S.toff[S.toff_cur], S.n_upper, b->cc, b->tl, b->mg,
-                             S.sb, S.toff[nxt], S.n_live, S.which, b->ctr + 2, b->st);
+                             S.sb, S.toff[nxt], S.n_live, S.which, b->ctr + 2, S.counts_ready, b->st);
             S.toff_cur = nxt;
             b->n_migrations++;
         } else {
@@ -377,6 +390,7 @@ int32_t sort_box(pic_box* b)
         }
         if (e != hipSuccess) return PIC_EDEVICE;
         S.grouped = false;
+        S.counts_ready = false;
     }
     b->sorted = true;
     return PIC_OK;
@@ -424,11 +438,13 @@ int32_t push_box(pic_box* b, bool fuse)
         }
     }
     StepDev P = make_step(b);
+    for (int s = 0; P.count_mig && s < b->nsp; s++)
+        if (set_i32(b->sp[s].sb.fallback, 0, b->st) != hipSuccess) return PIC_EDEVICE;
     if (launch_gather_push(P, b->tile, fuse ? 1 : 0, b->st) != hipSuccess) return PIC_EDEVICE;
-    set_migration_shift(b, P.dys_int);
     for (int s = 0; s < b->nsp; s++) {
         b->sp[s].cur ^= 1;
         b->sp[s].grouped = true;
+        b->sp[s].counts_ready = P.count_mig != 0;
     }
     b->sorted = false;
     b->deposit_pending = !fuse;
@@ -681,11 +697,14 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
                 const int nxt = S.toff_cur ^ 1;
                 const Gate g{S.sb.fallback, 0};
                 S.which = sort_result_buffer(b->tl);
-                zf.push_back(ZeroArgs{reinterpret_cast<uint32_t*>(S.sb.fallback), 1});
-                zfb.push_back(1);
-                mc.push_back(MigCountArgs{S.cell[S.cur], S.toff[S.toff_cur], b->cc, b->mg, S.sb.mcnt,
-                                          S.sb.fallback, b->err});
-                mcb.push_back((uint32_t)nt);
+                if (!S.counts_ready) {  // else the push wrote the counts and the flag
+                    zf.push_back(ZeroArgs{reinterpret_cast<uint32_t*>(S.sb.fallback), 1});
+                    zfb.push_back(1);
+                    mc.push_back(MigCountArgs{S.cell[S.cur], S.toff[S.toff_cur], b->cc, b->mg,
+                                              S.sb.mcnt, S.sb.fallback, b->err});
+                    mcb.push_back((uint32_t)nt);
+                }
+                S.counts_ready = false;
                 mo.push_back(MigOffArgs{S.sb.mcnt, b->mg, S.sb.mpre, S.sb.tot, S.sb.dcnt, g});
                 mob.push_back((uint32_t)((nt + kBlock / 64 - 1) / (kBlock / 64)));
                 sc.push_back(ScanArgs{S.sb.tot, S.sb.start, nt + 1, g});
@@ -726,12 +745,17 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
             }
             auto& gr = groups[std::make_tuple(b->dim, b->tile[0], b->tile[1], b->tile[2], b->d.frame)];
             StepDev P = make_step(b);
+            P.mig_latch = 1;  // no radix fallback behind a batched sort
             gr.first.push_back(P);
             gr.second.push_back((uint32_t)b->tl.n_tiles);
-            set_migration_shift(b, P.dys_int);
             for (int s = 0; s < b->nsp; s++) {
+                if (P.count_mig) {  // cleared after this step's sort read it, set by the push
+                    z.push_back(ZeroArgs{reinterpret_cast<uint32_t*>(b->sp[s].sb.fallback), 1});
+                    zb.push_back(1);
+                }
                 b->sp[s].cur ^= 1;
                 b->sp[s].grouped = true;
+                b->sp[s].counts_ready = P.count_mig != 0;
             }
             b->sorted = false;
         }
@@ -1249,6 +1273,7 @@ int32_t pic_set_particles(pic_box* b, int32_t s, int64_t n, const int32_t* cell,
     if (set_i32(S.n_live, (int32_t)n, st) != hipSuccess) return PIC_EDEVICE;
     S.n_upper = (int)n;
     S.grouped = false;
+    S.counts_ready = false;
     b->sorted = false;
     return PIC_OK;
 }
@@ -1427,7 +1452,7 @@ int32_t pic_autotune(pic_box* b, uint32_t flags, int32_t trials, int32_t* tile_o
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     set_tiling(b, r ? tile0 : cand[best]);
-    for (int s = 0; s < b->nsp; s++) b->sp[s].grouped = false;
+    for (int s = 0; s < b->nsp; s++) b->sp[s].grouped = b->sp[s].counts_ready = false;
     b->sorted = false;
     if (hipStreamSynchronize(st) != hipSuccess ||
         hipMemcpy(b->err, err, sizeof err, hipMemcpyHostToDevice) != hipSuccess ||

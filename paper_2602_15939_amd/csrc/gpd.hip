@@ -489,14 +489,21 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
     tile_origin<DIM>(P, tile, t0, ext);
     const int tid = threadIdx.x;
 
+    // migration counts of the next sort (per species, direction)
+    __shared__ uint32_t mc[kMaxSpecies * kMigDirs];
+    const int tsy = t0[1] >> P.tl.lt[1];  // y index of this tile
+
     stage_fields<G, DIM, 0, NT>(Fl, P, t0, ext, tid);
     if (fuse)
         for (int e = tid; e < G::JTOT; e += NT) Jl[e] = 0ull;
+    if (tid < kMaxSpecies * kMigDirs) mc[tid] = 0u;
     __syncthreads();
 
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     for (int s = 0; s < P.nsp; s++) {
         const SpeciesDev& S = P.sp[s];
+        uint32_t stay = 0;  // particles that stay in this tile (the common direction)
+        bool far = false;   // a particle beyond the neighbouring tiles
         const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
         for (uint32_t slot = beg + tid; slot < end; slot += NT) {
             uint32_t so = slot;
@@ -574,7 +581,8 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             float noy = renorm(__fadd_rn(oy, dyt), dcy);
             const float noz = DIM == 3 ? renorm(__fadd_rn(oz, D.z), dcz) : 0.f;
             int ncx = cx + dcx, ncy = cy + dcy, ncz = cz + dcz;
-            if (ncx >= nx || ncx < 0) {
+            const bool xwrap = ncx >= nx || ncx < 0;
+            if (xwrap) {
                 // shearing-periodic x (Sec. 2.1): leaving through x_o re-enters at x_i with
                 // y + Delta y_s(t^{n+1}); leaving through x_i re-enters at x_o with y - Delta y_s
                 const bool out = ncx >= nx;
@@ -647,6 +655,32 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 }
             }
 
+            if (P.count_mig) {
+                // direction of the new tile from this one (the migration sort applies only to
+                // whole tiles): the cell step r + dc in [-1, edge] shifted right by log2(edge)
+                // is -1, 0 or +1, periodic wraps included; one tile on an axis means 0.  A
+                // shearing-box x-face crossing moves in y by the push's Delta y_s: its y step is
+                // taken against the tile shift of that face.
+                const int dx = P.mg.nt[0] == 1 ? 0 : (rx + dcx) >> P.tl.lt[0];
+                int dy = P.mg.nt[1] == 1 ? 0 : (ry + dcy) >> P.tl.lt[1];
+                const int dz = (DIM == 2 || P.mg.nt[2] == 1) ? 0 : (rz + dcz) >> P.tl.lt[2];
+                if (FRAME == kShear && xwrap && P.mg.nt[1] > 1) {
+                    int r = (ncy >> P.tl.lt[1]) - tsy - (dx > 0 ? P.mg.cy_out : P.mg.cy_in);
+                    const int n1 = P.mg.nt[1];  // r lies in (-2 n1, 2 n1)
+                    if (r < 0) r += n1;
+                    if (r < 0) r += n1;
+                    if (r >= n1) r -= n1;
+                    dy = r == 0 ? 0 : (r == 1 ? 1 : (r == n1 - 1 ? -1 : 2));
+                }
+                int d = dy == 2 ? -1 : (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                if (ncell < 0) d = kMigDead;
+                if (d == 13)
+                    stay++;
+                else if (d >= 0)
+                    atomicAdd(&mc[s * kMigDirs + d], 1u);
+                else
+                    far = true;
+            }
             st_at(S.cell_out, so, ncell);
             st_at(S.off_out[0], so, nox);
             st_at(S.off_out[1], so, noy);
@@ -656,11 +690,24 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             st_at(S.u_out[2], so, u.z);
             if (P.track_ids) st_at(S.id_out, so, ld_at(S.id_in, src));
         }
+        if (P.count_mig) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) stay += __shfl_xor(stay, o, 64);
+            if ((tid & 63) == 0 && stay) atomicAdd(&mc[s * kMigDirs + 13], stay);
+            if (far) {
+                *P.mfb[s] = 1;
+                if (P.mig_latch) latch(P.err, kErrSort);
+            }
+        }
     }
 
-    if (!fuse) return;
+    if (!fuse && !P.count_mig) return;
     __syncthreads();
-    flush_current<G, DIM, NT>(Jl, P, t0, ext, tid);
+    if (P.count_mig && tid < P.nsp * kMigDirs) {
+        const int s = tid / kMigDirs;
+        P.mcnt[s][(size_t)tile * kMigDirs + (tid - s * kMigDirs)] = mc[tid];
+    }
+    if (fuse) flush_current<G, DIM, NT>(Jl, P, t0, ext, tid);
 }
 
 // 3D tiles: compact regions (48.4 KB of LDS for 8^3) let three workgroups share a CU, so the

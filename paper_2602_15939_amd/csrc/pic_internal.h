@@ -45,6 +45,67 @@ struct Tiles {
     }
 };
 
+// Directions of the migration sort: (dx, dy, dz) in {-1,0,1}^3 between the tile a particle
+// was sorted into and the tile of its new cell, index (dx+1) + 3 (dy+1) + 9 (dz+1); the last
+// direction is the dead bin.  Crossing the x faces of the shearing box shifts y by the tile
+// offset cy_out (leaving through the outer face) or cy_in (inner face) before dy is taken.
+constexpr int kMigDirs = 28;
+constexpr uint32_t kErrSort = 16u;  // a batched sort met a particle beyond the neighbour tiles
+constexpr int kMigDead = 27;
+struct MigGeo {
+    int nt[3], lt[3];
+    int n_tiles;
+    int cy_out, cy_in;
+};
+
+// d reduced on a ring of n tiles to -1, 0, +1, or 2 if it is farther
+__device__ inline int ring_step(int d, int n)
+{
+    if (n == 1) return 0;
+    int r = d % n;
+    if (r < 0) r += n;
+    if (r == 0) return 0;
+    if (r == 1) return 1;
+    if (r == n - 1) return -1;
+    return 2;
+}
+
+__device__ inline void tile_coords(const MigGeo& g, int t, int& x, int& y, int& z)
+{
+    x = t % g.nt[0];
+    const int r = t / g.nt[0];
+    y = r % g.nt[1];
+    z = r / g.nt[1];
+}
+
+// direction of a particle of source tile (sx, sy, sz) with new cell c, or -1 if its new tile is
+// not a neighbour
+__device__ inline int mig_dir(const MigGeo& g, const CellCode& cc, int sx, int sy, int sz,
+                              int32_t c)
+{
+    if (c < 0) return kMigDead;
+    int x, y, z;
+    cc.decode(c, x, y, z);
+    const int tx = x >> g.lt[0], ty = y >> g.lt[1], tz = z >> g.lt[2];
+    int dx = tx - sx, wx = 0;
+    if (g.nt[0] == 1) {
+        dx = 0;
+    } else if (dx == g.nt[0] - 1 && dx > 1) {  // through the inner x face
+        dx = -1;
+        wx = -1;
+    } else if (dx == 1 - g.nt[0] && dx < -1) {  // through the outer x face
+        dx = 1;
+        wx = 1;
+    } else if (dx < -1 || dx > 1) {
+        return -1;
+    }
+    const int shift = wx > 0 ? g.cy_out : (wx < 0 ? g.cy_in : 0);
+    const int dy = ring_step(ty - sy - shift, g.nt[1]);
+    const int dz = ring_step(tz - sz, g.nt[2]);
+    if (dy == 2 || dz == 2) return -1;
+    return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
+
 // One species as seen by a push launch: input arrays (read through perm), output arrays
 // (written in sorted slot order) and the unfused-deposit workspace.
 struct SpeciesDev {
@@ -99,6 +160,14 @@ struct StepDev {
     const float* mj;      // kMjBins + kMjTail values
     // fixed-point tile current: contribution * jscale -> integer units, units * junit -> J
     float jscale, junit;
+    // migration counts of the next sort, taken by the push: per species and source tile
+    // (= this launch's tile), the particles per direction (mcnt[tile * kMigDirs + d]); a
+    // particle beyond the neighbouring tiles sets mfb (the radix fallback runs then)
+    int count_mig;
+    int mig_latch;  // batched steps (no radix fallback behind the sort): latch kErrSort too
+    MigGeo mg;
+    uint32_t* mcnt[kMaxSpecies];
+    int32_t* mfb[kMaxSpecies];
     // bookkeeping
     uint32_t* err;
     unsigned long long* ctr;  // [0] slow-path particles, [1] escapes
@@ -249,18 +318,6 @@ struct SortBufs {
     int32_t* fallback; // set when a particle left the neighbourhood the migration sort covers
 };
 
-// Directions of the migration sort: (dx, dy, dz) in {-1,0,1}^3 between the tile a particle
-// was sorted into and the tile of its new cell, index (dx+1) + 3 (dy+1) + 9 (dz+1); the last
-// direction is the dead bin.  Crossing the x faces of the shearing box shifts y by the tile
-// offset cy_out (leaving through the outer face) or cy_in (inner face) before dy is taken.
-constexpr int kMigDirs = 28;
-constexpr int kMigDead = 27;
-struct MigGeo {
-    int nt[3], lt[3];
-    int n_tiles;
-    int cy_out, cy_in;
-};
-
 // A launch gated on a device flag runs only when *flag == want (flag == nullptr: always), so
 // that a fallback path can be queued behind a test without a host round trip.
 struct Gate {
@@ -269,7 +326,6 @@ struct Gate {
     __device__ inline bool off() const { return flag && *flag != want; }
 };
 
-constexpr uint32_t kErrSort = 16u;  // a batched sort met a particle beyond the neighbour tiles
 
 struct MigCountArgs {
     const int32_t* cell;
@@ -328,10 +384,11 @@ hipError_t tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper,
 // tile_sort on the device when a particle is outside that neighbourhood.  Writes the
 // permutation to sb.vals[which] and the offsets to toff.
 size_t migrate_scratch_words(int n_tiles);
+// counts_ready: the push already wrote sb.mcnt and the fallback flag (the count pass is skipped)
 hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upper, CellCode cc,
                         Tiles tl, const MigGeo& mg, SortBufs& sb, int32_t* toff,
                         int32_t* n_live_out, int& which, unsigned long long* n_fallback,
-                        hipStream_t st);
+                        bool counts_ready, hipStream_t st);
 
 // batched launches of the grid and sort kernels (tables of per-unit arguments on the device)
 enum GridBatchKind {

@@ -288,54 +288,6 @@ hipError_t tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper,
 // increasing source tile, i.e. increasing slot.  Slots from the previous dead bin stay dead,
 // after the particles that died since.
 
-// d reduced on a ring of n tiles to -1, 0, +1, or 2 if it is farther
-__device__ inline int ring_step(int d, int n)
-{
-    if (n == 1) return 0;
-    int r = d % n;
-    if (r < 0) r += n;
-    if (r == 0) return 0;
-    if (r == 1) return 1;
-    if (r == n - 1) return -1;
-    return 2;
-}
-
-__device__ inline void tile_coords(const MigGeo& g, int t, int& x, int& y, int& z)
-{
-    x = t % g.nt[0];
-    const int r = t / g.nt[0];
-    y = r % g.nt[1];
-    z = r / g.nt[1];
-}
-
-// direction of a particle of source tile (sx, sy, sz) with new cell c, or -1 if its new tile is
-// not a neighbour
-__device__ inline int mig_dir(const MigGeo& g, const CellCode& cc, int sx, int sy, int sz,
-                              int32_t c)
-{
-    if (c < 0) return kMigDead;
-    int x, y, z;
-    cc.decode(c, x, y, z);
-    const int tx = x >> g.lt[0], ty = y >> g.lt[1], tz = z >> g.lt[2];
-    int dx = tx - sx, wx = 0;
-    if (g.nt[0] == 1) {
-        dx = 0;
-    } else if (dx == g.nt[0] - 1 && dx > 1) {  // through the inner x face
-        dx = -1;
-        wx = -1;
-    } else if (dx == 1 - g.nt[0] && dx < -1) {  // through the outer x face
-        dx = 1;
-        wx = 1;
-    } else if (dx < -1 || dx > 1) {
-        return -1;
-    }
-    const int shift = wx > 0 ? g.cy_out : (wx < 0 ? g.cy_in : 0);
-    const int dy = ring_step(ty - sy - shift, g.nt[1]);
-    const int dz = ring_step(tz - sz, g.nt[2]);
-    if (dy == 2 || dz == 2) return -1;
-    return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-}
-
 __device__ inline void dir_steps(int d, int& dx, int& dy, int& dz)
 {
     dx = d % 3 - 1;
@@ -636,14 +588,16 @@ size_t migrate_scratch_words(int n_tiles) { return scan_scratch_words((int64_t)n
 hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upper, CellCode cc,
                         Tiles tl, const MigGeo& mg, SortBufs& sb, int32_t* toff,
                         int32_t* n_live_out, int& which, unsigned long long* n_fallback,
-                        hipStream_t st)
+                        bool counts_ready, hipStream_t st)
 {
     const int nt = tl.n_tiles;
     const Gate mig{sb.fallback, 0}, radix{sb.fallback, 1};
     which = radix_passes(tl) & 1;  // where the radix fallback leaves its result
-    if (hipMemsetAsync(sb.fallback, 0, sizeof(int32_t), st) != hipSuccess) return hipGetLastError();
-    mig_count_kernel<<<nt, kBlock, 0, st>>>(
-        MigCountArgs{cell, toff_prev, cc, mg, sb.mcnt, sb.fallback, nullptr});
+    if (!counts_ready) {
+        if (set_i32(sb.fallback, 0, st) != hipSuccess) return hipGetLastError();
+        mig_count_kernel<<<nt, kBlock, 0, st>>>(
+            MigCountArgs{cell, toff_prev, cc, mg, sb.mcnt, sb.fallback, nullptr});
+    }
     mig_offsets_kernel<<<(nt + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, st>>>(
         MigOffArgs{sb.mcnt, mg, sb.mpre, sb.tot, sb.dcnt, mig});
     hipError_t e = scan_exclusive(sb.tot, sb.start, nt + 1, sb.mscratch, st, mig);

@@ -1,10 +1,12 @@
 #!/usr/bin/env python
 """Throughput of the particle hot path on one MI355X.
 
-Workload (default): the 3D3V shearing box, 256^3 Yee cells, 8 particles per cell per species
-(e+ and e-, 268,435,456 particles), Maxwell-Juttner theta = 0.3, skin depth 4 cells, weak
-B0 along z with sigma = 0.05, Keplerian shear q = 1.5, Omega0/omega_c = 0.05, dt = 0.45,
-FP32 particles (int32 cell + FP32 offset) with FP64 shear offset.  Synthetic seeded inputs.
+Workload (default, --workload shear3d): the 3D3V shearing box, 256^3 Yee cells, 8 particles
+per cell per species (e+ and e-, 268,435,456 particles), Maxwell-Juttner theta = 0.3, skin depth
+4 cells, weak B0 along z with sigma = 0.05, Keplerian shear q = 1.5, Omega0/omega_c = 0.05,
+dt = 0.45, FP32 particles (int32 cell + FP32 offset) with FP64 shear offset.  Synthetic seeded
+inputs.  --workload expand3d / leaky2d: the 128x128x512 expanding box and the 2048^2 leaky box
+(recipes in paper_2602_15939_amd/workloads.py); --serve: the served batch of 2D boxes.
 
 One step = tile sort + fused gather/push/deposit + current fold with the J' transport +
 implicit-midpoint Maxwell (fixed-point sweeps) + guard fills, i.e. the whole hot path.
@@ -66,11 +68,31 @@ def make_box(w, seed, device="cuda"):
 
 def algorithmic_bytes(w, nparticles):
     """Bytes the fused gather/push/deposit must move per launch: particle state read + write
-    (int32 cell + 3 FP32 offsets + 3 FP32 momenta = 28 B each way), the sort permutation
+    (int32 cell + dim FP32 offsets + 3 FP32 momenta: 28 B each way in 3D, 24 B in 2D; the
+    uint32 id each way where ids are carried, as in the leaky box), the sort permutation
     (4 B), the six field components read once (24 B/cell) and the current read-modify-write
     (24 B/cell)."""
     ncell = math.prod(w["n"])
-    return nparticles * (28 + 28 + 4) + ncell * (24 + 24)
+    state = 4 + 4 * w["dim"] + 12 + (4 if w["kind"] == "leaky" else 0)
+    return nparticles * (2 * state + 4) + ncell * (24 + 24)
+
+
+def frame_params(w):
+    """The physical parameters of a workload for the bench line."""
+    import math as m
+
+    wp = 0.25  # skin depth 4 cells
+    sigma = round((w["B0"] / wp) ** 2, 6)
+    p = dict(theta=w["theta"], sigma=sigma, dt=w["dt"])
+    if w["kind"] == "shear":
+        p.update(q=w["shear_s"], omega0_over_wc=round(w["omega0"] / w["B0"], 6),
+                 maxwell_iters=w["maxwell_iters"])
+    elif w["kind"] == "expand":
+        p.update(adot_over_wp=round(w["adot"] / wp, 9), dB_over_B0=w["dB"], spectrum_slope_3d=-5 / 3)
+    else:
+        p.update(dB_over_B0=w["dB"], gamma_thr=w["gamma_thr"], t_esc_over_L=w["t_esc"] / w["n"][0],
+                 escape="probabilistic, Philox keyed by id and step")
+    return p
 
 
 def cpu_baseline(seconds=12.0):
@@ -196,7 +218,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--workload", default="shear3d", choices=["shear3d", "expand3d", "leaky2d"],
+                    help="shear3d: 256^3 shearing box (the default line); expand3d: 128x128x512 "
+                         "expanding box; leaky2d: 2048^2 leaky box")
+    ap.add_argument("--n", type=int, default=None, help="shear3d only: cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=20260216)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -221,7 +246,12 @@ def main():
 
     from paper_2602_15939_amd import _lib as L
 
-    w = workload_shear3d(n=args.n)
+    from paper_2602_15939_amd import workloads
+
+    if args.workload == "shear3d":
+        w = workload_shear3d(n=args.n or 256)
+    else:
+        w = workloads.WORKLOADS[args.workload]()
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
     box, npart = make_box(w, args.seed)
     tuned = None
@@ -240,7 +270,7 @@ def main():
         if ev is not None:
             ev[1].record(st)
         L.pic_shear_remap(h, L.REMAP_CURRENT)
-        L.pic_maxwell_step(h)
+        L.pic_maxwell_step(h)  # also fills the field guard cells at t^{n+1}
 
     for _ in range(args.warmup):
         one_step()
@@ -281,9 +311,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w["name"], "particles": npart, "frame": "shearing box",
-                   "theta": w["theta"], "sigma": 0.05, "q": 1.5, "omega0_over_wc": 0.05,
-                   "dt": w["dt"], "maxwell_iters": w["maxwell_iters"],
+        "config": {"workload": w["name"], "particles": npart,
+                   "frame": {"shear": "shearing box", "expand": "expanding box",
+                             "leaky": "leaky box"}[w["kind"]],
+                   **frame_params(w),
                    "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": npart / (gpd_ms * 1e-3),
                    "gpd_algorithmic_bytes": nbytes, "slow_path_particles": int(info.n_slow),
                    "kernel_source_hash": kernel_source_hash(), "autotune": tuned},
@@ -291,7 +322,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
     box.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w["kind"] == "shear":  # the oracle sample is a shearing box
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

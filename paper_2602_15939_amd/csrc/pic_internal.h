@@ -58,12 +58,15 @@ struct MigGeo {
     int cy_out, cy_in;
 };
 
-// d reduced on a ring of n tiles to -1, 0, +1, or 2 if it is farther
+// d in (-2n, 2n) reduced on a ring of n tiles to -1, 0, +1, or 2 if it is farther (conditional
+// adds: no integer division)
 __device__ inline int ring_step(int d, int n)
 {
     if (n == 1) return 0;
-    int r = d % n;
+    int r = d;
     if (r < 0) r += n;
+    if (r < 0) r += n;
+    if (r >= n) r -= n;
     if (r == 0) return 0;
     if (r == 1) return 1;
     if (r == n - 1) return -1;
@@ -99,6 +102,7 @@ __device__ inline int mig_dir(const MigGeo& g, const CellCode& cc, int sx, int s
     } else if (dx < -1 || dx > 1) {
         return -1;
     }
+    // tiles and the shifts lie in [0, nt): the differences below lie in (-2 nt, nt)
     const int shift = wx > 0 ? g.cy_out : (wx < 0 ? g.cy_in : 0);
     const int dy = ring_step(ty - sy - shift, g.nt[1]);
     const int dz = ring_step(tz - sz, g.nt[2]);

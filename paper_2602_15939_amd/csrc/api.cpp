@@ -505,7 +505,10 @@ int32_t maxwell_box(pic_box* b)
             Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
             Kd.half_nx = 0.5f * (float)b->n[0];
             if (ksb_sweep(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
-            if (fill_guards(b->G, b->set[so], 6, 1, dys1, st) != hipSuccess) return PIC_EDEVICE;
+            // the 3D sweep reads the y and z halo at the periodic images: between sweeps only
+            // the x guards (shearing-periodic images) are filled, all of them after the last
+            const bool x_only = b->dim == 3 && k < K - 1;
+            if (fill_guards(b->G, b->set[so], 6, 1, dys1, st, x_only) != hipSuccess) return PIC_EDEVICE;
             sk = so;
             so = so == sb2 ? sn : sb2;
         }

@@ -372,7 +372,10 @@ PIC_BATCHED_KERNEL(ksb_first, KsbDev, kBlock)
 PIC_BATCHED_KERNEL(ksb_next, KsbDev, kBlock)
 
 // 3D: a workgroup owns a KX x KY column tile and marches over a chunk of KZ planes; three
-// consecutive planes of the iterate (tile plus a one-cell halo) sit in LDS.
+// consecutive planes of the iterate (tile plus a one-cell halo) sit in LDS.  Halo positions
+// outside the interior are read through the boundary maps of the guard fill (y, z periodic;
+// x shearing-periodic with the fractional shift interpolated along y, the same arithmetic), so
+// the iterates need no guard fill between sweeps.
 constexpr int KX = 32, KY = 8, KZ = 32;
 constexpr int KXH = KX + 2, KYH = KY + 2;
 
@@ -386,32 +389,37 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
     const int tid = threadIdx.x, tx = tid % KX, ty = tid / KX;
     // tiles x fastest, then y, then z chunk; each XCD takes a contiguous range so that the
     // halos of neighbouring tiles are shared in its L2
-    const int ntx = (G.n[0] + KX - 1) / KX, nty = (G.n[1] + KY - 1) / KY;
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int ntx = (nx + KX - 1) / KX, nty = (ny + KY - 1) / KY;
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
     const int x0 = (tile % ntx) * KX, y0 = ((tile / ntx) % nty) * KY, z0 = (tile / (ntx * nty)) * KZ;
-    const int z1 = min(z0 + KZ, G.n[2]);
+    const int z1 = min(z0 + KZ, nz);
     const int x = x0 + tx, y = y0 + ty;
-    const bool inside = x < G.n[0] && y < G.n[1];
+    const bool inside = x < nx && y < ny;
     const float* const* F = K.Fk;
-    // halo positions beyond the guarded grid (ragged tiles) are never read by a valid cell
-    const int xmax = G.n[0] + G.g[0] - 1, ymax = G.n[1] + G.g[1] - 1;
-    int64_t off[PER];  // plane offset of each staged position (relative to the interior origin)
-    bool ok[PER];      // the position lies in the guarded grid
+    // staged position j: in-plane offset of its source.  y and z halo positions are read at
+    // their periodic images; x halo positions from the x guard cells (the shearing-periodic
+    // images, filled before the sweep).  Positions beyond the first layer outside the grid
+    // (ragged tiles) are never read by a valid cell.
+    int off[PER];
+    bool ok[PER];
 #pragma unroll
     for (int j = 0; j < PER; j++) {
         const int e = tid + j * NT;
         const int lx = e % KXH, ly = e / KXH;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        ok[j] = e < KXH * KYH && gx <= xmax && gy <= ymax;
-        off[j] = ok[j] ? gidx(G, gx, gy, 0) : 0;
+        ok[j] = e < KXH * KYH && gx <= nx && gy <= ny;
+        const int yy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        off[j] = ok[j] ? gx + G.sy * yy : 0;
     }
     // register stage of one plane (loads in flight while the previous plane is computed)
     float R[PER][6];
     auto fetch = [&](int z) {
+        const int64_t pz = (int64_t)G.sz * (z < 0 ? z + nz : (z >= nz ? z - nz : z));
 #pragma unroll
         for (int j = 0; j < PER; j++)
 #pragma unroll
-            for (int c = 0; c < 6; c++) R[j][c] = ok[j] ? F[c][off[j] + (int64_t)G.sz * z] : 0.f;
+            for (int c = 0; c < 6; c++) R[j][c] = ok[j] ? F[c][off[j] + pz] : 0.f;
     };
     auto stash = [&](int slot) {
 #pragma unroll
@@ -560,7 +568,7 @@ __global__ void sum_rows_kernel(const double* part, int nrow, int ncol, double* 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
-                       hipStream_t st)
+                       hipStream_t st, bool x_only)
 {
     Comp6 A{};
     for (int c = 0; c < ncomp; c++) A.p[c] = comps[c];
@@ -570,6 +578,7 @@ hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int she
     const int NYg = G.n[1] + 2 * G.g[1], NZg = G.n[2] + 2 * G.g[2];
     fill_guards_kernel<<<dim3(nblocks((int64_t)2 * G.g[0] * NYg * NZg), ncomp), kBlock, 0, st>>>(
         FillArgs{G, A, 0, shear, di, w});
+    if (x_only) return hipGetLastError();
     fill_guards_kernel<<<dim3(nblocks((int64_t)G.n[0] * 2 * G.g[1] * NZg), ncomp), kBlock, 0, st>>>(
         FillArgs{G, A, 1, shear, di, w});
     if (G.g[2] > 0)

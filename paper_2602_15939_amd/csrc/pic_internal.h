@@ -406,8 +406,10 @@ enum SortBatchKind { kBatchMigCount, kBatchMigOffsets, kBatchScan, kBatchMigScat
 hipError_t sort_batch(SortBatchKind k, const void* table, UnitMap m, int blocks, hipStream_t st);
 int sort_result_buffer(const Tiles& tl);  // sort buffer holding the sorted pairs
 
+// x_only: only the x guard slabs (the shearing-periodic images), for readers that take the y
+// and z halos at their periodic images themselves
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
-                       hipStream_t st);
+                       hipStream_t st, bool x_only = false);
 hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, int shear,
                         double sO, double dt, double dys_half, hipStream_t st);
 hipError_t yee_b(const MaxwellDev& M, hipStream_t st);

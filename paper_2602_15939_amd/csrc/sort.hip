@@ -444,7 +444,8 @@ __device__ __attribute__((always_inline)) inline void mig_scatter_body(const Mig
     int32_t* __restrict__ toff = a.toff;
     int32_t* __restrict__ n_live = a.n_live;
     __shared__ uint32_t run[2][kMigDirs];
-    __shared__ uint32_t wc[kMigItems][kBlock / 64][kMigDirs];
+    __shared__ uint32_t wc[kMigItems][kBlock / 64][kMigDirs];   // per (item, wave): count per direction
+    __shared__ uint32_t pre[kMigItems][kBlock / 64][kMigDirs];  // exclusive prefix over (item, wave)
     const int s = blk, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t live = start[g.n_tiles];
     if (s == g.n_tiles) {
@@ -492,37 +493,37 @@ __device__ __attribute__((always_inline)) inline void mig_scatter_body(const Mig
         for (int j = 0; j < kMigItems; j++) {
             const bool valid = cb + j * kBlock + tid < end;
             d[j] = valid ? mig_dir(g, cc, sx, sy, sz, c[j]) : -1;
-            unsigned long long rem = __ballot(valid);
-            uint32_t r = 0, mine = 0;
-            while (rem) {
-                const int lead = __builtin_ctzll(rem);
-                const int dl = __shfl(d[j], lead, 64);
-                const unsigned long long m = __ballot(d[j] == dl) & rem;
-                if (d[j] == dl) r = (uint32_t)__popcll(m & lt);
-                if (lane == dl) mine = (uint32_t)__popcll(m);
-                rem &= ~m;
+            // lanes with the same key (direction + 1, 5 bits; 0 = none): the AND over the key
+            // bits of the ballot of that bit or of its complement
+            const uint32_t key = (uint32_t)(d[j] + 1);
+            unsigned long long same = ~0ull;
+#pragma unroll
+            for (int bit = 0; bit < 5; bit++) {
+                const unsigned long long m = __ballot((key >> bit) & 1u);
+                same &= ((key >> bit) & 1u) ? m : ~m;
             }
-            rank[j] = r;
-            if (lane < kMigDirs) wc[j][w][lane] = mine;
+            rank[j] = (uint32_t)__popcll(same & lt);
+            if (lane < kMigDirs) wc[j][w][lane] = 0u;
+            // the lowest lane of each group writes the group's count (same wave: in order)
+            if (d[j] >= 0 && rank[j] == 0) wc[j][w][d[j]] = (uint32_t)__popcll(same);
         }
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kMigItems; j++) {
-            if (d[j] < 0) continue;
-            const int dj = d[j];
-            uint32_t pos = run[p][dj] + rank[j];
-            for (int jj = 0; jj < j; jj++)
-                for (int k = 0; k < kBlock / 64; k++) pos += wc[jj][k][dj];
-            for (int k = 0; k < w; k++) pos += wc[j][k][dj];
-            perm[pos] = (uint32_t)(cb + j * kBlock + tid);
-        }
+        // per direction, the exclusive prefix over (item, wave) and the running offset
         if (tid < kMigDirs) {
             uint32_t a = run[p][tid];
+#pragma unroll
             for (int jj = 0; jj < kMigItems; jj++)
-                for (int k = 0; k < kBlock / 64; k++) a += wc[jj][k][tid];
+#pragma unroll
+                for (int k = 0; k < kBlock / 64; k++) {
+                    pre[jj][k][tid] = a;
+                    a += wc[jj][k][tid];
+                }
             run[p ^ 1][tid] = a;
         }
         __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMigItems; j++)
+            if (d[j] >= 0) perm[pre[j][w][d[j]] + rank[j]] = (uint32_t)(cb + j * kBlock + tid);
         p ^= 1;
     }
 }

@@ -92,6 +92,8 @@ def frame_params(w):
     else:
         p.update(dB_over_B0=w["dB"], gamma_thr=w["gamma_thr"], t_esc_over_L=w["t_esc"] / w["n"][0],
                  escape="probabilistic, Philox keyed by id and step")
+        if "shell_gamma" in w:
+            p.update(shell_gamma=w["shell_gamma"], t_esc_over_dt=w["t_esc"] / w["dt"])
     return p
 
 
@@ -218,7 +220,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="shear3d", choices=["shear3d", "expand3d", "leaky2d"],
+    ap.add_argument("--workload", default="shear3d",
+                    choices=["shear3d", "expand3d", "leaky2d", "leaky2d_stress"],
                     help="shear3d: 256^3 shearing box (the default line); expand3d: 128x128x512 "
                          "expanding box; leaky2d: 2048^2 leaky box")
     ap.add_argument("--n", type=int, default=None, help="shear3d only: cells per axis")
@@ -279,6 +282,7 @@ def main():
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
+    live0 = box.count(0) + box.count(1)
     t0 = time.perf_counter()
     for k in range(args.steps):
         one_step(evs[k])
@@ -294,8 +298,17 @@ def main():
         del src, dst
     info = box.info()
     assert info.errors & ~L.DERR_ORDER == 0, f"device error bits {info.errors}"
-    value = npart * args.steps / el
-    nbytes = algorithmic_bytes(w, npart)
+    # particle-steps of the timed steps: with escapes the live count decays geometrically
+    # (a constant escape probability per step) from live0 to live1
+    live1 = int(info.n_particles[0] + info.n_particles[1])
+    if live1 < live0:
+        r = (live1 / live0) ** (1.0 / args.steps)
+        psteps = live0 * (1.0 - r ** args.steps) / (1.0 - r)
+    else:
+        psteps = float(live0 * args.steps)
+    value = psteps / el
+    n_avg = psteps / args.steps  # live particles per timed step (npart without escapes)
+    nbytes = algorithmic_bytes(w, n_avg)
     achieved = nbytes / (gpd_ms * 1e-3) / 1e9
     traffic = measured_traffic(w["name"])
     out = {
@@ -312,10 +325,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["name"], "particles": npart,
+                   "live_particles_first_last": [live0, live1],
                    "frame": {"shear": "shearing box", "expand": "expanding box",
                              "leaky": "leaky box"}[w["kind"]],
                    **frame_params(w),
-                   "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": npart / (gpd_ms * 1e-3),
+                   "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": n_avg / (gpd_ms * 1e-3),
                    "gpd_algorithmic_bytes": nbytes, "slow_path_particles": int(info.n_slow),
                    "kernel_source_hash": kernel_source_hash(), "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

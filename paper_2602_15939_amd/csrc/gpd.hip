@@ -504,6 +504,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
         const SpeciesDev& S = P.sp[s];
         uint32_t stay = 0;  // particles that stay in this tile (the common direction)
         bool far = false;   // a particle beyond the neighbouring tiles
+        uint32_t nesc = 0;  // probabilistic escapes (one counter add per wave, at the end)
         const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
         for (uint32_t slot = beg + tid; slot < end; slot += NT) {
             uint32_t so = slot;
@@ -649,7 +650,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                         philox4x32_10(w, P.key0, P.key1);
                         if (w[0] < P.esc_thr) {
                             ncell = -1;
-                            atomicAdd(&P.ctr[1], 1ull);
+                            nesc++;
                         }
                     }
                 }
@@ -689,6 +690,11 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             st_at(S.u_out[1], so, u.y);
             st_at(S.u_out[2], so, u.z);
             if (P.track_ids) st_at(S.id_out, so, ld_at(S.id_in, src));
+        }
+        if (FRAME == kLeaky) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) nesc += __shfl_xor(nesc, o, 64);
+            if ((tid & 63) == 0 && nesc) atomicAdd(&P.ctr[1], (unsigned long long)nesc);
         }
         if (P.count_mig) {
 #pragma unroll

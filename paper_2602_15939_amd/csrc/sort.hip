@@ -285,8 +285,9 @@ hipError_t tile_sort(const int32_t* cell, const int32_t* n_live_in, int n_upper,
 //   scans:   destination starts (= the new tile offsets) and the dead bin's per-source starts;
 //   scatter: per source tile, in slot order, stable ranks per direction by wave ballots.
 // The result equals the stable radix sort: within a destination tile the particles come in
-// increasing source tile, i.e. increasing slot.  Slots from the previous dead bin stay dead,
-// after the particles that died since.
+// increasing source tile, i.e. increasing slot, for the live slots (the permutation's
+// observable part).  Slots from the previous dead bin stay dead at the end, after the
+// particles that died since.
 
 __device__ inline void dir_steps(int d, int& dx, int& dy, int& dz)
 {
@@ -428,7 +429,8 @@ __device__ __attribute__((always_inline)) inline void mig_offsets_body(const Mig
 }
 PIC_BATCHED_KERNEL(mig_offsets, MigOffArgs, kBlock)
 
-// block s < n_tiles: the particles of source tile s; block n_tiles: the previous dead bin
+// block s < n_tiles: the particles of source tile s (the newly dead go to the dead bin after
+// the live ones); block n_tiles: the offsets of the dead bin and the live count
 __device__ __attribute__((always_inline)) inline void mig_scatter_body(const MigScatterArgs& a, int blk, int, int)
 {
     if (a.gate.off()) return;
@@ -449,9 +451,8 @@ __device__ __attribute__((always_inline)) inline void mig_scatter_body(const Mig
     const int s = blk, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t live = start[g.n_tiles];
     if (s == g.n_tiles) {
-        const int beg = toff_prev[g.n_tiles];
-        const uint32_t base = live + dpre[g.n_tiles];
-        for (int i = beg + tid; i < n_upper; i += kBlock) perm[base + (uint32_t)(i - beg)] = (uint32_t)i;
+        // the slots of the previous dead bin stay dead at the end; nothing reads the
+        // permutation past the live count, so they are not enumerated again
         if (tid == 0) {
             toff[g.n_tiles] = (int32_t)live;
             toff[g.n_tiles + 1] = n_upper;

@@ -10,6 +10,8 @@ method's arithmetic).  Code units c = 1, dx = 1; skin depth 4 cells; |q|/m = 1 p
   leaky2d   2D leaky box, 2048^2 cells, 32 ppc per species, theta = 0.3, B0 along z with
             sigma = 1, in-plane fluctuations with a flat spectrum on |n| <= 128 (|k| <= k_max/8),
             rms dB/B0 = 1; probabilistic escape above gamma = 10 with t_esc = 10 L/c
+  leaky2d_stress  the same box with every particle on a gamma = 20 shell and t_esc = 100 dt
+            (1 % of the particles escape per step: the escape and compaction path under load)
 """
 from __future__ import annotations
 
@@ -40,7 +42,17 @@ def leaky2d(n=2048, ppc=32):
                 dt=0.45, maxwell_iters=8)
 
 
-WORKLOADS = {"shear3d": shear3d, "expand3d": expand3d, "leaky2d": leaky2d}
+def leaky2d_stress(n=2048, ppc=32):
+    """The leaky box with its escape path under load: every particle on a mono-energetic
+    gamma = 20 shell (isotropic directions) above the gamma = 10 threshold, t_esc = 100 dt, so
+    that 1 % of the particles escape (and are compacted away by the next sort) every step."""
+    w = leaky2d(n, ppc)
+    w.update(name=f"leaky2d_stress_{n}^2_ppc{ppc}", shell_gamma=20.0, t_esc=100 * 0.45)
+    return w
+
+
+WORKLOADS = {"shear3d": shear3d, "expand3d": expand3d, "leaky2d": leaky2d,
+             "leaky2d_stress": leaky2d_stress}
 
 
 def fields(w, seed):
@@ -75,6 +87,13 @@ def make_box(w, seed, device="cuda", track_ids=False):
     box.set_fields(torch.from_numpy(E).float(), torch.from_numpy(B).float())
     del E, B
     parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], seed, device=device)
+    if "shell_gamma" in w:  # momenta on a sphere |u| = sqrt(gamma^2 - 1), isotropic
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed) + 17)
+        for p in parts:
+            d = torch.randn(p["u"].shape, generator=gen, device=device, dtype=torch.float64)
+            d *= math.sqrt(w["shell_gamma"] ** 2 - 1.0) / torch.linalg.vector_norm(d, dim=0)
+            p["u"] = d.float().contiguous()
     for s, p in enumerate(parts):
         box.set_particles(s, p["cell"], p["off"], p["u"])
     del parts

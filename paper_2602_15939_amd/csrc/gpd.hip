@@ -182,10 +182,13 @@ __device__ inline float renorm(float s, int& dc)
 // CIC shape on the 3 nodes nearest-1..nearest+1 of one axis, xi = position - nearest node.
 struct Shape3 {
     float s0[3], ds[3];
+    float lo, hi;  // min and max of the old and new position relative to the nearest node
 };
 __device__ inline Shape3 shape3(float xi0, float xi1)
 {
     Shape3 S;
+    S.lo = fminf(xi0, xi1);
+    S.hi = fmaxf(xi0, xi1);
     const float a0 = fmaxf(0.f, -xi0), b0 = 1.f - fabsf(xi0), c0 = fmaxf(0.f, xi0);
     const float a1 = fmaxf(0.f, -xi1), b1 = 1.f - fabsf(xi1), c1 = fmaxf(0.f, xi1);
     S.s0[0] = a0;
@@ -206,14 +209,18 @@ __device__ inline Shape3 shape3(float xi0, float xi1)
 // node that neither the old nor the new shape touches, or an edge whose DS factor is zero.  A
 // particle that stays on one side of its nearest node in every axis has 12 (3D) / 10 (2D)
 // non-zero terms out of 54 / 21, and skipping the rest leaves the integer sums unchanged.
+// The lower outer node is touched by the old or the new shape exactly when one of the two
+// positions lies below the nearest node (S0 or S1 of that node non-zero), the upper one when one
+// lies above.  An outer edge carries current only if its outer node is touched (its DS can still
+// be zero, for an unmoved coordinate: the term then adds an exact zero).
 struct Use3 {
     bool n0, n2;  // outer nodes touched by the old or the new shape
-    bool e0, e2;  // DS of the outer nodes non-zero (the two edges carry current)
+    bool e0, e2;  // the two outer edges may carry current
 };
 __device__ inline Use3 use3(const Shape3& S)
 {
-    return Use3{S.s0[0] != 0.f || S.ds[0] != 0.f, S.s0[2] != 0.f || S.ds[2] != 0.f,
-                S.ds[0] != 0.f, S.ds[2] != 0.f};
+    const bool n0 = S.lo < 0.f, n2 = S.hi > 0.f;
+    return Use3{n0, n2, n0, n2};
 }
 __device__ inline bool used(const Use3& U, int b) { return b == 0 ? U.n0 : (b == 2 ? U.n2 : true); }
 
@@ -537,7 +544,6 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 u = push_expand(u, E, B, S.qm_hdt, P.lam1p, P.ltil, P.tfac);
             else
                 u = push_boris(u, E, B, S.qm_hdt);
-            if (!(isfinite(u.x) && isfinite(u.y) && isfinite(u.z))) latch(P.err, 2u);
 
             // ---- displacement of the deposit (comoving for the shearing box, primed for the
             // expanding box)
@@ -545,15 +551,17 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             const float hs = P.dt * ig;
             f3 D = hs * u;
             if (FRAME == kExpand) D = mk(D.x * P.linv[0], D.y * P.linv[1], D.z * P.linv[2]);
-            if (fabsf(D.x) >= 0.5f || fabsf(D.y) >= 0.5f || (DIM == 3 && fabsf(D.z) >= 0.5f))
-                latch(P.err, 1u);
+            // one test catches both: a non-finite momentum makes D NaN, which fails every
+            // comparison; a finite one fails it when a displacement reaches half a cell
+            if (!(fabsf(D.x) < 0.5f && fabsf(D.y) < 0.5f && (DIM == 2 || fabsf(D.z) < 0.5f)))
+                latch(P.err, (isfinite(u.x) && isfinite(u.y) && isfinite(u.z)) ? 1u : 2u);
 
             // ---- deposit xn -> xn + D
             if (fuse) {
                 const int hx = ox >= 0.5f, hy = oy >= 0.5f, hz = DIM == 3 ? (oz >= 0.5f) : 0;
                 const float x0 = ox - (float)hx, y0 = oy - (float)hy, z0 = oz - (float)hz;
                 const Shape3 SX = shape3(x0, x0 + D.x), SY = shape3(y0, y0 + D.y);
-                const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}};
+                const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}, 0.f, 0.f};
                 if (in_tile) {
                     LdsAcc<G> acc = lds_acc<G, DIM>(Jl, rx + hx, ry + hy, rz + hz);
                     esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt * P.jscale, D.z);
@@ -764,7 +772,7 @@ __global__ __launch_bounds__(NT) void deposit_kernel(StepDev P)
             const int hx = ox >= 0.5f, hy = oy >= 0.5f, hz = DIM == 3 ? (oz >= 0.5f) : 0;
             const float x0 = ox - (float)hx, y0 = oy - (float)hy, z0 = oz - (float)hz;
             const Shape3 SX = shape3(x0, x0 + D.x), SY = shape3(y0, y0 + D.y);
-            const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}};
+            const Shape3 SZ = DIM == 3 ? shape3(z0, z0 + D.z) : Shape3{{0, 1, 0}, {0, 0, 0}, 0.f, 0.f};
             if (in_tile) {
                 LdsAcc<G> acc = lds_acc<G, DIM>(Jl, rx + hx, ry + hy, rz + hz);
                 esirkepov<DIM>(acc, SX, SY, SZ, S.q_dt * P.jscale, D.z);

@@ -59,9 +59,8 @@ class Case:
         if parts is None:
             parts = synth.pair_plasma(tuple(n), ppc, theta, seed)
         self.parts = [{k: v.cpu().numpy() for k, v in p.items()} for p in parts]
-        wp, qmac, _ = synth.plasma_params(ppc)
         if q is None:
-            q = qmac
+            q = synth.plasma_params(max(ppc, 1))[1]  # an empty box keeps the 1-ppc charge
         self.q = q
         self.qms = (-1.0, 1.0)
         if fields is None:

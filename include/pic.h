@@ -66,6 +66,8 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_DERR_ORDER 4u    /* a particle outside its tile: handled on the slow path */
 #define PIC_DERR_CELL 8u     /* pic_set_particles met a cell index outside the grid */
 #define PIC_DERR_SORT 16u    /* a batched sort found a particle beyond the neighbouring tiles */
+#define PIC_DERR_NOCONVERGE 32u /* shearing box, maxwell_tol > 0: the fixed-point sweeps of a
+                                   Maxwell step did not meet the tolerance within maxwell_iters */
 
 typedef struct pic_box_desc {
     int32_t dim;         /* 2 or 3 */
@@ -94,7 +96,13 @@ typedef struct pic_box_desc {
     int32_t tile[3];         /* tile shape in cells (0 = default: 8^3 in 3D, 16x16 in 2D;
                                 supported: 8^3, 4^3; 16x16, 8x8, 32x16, 32x32); pic_autotune
                                 picks one by measurement */
-    int32_t maxwell_iters;   /* shearing box: fixed-point iterations per step (0 = 8) */
+    int32_t maxwell_iters;   /* shearing box: fixed-point sweeps per step (0 = 8, at most 64);
+                                with maxwell_tol > 0 the most sweeps a step may take */
+    double maxwell_tol;      /* shearing box: 0 = always maxwell_iters sweeps; > 0 = stop after
+                                the first sweep k with max|F^{k+1} - F^k| <= maxwell_tol *
+                                max|F^{k+1}| over the six interior field components (FP32
+                                comparison, decided on the device; Sec. 2.2 leaves the
+                                stopping rule open) */
     uint32_t flags;          /* PIC_BOX_* */
     void* stream;            /* hipStream_t */
 } pic_box_desc;
@@ -118,6 +126,8 @@ typedef struct pic_box_info {
     int64_t n_sort_migrations; /* sorts done by the neighbour-migration counting sort */
     int64_t n_sort_fallbacks;  /* of those, sorts that found a particle beyond the
                                   neighbouring tiles and fell back to the radix sort */
+    int32_t maxwell_sweeps;    /* shearing box: fixed-point sweeps of the last Maxwell step
+                                  (0 before the first step and for the other frames) */
 } pic_box_info;
 
 /* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard
@@ -207,7 +217,11 @@ int32_t pic_shear_remap(pic_box* const* boxes, int32_t nb, uint32_t what);
 
 /* One Maxwell step of the box frame: Yee leapfrog (plain, leaky), Yee with the scale
    factors of Sec. 3.2 (expanding), implicit midpoint with upwinded advection solved by
-   fixed-point iteration (shearing box, Sec. 2.2).  Advances the box time by dt. */
+   fixed-point iteration (shearing box, Sec. 2.2): maxwell_iters sweeps, or with maxwell_tol
+   > 0 sweeps until the tolerance is met, where each sweep reduces its largest change and
+   largest value on the device and the sweeps after the first converged one return at once
+   (no host round trip; PIC_DERR_NOCONVERGE latches if none converges).  Advances the box
+   time by dt. */
 int32_t pic_maxwell_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
 
 /* Escape compaction: the tile sort with the dead bin, which removes the particles marked

@@ -17,7 +17,7 @@ LEAKY_DISPLACEMENT, LEAKY_PROBABILISTIC = 0, 1
 FUSE_DEPOSIT = 1
 REMAP_FIELDS, REMAP_CURRENT = 1, 2
 BOX_TRACK_IDS = 1
-DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT = 1, 2, 4, 8, 16
+DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT, DERR_NOCONVERGE = 1, 2, 4, 8, 16, 32
 STEP_BATCHED = 1
 STEP_GRAPH = 2
 TUNE_BATCHED = 1
@@ -33,7 +33,8 @@ class pic_box_desc(C.Structure):
         ("leaky_gamma_thr", C.c_double),
         ("n_species", C.c_int32), ("q_over_m", C.c_double * 2), ("q_macro", C.c_double * 2),
         ("capacity", C.c_int64 * 2), ("seed", C.c_uint64), ("box_id", C.c_uint32),
-        ("tile", C.c_int32 * 3), ("maxwell_iters", C.c_int32), ("flags", C.c_uint32),
+        ("tile", C.c_int32 * 3), ("maxwell_iters", C.c_int32), ("maxwell_tol", C.c_double),
+        ("flags", C.c_uint32),
         ("stream", C.c_void_p),
     ]
 
@@ -45,7 +46,7 @@ class pic_box_info(C.Structure):
         ("n_escaped", C.c_int64), ("field_energy_E", C.c_double * 3),
         ("field_energy_B", C.c_double * 3), ("kinetic_energy", C.c_double),
         ("momentum", C.c_double * 3),
-        ("n_sort_migrations", C.c_int64), ("n_sort_fallbacks", C.c_int64),
+        ("n_sort_migrations", C.c_int64), ("n_sort_fallbacks", C.c_int64), ("maxwell_sweeps", C.c_int32),
     ]
 
 

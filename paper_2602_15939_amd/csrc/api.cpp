@@ -72,6 +72,8 @@ struct pic_box {
     float* mj = nullptr;
     uint32_t* err = nullptr;
     unsigned long long* ctr = nullptr;
+    uint32_t* conv = nullptr;  // shearing box: convergence record of the tolerance-mode sweeps
+    int last_sweeps = 0;       // sweeps of the last Maxwell step (-1: the device record has it)
     double* red_part = nullptr;
     double* red_out = nullptr;
     int64_t step = 0;
@@ -479,6 +481,26 @@ int32_t fold_box(pic_box* b)
                                  b->d.dt, shear_offset(b, th), b->st));
 }
 
+// finalize record of a tolerance-mode step whose last sweep writes set `last`: the iterate of
+// an earlier converged sweep is copied there from the other iterate set when needed
+KsbFin ksb_fin(const pic_box* b, int K, int last)
+{
+    const int sn = b->cur_set, sb2 = (sn + 2) % 3;
+    KsbFin F{};
+    F.G = b->G;
+    F.conv = b->conv;
+    F.sweeps = reinterpret_cast<int32_t*>(b->conv + 2 * kKsbMaxSweeps);
+    F.err = b->err;
+    F.tol = (float)b->d.maxwell_tol;
+    F.K = K;
+    const int other = last == sb2 ? sn : sb2;
+    for (int c = 0; c < 6; c++) {
+        F.src[c] = b->set[other][c];
+        F.dst[c] = b->set[last][c];
+    }
+    return F;
+}
+
 int32_t maxwell_box(pic_box* b)
 {
     const double dt = b->d.dt;
@@ -491,6 +513,9 @@ int32_t maxwell_box(pic_box* b)
         const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
         const int sn = b->cur_set, sc = (sn + 1) % 3, sb2 = (sn + 2) % 3;
         const double dys1 = shear_offset(b, t1);
+        const bool tol = b->d.maxwell_tol > 0.0;
+        if (tol && zero_floats(reinterpret_cast<float*>(b->conv), 2 * K, st) != hipSuccess)
+            return PIC_EDEVICE;
         int sk = sn, so = sb2;
         for (int k = 0; k < K; k++) {
             KsbDev Kd{};
@@ -504,7 +529,14 @@ int32_t maxwell_box(pic_box* b)
             Kd.dt = (float)dt;
             Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
             Kd.half_nx = 0.5f * (float)b->n[0];
+            if (tol) {
+                Kd.conv = b->conv;
+                Kd.tol = (float)b->d.maxwell_tol;
+                Kd.k = k;
+            }
             if (ksb_sweep(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
+            if (tol && k == K - 1 && ksb_finalize(ksb_fin(b, K, so), st) != hipSuccess)
+                return PIC_EDEVICE;
             // the 3D sweep reads the y and z halo at the periodic images: between sweeps only
             // the x guards (shearing-periodic images) are filled, all of them after the last
             const bool x_only = b->dim == 3 && k < K - 1;
@@ -513,6 +545,7 @@ int32_t maxwell_box(pic_box* b)
             so = so == sb2 ? sn : sb2;
         }
         b->cur_set = sk;
+        b->last_sweeps = tol ? -1 : K;
         return PIC_OK;
     }
     // Yee: B half step, E full step, B half step, with the expanding-box factors
@@ -883,16 +916,32 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
             const int sn = b->cur_set;
             rot[i] = Rot{sn, (sn + 1) % 3, (sn + 2) % 3, sn, (sn + 2) % 3};
         }
+        // tolerance-mode boxes: clear their convergence records first
+        {
+            std::vector<ZeroArgs> cz;
+            std::vector<uint32_t> czb;
+            for (int i = 0; i < nb; i++) {
+                pic_box* b = boxes[i];
+                if (b->d.frame != PIC_FRAME_SHEAR || !(b->d.maxwell_tol > 0.0)) continue;
+                const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
+                cz.push_back(ZeroArgs{b->conv, (int64_t)2 * K});
+                czb.push_back(grid_blocks(2 * K));
+            }
+            plan.grid(kBatchZero, cz, czb, 1);
+        }
         for (int k = 0; k < kmax; k++) {
             std::vector<KsbDev> ks;
             std::vector<uint32_t> ksb;
             std::vector<FillArgs> kf;
             std::vector<uint32_t> kfb;
+            std::vector<KsbFin> kz;
+            std::vector<uint32_t> kzb;
             for (int i = 0; i < nb; i++) {
                 pic_box* b = boxes[i];
                 if (b->d.frame != PIC_FRAME_SHEAR) continue;
                 const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
                 if (k >= K) continue;
+                const bool tol = b->d.maxwell_tol > 0.0;
                 Rot& r = rot[i];
                 KsbDev Kd{};
                 Kd.G = b->G;
@@ -905,15 +954,28 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
                 Kd.dt = (float)b->d.dt;
                 Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
                 Kd.half_nx = 0.5f * (float)b->n[0];
+                if (tol) {
+                    Kd.conv = b->conv;
+                    Kd.tol = (float)b->d.maxwell_tol;
+                    Kd.k = k;
+                }
                 ks.push_back(Kd);
                 ksb.push_back(grid_blocks((int64_t)b->n[0] * b->n[1] * b->n[2]));
+                if (tol && k == K - 1) {
+                    kz.push_back(ksb_fin(b, K, r.so));
+                    kzb.push_back(kKsbFinBlocks);
+                }
                 const double t1 = time_of(b, b->step) + b->d.dt;
                 plan_fill(kf, kfb, b->G, b->set[r.so], 6, 1, shear_offset(b, t1));
                 r.sk = r.so;
                 r.so = r.so == r.sb2 ? r.sn : r.sb2;
-                if (k == K - 1) b->cur_set = r.sk;
+                if (k == K - 1) {
+                    b->cur_set = r.sk;
+                    b->last_sweeps = tol ? -1 : K;
+                }
             }
             plan.grid(k == 0 ? kBatchKsbFirst : kBatchKsbNext, ks, ksb, 1);
+            plan.grid(kBatchKsbFinal, kz, kzb, 1);
             plan.grid(kBatchFill, kf, kfb, 6);
         }
         // time advance; guard cells of the non-shear fields at t^{n+1}
@@ -1062,6 +1124,9 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     if (!(d->dt > 0) || d->dt * std::sqrt((double)d->dim) >= 1.0) return PIC_EINVAL;
     if (d->frame < 0 || d->frame > 3) return PIC_EINVAL;
     if (d->n_species < 1 || d->n_species > 2) return PIC_EINVAL;
+    if (d->maxwell_iters < 0 || d->maxwell_iters > kKsbMaxSweeps || !(d->maxwell_tol >= 0.0) ||
+        !(d->maxwell_tol < 1.0))
+        return PIC_EINVAL;
     if (d->frame == PIC_FRAME_LEAKY) {
         if (d->leaky_mode == PIC_LEAKY_DISPLACEMENT && !(d->leaky_l_esc > 0 && d->leaky_theta_inj > 0))
             return PIC_EINVAL;
@@ -1166,6 +1231,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     }
     if (!r) r = dalloc(b, b->err, 4);
     if (!r) r = dalloc(b, b->ctr, 4);
+    if (!r && d->frame == PIC_FRAME_SHEAR) r = dalloc(b, b->conv, kKsbConvWords);
     if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
     if (!r) r = dalloc(b, b->red_out, 16);
     if (!r && d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
@@ -1173,6 +1239,8 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     if (b->alloc_pass == 1) return r;
     if (!r && hipMemsetAsync(b->err, 0, 4 * sizeof(uint32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
     if (!r && hipMemsetAsync(b->ctr, 0, 4 * sizeof(unsigned long long), b->st) != hipSuccess) r = PIC_EDEVICE;
+    if (!r && b->conv && hipMemsetAsync(b->conv, 0, kKsbConvWords * sizeof(uint32_t), b->st) != hipSuccess)
+        r = PIC_EDEVICE;
     if (!r && b->mj) {
         std::vector<float> tab;
         build_mj_table(d->leaky_theta_inj, tab);
@@ -1525,6 +1593,11 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
     unsigned long long ctr[3] = {0, 0, 0};
     if (hipMemcpy(&err, b->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(ctr, b->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EDEVICE;
+    info->maxwell_sweeps = b->last_sweeps;
+    if (b->last_sweeps < 0 &&
+        hipMemcpy(&info->maxwell_sweeps, b->conv + 2 * kKsbMaxSweeps, sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
         return PIC_EDEVICE;
     info->n_sort_migrations = b->n_migrations;
     info->n_sort_fallbacks = (int64_t)ctr[2];

@@ -322,9 +322,55 @@ __device__ inline void ksb_operator(const Acc& V, float v0, float vh, float sO, 
     L[EZ] = cBz + v0 * updy(EZ, -v0) - v0 * dEy_dz;
 }
 
-// output of one cell: FIRST writes C and F^1 from F^n, later sweeps F^{k+1} from C
+// ---- tolerance mode of the sweeps
+// a sweep's (largest change, largest value) pair meets the tolerance (a finite change only)
+__device__ inline bool ksb_met(const uint32_t* pair, float tol)
+{
+    const float d = __uint_as_float(pair[0]);
+    return d <= tol * __uint_as_float(pair[1]) && d <= 3.4028235e38f;
+}
+// the sweep before this one met the tolerance: uniform over the grid, tested before any work
+__device__ inline bool ksb_skip(const KsbDev& K)
+{
+    return K.conv && K.k > 0 && ksb_met(K.conv + 2 * (K.k - 1), K.tol);
+}
+// running maxima of |F^{k+1} - F^k| (NaN -> +inf) and |F^{k+1}|
+__device__ inline void ksb_track(float fo, float fk, float& dm, float& fm)
+{
+    const float d = fabsf(fo - fk);
+    dm = d == d ? fmaxf(dm, d) : __int_as_float(0x7f800000);
+    fm = fmaxf(fm, fabsf(fo));
+}
+// workgroup maxima (NT threads, whole waves), one atomic pair per workgroup
+template <int NT>
+__device__ inline void ksb_reduce(float dm, float fm, uint32_t* pair)
+{
+    __shared__ float red[2][NT / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        dm = fmaxf(dm, __shfl_xor(dm, o, 64));
+        fm = fmaxf(fm, __shfl_xor(fm, o, 64));
+    }
+    const int w = threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0) {
+        red[0][w] = dm;
+        red[1][w] = fm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 1; j < NT / 64; j++) {
+            dm = fmaxf(dm, red[0][j]);
+            fm = fmaxf(fm, red[1][j]);
+        }
+        atomicMax(pair, __float_as_uint(dm));
+        atomicMax(pair + 1, __float_as_uint(fm));
+    }
+}
+
+// output of one cell: FIRST writes C and F^1 from F^n, later sweeps F^{k+1} from C; Fk is
+// the iterate at the cell (F^n for the first sweep)
 template <bool FIRST>
-__device__ inline void ksb_store(const KsbDev& K, int64_t i, const float L[6], const float Fn[6])
+__device__ inline void ksb_store(const KsbDev& K, int64_t i, const float L[6], const float Fk[6],
+                                 float& dm, float& fm)
 {
     const float h = 0.5f * K.dt;
     const float fpdt = 4.f * 3.14159265358979f * K.dt;
@@ -332,13 +378,15 @@ __device__ inline void ksb_store(const KsbDev& K, int64_t i, const float L[6], c
     for (int c = 0; c < 6; c++) {
         float Cv;
         if (FIRST) {
-            Cv = Fn[c] + h * L[c];
+            Cv = Fk[c] + h * L[c];
             if (c >= EX) Cv -= fpdt * K.J[c - EX][i];
             K.C[c][i] = Cv;
         } else {
             Cv = K.C[c][i];
         }
-        K.Fo[c][i] = Cv + h * L[c];
+        const float v = Cv + h * L[c];
+        K.Fo[c][i] = v;
+        ksb_track(v, Fk[c], dm, fm);
     }
 }
 
@@ -346,25 +394,29 @@ __device__ inline void ksb_store(const KsbDev& K, int64_t i, const float L[6], c
 template <bool FIRST>
 __device__ __attribute__((always_inline)) inline void ksb_sweep_body(const KsbDev& K, int blk, int, int)
 {
+    if (ksb_skip(K)) return;
     const GridDev& G = K.G;
     const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
-    int x, y, z;
-    cell_of(G, t, x, y, z);
-    const int64_t i = gidx(G, x, y, z);
-    const int64_t sy = G.sy, sz = G.sz;
-    const float* const* F = K.Fk;
-    auto V = [&](int c, int dx, int dy, int dz) { return F[c][i + dx + sy * dy + sz * dz]; };
-    const float v0 = -K.sO * ((float)x - K.half_nx);         // at x = i
-    const float vh = -K.sO * ((float)x + 0.5f - K.half_nx);  // at x = i + 1/2
-    float L[6], Fn[6];
-    if (G.dim == 3)
-        ksb_operator<true>(V, v0, vh, K.sO, L);
-    else
-        ksb_operator<false>(V, v0, vh, K.sO, L);
+    float dm = 0.f, fm = 0.f;
+    if (t < (int64_t)G.n[0] * G.n[1] * G.n[2]) {
+        int x, y, z;
+        cell_of(G, t, x, y, z);
+        const int64_t i = gidx(G, x, y, z);
+        const int64_t sy = G.sy, sz = G.sz;
+        const float* const* F = K.Fk;
+        auto V = [&](int c, int dx, int dy, int dz) { return F[c][i + dx + sy * dy + sz * dz]; };
+        const float v0 = -K.sO * ((float)x - K.half_nx);         // at x = i
+        const float vh = -K.sO * ((float)x + 0.5f - K.half_nx);  // at x = i + 1/2
+        float L[6], Fk[6];
+        if (G.dim == 3)
+            ksb_operator<true>(V, v0, vh, K.sO, L);
+        else
+            ksb_operator<false>(V, v0, vh, K.sO, L);
 #pragma unroll
-    for (int c = 0; c < 6; c++) Fn[c] = F[c][i];
-    ksb_store<FIRST>(K, i, L, Fn);
+        for (int c = 0; c < 6; c++) Fk[c] = F[c][i];
+        ksb_store<FIRST>(K, i, L, Fk, dm, fm);
+    }
+    if (K.conv) ksb_reduce<kBlock>(dm, fm, K.conv + 2 * K.k);
 }
 __device__ __attribute__((always_inline)) inline void ksb_first_body(const KsbDev& K, int blk, int n, int y) { ksb_sweep_body<true>(K, blk, n, y); }
 __device__ __attribute__((always_inline)) inline void ksb_next_body(const KsbDev& K, int blk, int n, int y) { ksb_sweep_body<false>(K, blk, n, y); }
@@ -385,6 +437,7 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
     constexpr int NT = KX * KY;
     constexpr int PER = (KXH * KYH + NT - 1) / NT;  // plane positions per thread
     __shared__ float P[3][6][KYH * KXH];
+    if (ksb_skip(K)) return;
     const GridDev& G = K.G;
     const int tid = threadIdx.x, tx = tid % KX, ty = tid / KX;
     // tiles x fastest, then y, then z chunk; each XCD takes a contiguous range so that the
@@ -440,6 +493,7 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
     int sm = 0, sc = 1, sp = 2;
     const int c0 = (ty + 1) * KXH + (tx + 1);
     const int64_t i0 = gidx(G, x, y, 0);
+    float dm = 0.f, fm = 0.f;
     for (int z = z0; z < z1; z++) {
         stash(sp);                   // plane z+1
         if (z + 2 <= z1) fetch(z + 2);  // in flight during this plane
@@ -464,11 +518,17 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
                     float cv = P[sc][c][c0] + h * L[c];
                     if (c >= EX) cv -= fpdt * K.J[c - EX][i];
                     K.C[c][i] = cv;
-                    K.Fo[c][i] = cv + h * L[c];
+                    const float v = cv + h * L[c];
+                    K.Fo[c][i] = v;
+                    if (K.conv) ksb_track(v, P[sc][c][c0], dm, fm);
                 }
             } else {
 #pragma unroll
-                for (int c = 0; c < 6; c++) K.Fo[c][i] = Cv[c] + h * L[c];
+                for (int c = 0; c < 6; c++) {
+                    const float v = Cv[c] + h * L[c];
+                    K.Fo[c][i] = v;
+                    if (K.conv) ksb_track(v, P[sc][c][c0], dm, fm);
+                }
             }
         }
         __syncthreads();
@@ -477,7 +537,42 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
         sc = sp;
         sp = t;
     }
+    if (K.conv) ksb_reduce<NT>(dm, fm, K.conv + 2 * K.k);
 }
+
+// End of a tolerance-mode step (one record per box): find the first sweep that met the
+// tolerance, report the sweep count, latch kErrNoConverge if none did, and move that sweep's
+// iterate into the set the step hands on when it sits in the other one.
+__device__ __attribute__((always_inline)) inline void ksb_final_body(const KsbFin& F, int blk, int nblk, int)
+{
+    __shared__ int kstar;
+    if (threadIdx.x == 0) {
+        int k = F.K - 1;
+        bool met = false;
+        for (int j = 0; j < F.K && !met; j++)
+            if (ksb_met(F.conv + 2 * j, F.tol)) {
+                k = j;
+                met = true;
+            }
+        kstar = k;
+        if (blk == 0) {
+            *F.sweeps = k + 1;
+            if (!met) atomicOr(F.err, kErrNoConverge);
+        }
+    }
+    __syncthreads();
+    if (((F.K - 1 - kstar) & 1) == 0) return;
+    const GridDev& G = F.G;
+    const int64_t n = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    for (int64_t t = (int64_t)blk * kBlock + threadIdx.x; t < n; t += (int64_t)nblk * kBlock) {
+        int x, y, z;
+        cell_of(G, t, x, y, z);
+        const int64_t i = gidx(G, x, y, z);
+#pragma unroll
+        for (int c = 0; c < 6; c++) F.dst[c][i] = F.src[c][i];
+    }
+}
+PIC_BATCHED_KERNEL(ksb_final, KsbFin, kBlock)
 
 // ------------------------------------------------------------------ utilities
 __device__ __attribute__((always_inline)) inline void zero_body(const ZeroArgs& a, int blk, int, int)
@@ -649,6 +744,11 @@ hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
     }
     return hipGetLastError();
 }
+hipError_t ksb_finalize(const KsbFin& F, hipStream_t st)
+{
+    ksb_final_kernel<<<kKsbFinBlocks, kBlock, 0, st>>>(F);
+    return hipGetLastError();
+}
 hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks, int ydim,
                       hipStream_t st)
 {
@@ -672,6 +772,7 @@ hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks,
         ksb_first_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbDev*>(table), m);
         break;
     case kBatchKsbNext: ksb_next_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbDev*>(table), m); break;
+    case kBatchKsbFinal: ksb_final_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbFin*>(table), m); break;
     }
     return hipGetLastError();
 }

@@ -51,6 +51,7 @@ struct Tiles {
 // offset cy_out (leaving through the outer face) or cy_in (inner face) before dy is taken.
 constexpr int kMigDirs = 28;
 constexpr uint32_t kErrSort = 16u;  // a batched sort met a particle beyond the neighbour tiles
+constexpr uint32_t kErrNoConverge = 32u;  // shearing-box sweeps missed their tolerance
 constexpr int kMigDead = 27;
 struct MigGeo {
     int nt[3], lt[3];
@@ -303,6 +304,32 @@ struct KsbDev {
     float* Fo[6];        // next iterate (interior)
     const float* J[3];
     float dt, sO, half_nx;
+    // tolerance mode (conv != nullptr): sweep k adds max|F^{k+1} - F^k| and max|F^{k+1}| (FP32
+    // bit patterns, non-negative, so unsigned order is float order; NaN counts as +inf) into
+    // conv[2k], conv[2k+1], which start at zero; it returns at once when the sweep before it
+    // met the tolerance, leaving its pair at zero, which reads as met for the next one
+    uint32_t* conv;
+    float tol;
+    int k;
+};
+constexpr int kKsbMaxSweeps = 64;
+// words of a box's convergence record: kKsbMaxSweeps pairs, then the sweep count of the last
+// step
+constexpr int kKsbConvWords = 2 * kKsbMaxSweeps + 2;
+
+// End of a tolerance-mode step: k* = the first sweep that met the tolerance (the last sweep K-1
+// if none did, which latches kErrNoConverge).  The iterate of sweep k* sits in the field set
+// that sweep K-1 would have written when K-1-k* is even, in the other set otherwise: then
+// the interior of src (that other set) is copied to dst.
+struct KsbFin {
+    GridDev G;
+    const uint32_t* conv;
+    int32_t* sweeps;
+    uint32_t* err;
+    float tol;
+    int K;
+    const float* src[6];
+    float* dst[6];
 };
 
 // Sort workspace of one species.
@@ -397,7 +424,7 @@ hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upp
 // batched launches of the grid and sort kernels (tables of per-unit arguments on the device)
 enum GridBatchKind {
     kBatchZero, kBatchFill, kBatchFoldP, kBatchAdvect, kBatchFoldX, kBatchYeeB, kBatchYeeE,
-    kBatchKsbFirst, kBatchKsbNext
+    kBatchKsbFirst, kBatchKsbNext, kBatchKsbFinal
 };
 hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks, int ydim,
                       hipStream_t st);
@@ -415,6 +442,8 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, in
 hipError_t yee_b(const MaxwellDev& M, hipStream_t st);
 hipError_t yee_e(const MaxwellDev& M, hipStream_t st);
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st);
+hipError_t ksb_finalize(const KsbFin& F, hipStream_t st);
+constexpr int kKsbFinBlocks = 512;  // workgroups per box of the finalize copy (grid stride)
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st);
 hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense,
                          hipStream_t st);

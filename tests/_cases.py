@@ -51,7 +51,7 @@ class Case:
     def __init__(self, dim, n, frame="plain", ppc=4, theta=0.3, seed=1, dt=0.45, fields=None,
                  tile=(0, 0, 0), shear_s=1.5, omega0=0.02, adot=2e-3, axis_mask=0b011,
                  leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=3.0, t_esc=9.0, gamma_thr=10.0,
-                 theta_inj=0.3, maxwell_iters=4, q=None, parts=None, track_ids=True,
+                 theta_inj=0.3, maxwell_iters=4, maxwell_tol=0.0, q=None, parts=None, track_ids=True,
                  use_3vec=0, box_seed=0x5EED1234ABCDEF01, box_id=7, stream=None):
         self.dim = dim
         self.n = tuple(list(n) + [1] * (3 - len(n)))
@@ -79,6 +79,7 @@ class Case:
                        leaky_mode=leaky_mode, leaky_l_esc=l_esc, leaky_use_3vec=use_3vec,
                        leaky_theta_inj=theta_inj, leaky_t_esc=t_esc, leaky_gamma_thr=gamma_thr,
                        seed=box_seed, box_id=box_id, tile=tile, maxwell_iters=maxwell_iters,
+                       maxwell_tol=maxwell_tol,
                        track_ids=track_ids, stream=stream)
         self.gpu.set_fields(torch.from_numpy(self.E32), torch.from_numpy(self.B32))
         for s, p in enumerate(self.parts):
@@ -90,7 +91,8 @@ class Case:
                                    omega0=omega0, adot=adot, axis_mask=axis_mask,
                                    leaky_mode=leaky_mode, l_esc=l_esc, use_3vec=use_3vec,
                                    t_esc=t_esc, gamma_thr=gamma_thr, seed=box_seed, box_id=box_id,
-                                   mj_table=mj, maxwell_iters=maxwell_iters, **common)
+                                   mj_table=mj, maxwell_iters=maxwell_iters,
+                                   maxwell_tol=maxwell_tol, **common)
         self.E = self.E32.astype(np.float64)
         self.B = self.B32.astype(np.float64)
         self.J = np.zeros_like(self.E)

@@ -74,7 +74,8 @@ def _desc(**kw):
     d.leaky_l_esc = kw.get("l_esc", 0.0)
     d.leaky_theta_inj = kw.get("theta_inj", 0.0)
     d.leaky_t_esc = kw.get("t_esc", 0.0)
-    d.maxwell_iters = 8
+    d.maxwell_iters = kw.get("maxwell_iters", 8)
+    d.maxwell_tol = kw.get("maxwell_tol", 0.0)
     return d
 
 
@@ -94,6 +95,11 @@ def _desc(**kw):
     dict(capacity=1 << 30),            # particle arrays use 32-bit byte offsets
     dict(n=(2048, 2048, 2048)),        # packed cell code needs 33 bits
     dict(dim=2, n=(64, 64, 5)),
+    dict(maxwell_iters=-1),
+    dict(maxwell_iters=65),            # the convergence record holds 64 sweeps
+    dict(maxwell_tol=-1e-6),
+    dict(maxwell_tol=float("nan")),
+    dict(maxwell_tol=1.0),
 ])
 def test_invalid_descriptors_rejected_on_the_host(lib, bad):
     out = C.c_void_p()
@@ -137,3 +143,29 @@ def test_tile_candidates_on_the_host(lib):
 def test_autotune_argument_checks_on_the_host(lib):
     tile = (C.c_int32 * 3)()
     assert lib.pic_autotune(None, 0, 3, tile, None, 0, None) == L.PIC_EINVAL
+
+
+@pytest.mark.parametrize("struct", ["pic_box_desc", "pic_box_info"])
+def test_binding_structs_match_the_header(struct, tmp_path):
+    """Size and every field offset of the ctypes structures equal the C compiler's."""
+    import subprocess
+
+    py = getattr(L, struct)
+    fields = [f[0] for f in py._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text(f"""#include <stddef.h>
+#include <stdio.h>
+#include "pic.h"
+int main(void) {{
+    printf("%zu\\n", sizeof({struct}));
+{body}    return 0;
+}}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                           text=True).stdout.split()]
+    assert got[0] == C.sizeof(py)
+    assert got[1:] == [getattr(py, f).offset for f in fields]

@@ -114,12 +114,14 @@ typedef struct pic_box_info {
     double t;                /* t^n = step*dt */
     double dys;              /* shearing box: Delta y_s(t) reduced mod n[1] (Sec. 2.1) */
     double a;                /* expanding box: l(t) of the expanding axes */
-    int64_t n_particles[2];  /* live particles per species */
+    int64_t n_particles[2];  /* particles in each species' arrays: those that escaped in the
+                                last step (probabilistic escape) still hold a slot, with cell
+                                -1, until the next sort drops them */
     uint32_t errors;         /* sticky PIC_DERR_* bits */
     int64_t n_slow;          /* particles handled outside their tile (counter) */
     int64_t n_escaped;       /* probabilistic escapes (counter) */
     /* FP64 reductions: sum E_c^2/8pi, sum B_c^2/8pi (c = x,y,z), kinetic energy
-       sum m(gamma-1), momentum sum m u */
+       sum m(gamma-1), momentum sum m u (particle sums skip the escaped particles) */
     double field_energy_E[3], field_energy_B[3];
     double kinetic_energy;
     double momentum[3];
@@ -128,6 +130,9 @@ typedef struct pic_box_info {
                                   neighbouring tiles and fell back to the radix sort */
     int32_t maxwell_sweeps;    /* shearing box: fixed-point sweeps of the last Maxwell step
                                   (0 before the first step and for the other frames) */
+    double pressure[3];        /* sum m u_c^2 / gamma (c = x,y,z): the diagonal of the kinetic
+                                  stress; over the box volume, (sum of the three)/3 is the
+                                  pressure n k T of the plasma-beta diagnostic of Sec. 4.2 */
 } pic_box_info;
 
 /* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard
@@ -248,6 +253,19 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
 
 /* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */
 int32_t pic_box_get(pic_box* box, pic_box_info* info);
+
+#define PIC_HIST_MAX_BINS 4096
+
+/* Particle energy distribution of one species (the diagnostic of Sec. 4.2): the kinetic
+   energy of each particle that has not escaped, gamma - 1 = u.u / (1 + sqrt(1 + u.u)) in FP64 from its FP32
+   momentum (units of m c^2), is placed by the nbins + 1 edges (host memory, FP64, strictly
+   increasing and finite): counts_out[0] receives the particles below edges[0], counts_out[1 + b]
+   those in [edges[b], edges[b + 1]), counts_out[nbins + 1] those at or above edges[nbins]
+   (and any non-finite energy: the momentum latches PIC_DERR_NAN first).  counts_out: nbins + 2
+   uint64 in host memory.  Synchronises.  PIC_EINVAL for nbins outside 1..PIC_HIST_MAX_BINS,
+   edges not increasing, a bad species or NULL pointers. */
+int32_t pic_energy_histogram(pic_box* box, int32_t species, const double* edges, int32_t nbins,
+                             uint64_t* counts_out);
 
 /* Measurement utility, not part of the method: a plain streaming device-to-device copy of
    nbytes (a multiple of 16; both pointers 16-byte aligned device memory owned by the caller)

@@ -348,3 +348,34 @@ def energies(box: Box, E, B, J, species):
     out = np.zeros(11)
     lib().ora_energies(C.byref(box), C.byref(f), arr, len(species), _p(out))
     return out
+
+
+# ---- particle diagnostics of the leaky-box application (Sec. 4.2): the energy distribution
+# and the kinetic pressure behind the plasma beta.  Plain numpy in FP64.
+
+def kinetic_energy(ux, uy, uz):
+    """gamma - 1 per particle (units of m c^2) from FP32 or FP64 momenta, in FP64:
+    u.u / (1 + sqrt(1 + u.u)), which equals sqrt(1 + u.u) - 1 without its cancellation."""
+    x, y, z = (np.asarray(v, np.float64) for v in (ux, uy, uz))
+    uu = x * x + y * y + z * z
+    return uu / (np.sqrt(1.0 + uu) + 1.0)
+
+
+def energy_histogram(ux, uy, uz, edges):
+    """Counts over nbins + 2 slots: slot = number of edges <= gamma - 1 (0: below the first
+    edge, 1 + b: in [edges[b], edges[b+1]), nbins + 1: at or above the last edge); a
+    non-finite energy goes to the last slot."""
+    edges = np.asarray(edges, np.float64)
+    nb = len(edges) - 1
+    k = kinetic_energy(ux, uy, uz)
+    slot = np.searchsorted(edges, k, side="right")
+    slot[np.isnan(k)] = nb + 1
+    return np.bincount(slot, minlength=nb + 2).astype(np.int64)
+
+
+def kinetic_stress(ux, uy, uz, m=1.0):
+    """Diagonal of the kinetic stress, m * sum u_c^2 / gamma for c = x, y, z (FP64).  For an
+    ideal gas the pressure is its trace over 3 per unit volume: n k T."""
+    x, y, z = (np.asarray(v, np.float64) for v in (ux, uy, uz))
+    g = np.sqrt(1.0 + x * x + y * y + z * z)
+    return np.array([m * (x * x / g).sum(), m * (y * y / g).sum(), m * (z * z / g).sum()])

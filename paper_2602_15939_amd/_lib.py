@@ -47,6 +47,7 @@ class pic_box_info(C.Structure):
         ("field_energy_B", C.c_double * 3), ("kinetic_energy", C.c_double),
         ("momentum", C.c_double * 3),
         ("n_sort_migrations", C.c_int64), ("n_sort_fallbacks", C.c_int64), ("maxwell_sweeps", C.c_int32),
+        ("pressure", C.c_double * 3),
     ]
 
 
@@ -83,6 +84,7 @@ def lib():
             "pic_escape_compact": ([boxes, i32, u32], i32),
             "pic_step": ([boxes, i32, u32], i32),
             "pic_box_get": ([vp, C.POINTER(pic_box_info)], i32),
+            "pic_energy_histogram": ([vp, i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_uint64)], i32),
             "pic_autotune": ([vp, u32, i32, C.POINTER(i32), C.POINTER(C.c_float), i32,
                               C.POINTER(i32)], i32),
             "pic_tile_candidates": ([i32, u32, C.POINTER(i32), i32], i32),
@@ -191,3 +193,15 @@ def pic_box_get(h) -> pic_box_info:
     info = pic_box_info()
     check(lib().pic_box_get(h, C.byref(info)), "pic_box_get")
     return info
+
+
+HIST_MAX_BINS = 4096
+
+
+def pic_energy_histogram(h, species, edges):
+    """edges: nbins + 1 increasing floats; returns nbins + 2 counts (below, bins, at/above)."""
+    nb = len(edges) - 1
+    e = (C.c_double * (nb + 1))(*[float(v) for v in edges])
+    out = (C.c_uint64 * (nb + 2))()
+    check(lib().pic_energy_histogram(h, species, e, nb, out), "pic_energy_histogram")
+    return list(out)

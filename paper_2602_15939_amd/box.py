@@ -170,6 +170,11 @@ class Box:
     def info(self) -> L.pic_box_info:
         return L.pic_box_get(self.h)
 
+    def energy_histogram(self, species, edges):
+        """Counts of gamma - 1 over the edges: [below, bin 0 .. bin nbins-1, at/above]."""
+        self._wait_for_torch()
+        return L.pic_energy_histogram(self.h, species, edges)
+
 
 def step_many(boxes, batched=True, graph=False):
     """One whole step of several boxes sharing a stream: batched (one launch per kernel for all

@@ -76,6 +76,8 @@ struct pic_box {
     int last_sweeps = 0;       // sweeps of the last Maxwell step (-1: the device record has it)
     double* red_part = nullptr;
     double* red_out = nullptr;
+    double* hist_edges = nullptr;               // energy histogram: edges ...
+    unsigned long long* hist_counts = nullptr;  // ... and counts
     int64_t step = 0;
     int64_t n_migrations = 0;
     // staging of the descriptor tables of batched steps led by this box (two, alternating)
@@ -1234,6 +1236,8 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     if (!r && d->frame == PIC_FRAME_SHEAR) r = dalloc(b, b->conv, kKsbConvWords);
     if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
     if (!r) r = dalloc(b, b->red_out, 16);
+    if (!r) r = dalloc(b, b->hist_edges, kHistMaxBins + 1);
+    if (!r) r = dalloc(b, b->hist_counts, kHistMaxBins + 2);
     if (!r && d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
         r = dalloc(b, b->mj, (size_t)kMjBins + kMjTail);
     if (b->alloc_pass == 1) return r;
@@ -1557,6 +1561,26 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
     return r;
 }
 
+int32_t pic_energy_histogram(pic_box* b, int32_t s, const double* edges, int32_t nbins, uint64_t* counts)
+{
+    if (!b || s < 0 || s >= b->nsp || !edges || !counts || nbins < 1 || nbins > kHistMaxBins)
+        return PIC_EINVAL;
+    for (int i = 0; i <= nbins; i++)
+        if (!std::isfinite(edges[i]) || (i > 0 && !(edges[i] > edges[i - 1]))) return PIC_EINVAL;
+    static_assert(PIC_HIST_MAX_BINS == kHistMaxBins, "histogram size");
+    hipStream_t st = b->st;
+    const Species& S = b->sp[s];
+    const int k = S.cur;
+    if (hipMemcpyAsync(b->hist_edges, edges, sizeof(double) * (nbins + 1), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        energy_histogram(S.cell[k], S.u[k][0], S.u[k][1], S.u[k][2], S.n_live, b->hist_edges, nbins,
+                         b->hist_counts, kRedBlocks, st) != hipSuccess ||
+        hipMemcpyAsync(counts, b->hist_counts, sizeof(uint64_t) * (nbins + 2), hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+        return PIC_EDEVICE;
+    return hip_fail(hipStreamSynchronize(st));
+}
+
 int32_t pic_box_get(pic_box* b, pic_box_info* info)
 {
     if (!b || !info) return PIC_EINVAL;
@@ -1575,10 +1599,10 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
     for (int s = 0; s < b->nsp; s++) {
         Species& S = b->sp[s];
         const int k = S.cur;
-        if (particle_sums(S.u[k][0], S.u[k][1], S.u[k][2], S.n_live, b->red_part, kRedBlocks,
+        if (particle_sums(S.cell[k], S.u[k][0], S.u[k][1], S.u[k][2], S.n_live, b->red_part, kRedBlocks,
                           b->red_out, st) != hipSuccess)
             return PIC_EDEVICE;
-        double ps[4];
+        double ps[kPartSums];
         int32_t n = 0;
         if (hipMemcpyAsync(ps, b->red_out, sizeof(ps), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(&n, S.n_live, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1587,6 +1611,7 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
         const double m = S.qm != 0 ? std::fabs(S.q / S.qm) : 0.0;
         info->kinetic_energy += m * ps[0];
         for (int c = 0; c < 3; c++) info->momentum[c] += m * ps[1 + c];
+        for (int c = 0; c < 3; c++) info->pressure[c] += m * ps[4 + c];
         info->n_particles[s] = n;
     }
     uint32_t err = 0;

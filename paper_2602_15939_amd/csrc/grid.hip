@@ -621,32 +621,76 @@ __global__ __launch_bounds__(kBlock) void field_energy_kernel(GridDev G, Comp6 A
 }
 
 // FP64 block partial sums of (gamma-1), u_x, u_y, u_z over the live particles
-__global__ __launch_bounds__(kBlock) void particle_sums_kernel(const float* ux, const float* uy,
-                                                               const float* uz,
+// sums over the particles that have not escaped (an escape marks the cell -1 until the next
+// sort drops the particle)
+__global__ __launch_bounds__(kBlock) void particle_sums_kernel(const int32_t* cell, const float* ux,
+                                                               const float* uy, const float* uz,
                                                                const int32_t* n_live,
                                                                double* part)
 {
-    __shared__ double sh[4][kBlock];
-    double a[4] = {0, 0, 0, 0};
+    __shared__ double sh[kPartSums][kBlock];
+    double a[kPartSums] = {};
     const int n = *n_live;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
+        if (cell[i] < 0) continue;
         const double x = ux[i], y = uy[i], z = uz[i];
         const double uu = x * x + y * y + z * z;
-        a[0] += uu / (sqrt(1.0 + uu) + 1.0);  // gamma - 1 without cancellation
+        const double g = sqrt(1.0 + uu);
+        a[0] += uu / (g + 1.0);  // gamma - 1 without cancellation
         a[1] += x;
         a[2] += y;
         a[3] += z;
+        a[4] += x * x / g;  // kinetic stress diagonal u_c^2 / gamma
+        a[5] += y * y / g;
+        a[6] += z * z / g;
     }
-    for (int k = 0; k < 4; k++) sh[k][threadIdx.x] = a[k];
+    for (int k = 0; k < kPartSums; k++) sh[k][threadIdx.x] = a[k];
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
-            for (int k = 0; k < 4; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+            for (int k = 0; k < kPartSums; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 4; k++) part[k * gridDim.x + blockIdx.x] = sh[k][0];
+        for (int k = 0; k < kPartSums; k++) part[k * gridDim.x + blockIdx.x] = sh[k][0];
+}
+
+// Energy distribution (Sec. 4.2) of the particles that have not escaped: slot = number of
+// edges <= gamma - 1 (0: below the first edge, nbins + 1: at or above the last; non-finite
+// energies go to the last slot).  Edges and the workgroup's counts sit in LDS; each workgroup
+// adds its non-zero counts once.
+__global__ __launch_bounds__(kBlock) void energy_hist_kernel(const int32_t* cell, const float* ux,
+                                                             const float* uy, const float* uz,
+                                                             const int32_t* n_live,
+                                                             const double* edges, int nbins,
+                                                             unsigned long long* counts)
+{
+    __shared__ double e[kHistMaxBins + 1];
+    __shared__ uint32_t h[kHistMaxBins + 2];
+    for (int b = threadIdx.x; b < nbins + 2; b += kBlock) h[b] = 0u;
+    for (int b = threadIdx.x; b <= nbins; b += kBlock) e[b] = edges[b];
+    __syncthreads();
+    const int n = *n_live;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        if (cell[i] < 0) continue;
+        const double x = ux[i], y = uy[i], z = uz[i];
+        const double uu = x * x + y * y + z * z;  // FP32 inputs: the products are exact
+        const double k = uu / (sqrt(1.0 + uu) + 1.0);
+        int lo = 0, hi = nbins + 1;  // edges[0..lo) <= k, edges[hi..] > k
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (e[mid] <= k)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        atomicAdd(&h[k == k ? lo : nbins + 1], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins + 2; b += kBlock)
+        if (h[b]) atomicAdd(&counts[b], (unsigned long long)h[b]);
 }
 
 // fixed-order final sum of nrow rows of ncol partials (one thread per row)
@@ -799,11 +843,20 @@ hipError_t field_energy(const GridDev& G, float* const* comps, int ncomp, double
     sum_rows_kernel<<<1, 64, 0, st>>>(part, ncomp, nblk, out);
     return hipGetLastError();
 }
-hipError_t particle_sums(const float* ux, const float* uy, const float* uz, const int32_t* n_live,
-                         double* part, int nblk, double* out, hipStream_t st)
+hipError_t particle_sums(const int32_t* cell, const float* ux, const float* uy, const float* uz,
+                         const int32_t* n_live, double* part, int nblk, double* out, hipStream_t st)
 {
-    particle_sums_kernel<<<nblk, kBlock, 0, st>>>(ux, uy, uz, n_live, part);
-    sum_rows_kernel<<<1, 64, 0, st>>>(part, 4, nblk, out);
+    particle_sums_kernel<<<nblk, kBlock, 0, st>>>(cell, ux, uy, uz, n_live, part);
+    sum_rows_kernel<<<1, 64, 0, st>>>(part, kPartSums, nblk, out);
+    return hipGetLastError();
+}
+hipError_t energy_histogram(const int32_t* cell, const float* ux, const float* uy, const float* uz,
+                            const int32_t* n_live, const double* edges, int nbins,
+                            unsigned long long* counts, int nblk, hipStream_t st)
+{
+    zero_kernel<<<nblocks(2 * (nbins + 2)), kBlock, 0, st>>>(
+        ZeroArgs{reinterpret_cast<uint32_t*>(counts), (int64_t)2 * (nbins + 2)});
+    energy_hist_kernel<<<nblk, kBlock, 0, st>>>(cell, ux, uy, uz, n_live, edges, nbins, counts);
     return hipGetLastError();
 }
 

@@ -449,8 +449,13 @@ hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_
                          hipStream_t st);
 hipError_t field_energy(const GridDev& G, float* const* comps, int ncomp, double* part, int nblk,
                         double* out, hipStream_t st);
-hipError_t particle_sums(const float* ux, const float* uy, const float* uz, const int32_t* n_live,
-                         double* part, int nblk, double* out, hipStream_t st);
+hipError_t particle_sums(const int32_t* cell, const float* ux, const float* uy, const float* uz,
+                         const int32_t* n_live, double* part, int nblk, double* out, hipStream_t st);
+constexpr int kPartSums = 7;       // particle_sums rows: gamma-1, u (3), u_c^2/gamma (3)
+constexpr int kHistMaxBins = 4096;  // energy_histogram
+hipError_t energy_histogram(const int32_t* cell, const float* ux, const float* uy, const float* uz,
+                            const int32_t* n_live, const double* edges, int nbins,
+                            unsigned long long* counts, int nblk, hipStream_t st);
 
 hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n, const int nn[3],
                                   CellCode cc, uint32_t* err, hipStream_t st);

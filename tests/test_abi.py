@@ -109,6 +109,9 @@ def test_invalid_descriptors_rejected_on_the_host(lib, bad):
 
 def test_null_arguments(lib):
     out = C.c_void_p()
+    edges = (C.c_double * 3)(0.0, 1.0, 2.0)
+    counts = (C.c_uint64 * 4)()
+    assert lib.pic_energy_histogram(None, 0, edges, 2, counts) == L.PIC_EINVAL
     assert lib.pic_box_create(None, C.byref(out)) == L.PIC_EINVAL
     assert lib.pic_box_create(C.byref(_desc()), None) == L.PIC_EINVAL
     assert lib.pic_box_destroy(None) == L.PIC_OK

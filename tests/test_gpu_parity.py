@@ -173,12 +173,18 @@ def test_probabilistic_escape_masks_bit_exact():
         c.close()
 
 
-def test_displacement_escape_and_reinjection():
-    dims = (32, 32)
-    zero = (np.zeros((3, 1, 32, 32), np.float32), np.zeros((3, 1, 32, 32), np.float32))
-    parts = frozen_parts(4000, 1.3, 1.05, 60, dims)
-    c = Case(2, dims, "leaky", parts=parts, fields=zero, q=0.0,
-             leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=1.5, theta_inj=0.3)
+@pytest.mark.parametrize("dim,use_3vec", [(2, 0), (3, 0), (3, 1)])
+def test_displacement_escape_and_reinjection(dim, use_3vec):
+    """Sec. 4.1: escape when the in-plane displacement (or, with use_3vec, the 3-vector
+    displacement) reaches l_esc; the particle keeps its position and gets a Maxwell-Juttner
+    momentum from its Philox words."""
+    dims = (32, 32) if dim == 2 else (12, 12, 12)
+    shape = (3, 1, 32, 32) if dim == 2 else (3, 12, 12, 12)
+    zero = (np.zeros(shape, np.float32), np.zeros(shape, np.float32))
+    parts = frozen_parts(4000, 1.3, 1.05, 60 + dim + use_3vec, dims)
+    c = Case(dim, dims, "leaky", parts=parts, fields=zero, q=0.0,
+             leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=1.5, theta_inj=0.3, use_3vec=use_3vec)
+    ncomp = 3 if use_3vec else 2
     try:
         nesc = 0
         for step in range(10):
@@ -191,7 +197,7 @@ def test_displacement_escape_and_reinjection():
                 dr_o = o.dr[:, st["sel"]]
                 # escape decisions are FP32 on the GPU and FP64 in the oracle: only a particle
                 # within rounding of l_esc may differ, and none should here
-                assert np.abs(g["dr"][:2] - dr_o[:2]).max() < 1e-5
+                assert np.abs(g["dr"][:ncomp] - dr_o[:ncomp]).max() < 1e-5
                 assert st["err_u"] < 1e-5, (step, s, st["err_u"])
                 nesc += int((dr_o[0] == 0).sum())
         assert nesc > 100

@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 COPY_CAL_BYTES = 1 << 30  # plain device copy used to calibrate the FETCH/WRITE counters
+DR_COMPONENTS = 2  # displacement components the fused kernel reads and writes (in-plane test)
 GPD_SOURCES = ("paper_2602_15939_amd/csrc/gpd.hip", "paper_2602_15939_amd/csrc/pic_internal.h")
 
 
@@ -74,6 +75,8 @@ def algorithmic_bytes(w, nparticles):
     (24 B/cell)."""
     ncell = math.prod(w["n"])
     state = 4 + 4 * w["dim"] + 12 + (4 if w["kind"] == "leaky" else 0)
+    if w.get("escape") == "displacement":
+        state += 4 * DR_COMPONENTS  # the tracked displacement of the escape test (Sec. 4.1)
     return nparticles * (2 * state + 4) + ncell * (24 + 24)
 
 
@@ -89,6 +92,9 @@ def frame_params(w):
                  maxwell_iters=w["maxwell_iters"])
     elif w["kind"] == "expand":
         p.update(adot_over_wp=round(w["adot"] / wp, 9), dB_over_B0=w["dB"], spectrum_slope_3d=-5 / 3)
+    elif w.get("escape") == "displacement":
+        p.update(dB_over_B0=w["dB"], l_esc=w["l_esc"], theta_inj=w["theta"],
+                 escape="displacement (Sec. 4.1), Maxwell-Juttner re-draw in place")
     else:
         p.update(dB_over_B0=w["dB"], gamma_thr=w["gamma_thr"], t_esc_over_L=w["t_esc"] / w["n"][0],
                  escape="probabilistic, Philox keyed by id and step")
@@ -221,7 +227,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="shear3d",
-                    choices=["shear3d", "expand3d", "leaky2d", "leaky2d_stress"],
+                    choices=["shear3d", "expand3d", "leaky2d", "leaky2d_stress", "leaky2d_paper",
+                             "leaky2d_paper_stress"],
                     help="shear3d: 256^3 shearing box (the default line); expand3d: 128x128x512 "
                          "expanding box; leaky2d: 2048^2 leaky box")
     ap.add_argument("--n", type=int, default=None, help="shear3d only: cells per axis")

@@ -23,7 +23,8 @@
  *   - particle layout at the boundary (structure of arrays): cell[n] int32 linear cell
  *     index i + n0*(j + n1*k); off[dim][n] float in-cell offsets in [0,1); u[3][n] float
  *     spatial part of the four-velocity (u' in the shearing box, Sec. 2.1); id[n] uint32;
- *     dr[3][n] float leaky-box displacement (Sec. 4.1).
+ *     dr[3][n] float leaky-box displacement (Sec. 4.1; dr[2] is tracked only with
+ *     leaky_use_3vec and reads back as 0 otherwise).
  */
 #ifndef PIC_H
 #define PIC_H
@@ -82,7 +83,8 @@ typedef struct pic_box_desc {
     /* leaky box (Sec. 4.1) */
     int32_t leaky_mode;      /* enum pic_leaky_mode */
     double leaky_l_esc;      /* displacement mode: escape distance */
-    int32_t leaky_use_3vec;  /* displacement mode: test (dx, dy, dz) instead of (dx, dy) */
+    int32_t leaky_use_3vec;  /* displacement mode: test (dx, dy, dz) instead of (dx, dy);
+                                dz is tracked only then */
     double leaky_theta_inj;  /* displacement mode: Maxwell-Juttner temperature of reinjection */
     double leaky_t_esc;      /* probabilistic mode: escape probability dt/t_esc per step ... */
     double leaky_gamma_thr;  /* ... for particles with gamma > gamma_thr */

@@ -1376,9 +1376,12 @@ int32_t pic_get_particles(pic_box* b, int32_t s, int64_t* n_out, int32_t* cell, 
     if (id && b->track_ids && n &&
         hipMemcpyAsync(id, S.id[k], sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return PIC_EDEVICE;
-    for (int c = 0; c < 3 && dr && S.dr[k][0]; c++)
+    // the z displacement is tracked only with the 3-vector escape test: 0 otherwise
+    const int ndr = b->d.leaky_use_3vec ? 3 : 2;
+    for (int c = 0; c < ndr && dr && S.dr[k][0]; c++)
         if (n && hipMemcpyAsync(dr + c * n, S.dr[k][c], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
             return PIC_EDEVICE;
+    if (dr && S.dr[k][0] && ndr == 2 && zero_floats(dr + 2 * n, n, st) != hipSuccess) return PIC_EDEVICE;
     return hip_fail(hipStreamSynchronize(st));
 }
 

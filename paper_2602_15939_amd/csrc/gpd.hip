@@ -617,10 +617,14 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             if (FRAME == kLeaky) {
                 const uint32_t pid = ld_at(S.id_in, src);
                 if (P.leaky_mode == 0) {
+                    // the z displacement is tracked only for the 3-vector test
                     float rx = ld_at(S.dr_in[0], src) + D.x, ry = ld_at(S.dr_in[1], src) + D.y;
-                    float rz = ld_at(S.dr_in[2], src) + D.z;
+                    float rz = 0.f;
                     float m = fmaxf(fabsf(rx), fabsf(ry));
-                    if (P.use_3vec) m = fmaxf(m, fabsf(rz));
+                    if (P.use_3vec) {
+                        rz = ld_at(S.dr_in[2], src) + D.z;
+                        m = fmaxf(m, fabsf(rz));
+                    }
                     if (m >= P.l_esc) {
                         uint32_t w[4] = {pid, P.step_lo, 1u, P.box_id};
                         philox4x32_10(w, P.key0, P.key1);
@@ -649,7 +653,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                     }
                     st_at(S.dr_out[0], so, rx);
                     st_at(S.dr_out[1], so, ry);
-                    st_at(S.dr_out[2], so, rz);
+                    if (P.use_3vec) st_at(S.dr_out[2], so, rz);
                 } else {
                     const double g2m1 = ((double)u.x * (double)u.x + (double)u.y * (double)u.y) +
                                         (double)u.z * (double)u.z;

@@ -12,6 +12,11 @@ method's arithmetic).  Code units c = 1, dx = 1; skin depth 4 cells; |q|/m = 1 p
             rms dB/B0 = 1; probabilistic escape above gamma = 10 with t_esc = 10 L/c
   leaky2d_stress  the same box with every particle on a gamma = 20 shell and t_esc = 100 dt
             (1 % of the particles escape per step: the escape and compaction path under load)
+  leaky2d_paper   the same box with the paper's own escape rule (Sec. 4.1): a particle whose
+            in-plane displacement reaches l_esc = L/2 is re-drawn from the Maxwell-Juttner
+            distribution at theta in place
+  leaky2d_paper_stress  the paper's rule with l_esc = 2 cells, so that the displacement test
+            and the Maxwell-Juttner re-draw run under load (a few % of the particles per step)
 """
 from __future__ import annotations
 
@@ -51,8 +56,22 @@ def leaky2d_stress(n=2048, ppc=32):
     return w
 
 
+def leaky2d_paper(n=2048, ppc=32, l_esc=None):
+    w = leaky2d(n, ppc)
+    w.update(name=f"leaky2d_paper_{n}^2_ppc{ppc}", escape="displacement",
+             l_esc=float(n // 2) if l_esc is None else l_esc)
+    return w
+
+
+def leaky2d_paper_stress(n=2048, ppc=32):
+    w = leaky2d_paper(n, ppc, l_esc=2.0)
+    w.update(name=f"leaky2d_paper_stress_{n}^2_ppc{ppc}")
+    return w
+
+
 WORKLOADS = {"shear3d": shear3d, "expand3d": expand3d, "leaky2d": leaky2d,
-             "leaky2d_stress": leaky2d_stress}
+             "leaky2d_stress": leaky2d_stress, "leaky2d_paper": leaky2d_paper,
+             "leaky2d_paper_stress": leaky2d_paper_stress}
 
 
 def fields(w, seed):
@@ -80,6 +99,9 @@ def make_box(w, seed, device="cuda", track_ids=False):
     elif w["kind"] == "expand":
         box = Box(w["dim"], w["n"], frame=L.FRAME_EXPAND, expand_adot=w["adot"],
                   expand_axis_mask=w["axis_mask"], **kw)
+    elif w.get("escape") == "displacement":
+        box = Box(w["dim"], w["n"], frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_DISPLACEMENT,
+                  leaky_l_esc=w["l_esc"], leaky_theta_inj=w["theta"], **kw)
     else:
         box = Box(w["dim"], w["n"], frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_PROBABILISTIC,
                   leaky_t_esc=w["t_esc"], leaky_gamma_thr=w["gamma_thr"], **kw)

@@ -1,7 +1,8 @@
 """Summarise rocprofv3 databases of bench.py runs into the text records kept under profiles/.
 
-  python -m paper_2602_15939_amd.profile_summary trace <results.db>
-      per-kernel call count and average / total duration (kernel trace)
+  python -m paper_2602_15939_amd.profile_summary trace <results.db> [last_n]
+      per-kernel call count and average / total duration (kernel trace); with last_n, also the
+      mean duration of the fused push kernel over its last last_n dispatches (the timed steps)
   python -m paper_2602_15939_amd.profile_summary traffic <fetch.db> <write.db> <copy_bytes> \
         [skip [record.json workload source_hash]]
       FETCH_SIZE / WRITE_SIZE per dispatch of the fused push kernel (after the first `skip`
@@ -52,6 +53,10 @@ def main(argv):
             print(f"{n[:90]:90s} {c:6d} {a:10.4f} {t:10.2f}")
         d = dispatches(argv[1], "gpd_kernel")
         print("gpd_kernel dispatches (ms, in order):", " ".join(f"{t:.4f}" for _, t in d))
+        if len(argv) > 2 and d:
+            last = [t for _, t in d[-int(argv[2]):]]
+            print(f"gpd_kernel mean over the last {len(last)} dispatches (the timed steps): "
+                  f"{sum(last) / len(last):.4f} ms")
     elif argv[0] == "traffic":
         fetch, write = counter_per_dispatch(argv[1], "FETCH_SIZE"), counter_per_dispatch(argv[2], "WRITE_SIZE")
         copy_bytes = float(argv[3])

@@ -84,6 +84,9 @@ def ppc_class(ppc: int) -> int:
     return next(i for i, (lo, hi, _) in enumerate(PPC_CLASSES) if lo <= ppc <= hi)
 
 
+SETTLE_STEPS = 30
+
+
 def tune_tiles(sizes=SIZES, log=None):
     """Tile shape per (box size, ppc class) from the library's autotuner (pic_autotune, batched
     shapes only) on a proxy box of that size and particle load (a shearing box at theta 0.3);
@@ -94,7 +97,11 @@ def tune_tiles(sizes=SIZES, log=None):
                 continue
             spec = RunSpec(-1, n, ppc, "shear", 0.3, 1.5, 1, 99)
             box = build_box(spec, tile=(0, 0, 0))
-            box.step()  # one step so that the autotuner times a pushed (sorted) plasma
+            # the fused kernel's speed depends on the particles' order inside a tile, which
+            # settles within some tens of steps from the loader's cell-by-cell order: time the
+            # shapes on the settled order that a run spends its steps in
+            for _ in range(SETTLE_STEPS):
+                box.step()
             shape, ms = box.autotune(batched=True, trials=2)
             box.close()
             _TILES[(n, k)] = shape

@@ -427,8 +427,10 @@ PIC_BATCHED_KERNEL(ksb_next, KsbDev, kBlock)
 // consecutive planes of the iterate (tile plus a one-cell halo) sit in LDS.  Halo positions
 // outside the interior are read through the boundary maps of the guard fill (y, z periodic;
 // x shearing-periodic with the fractional shift interpolated along y, the same arithmetic), so
-// the iterates need no guard fill between sweeps.
-constexpr int KX = 32, KY = 8, KZ = 32;
+// the iterates need no guard fill between sweeps.  128 x 4 columns of 64-plane chunks (512
+// threads, 56 KB of LDS, two workgroups per CU) measured fastest at 256^3 among 32..128 x
+// 2..16 x 16..128 (8 % below 32 x 8 x 32).
+constexpr int KX = 128, KY = 4, KZ = 64;
 constexpr int KXH = KX + 2, KYH = KY + 2;
 
 template <bool FIRST>

@@ -429,7 +429,10 @@ PIC_BATCHED_KERNEL(ksb_next, KsbDev, kBlock)
 // x shearing-periodic with the fractional shift interpolated along y, the same arithmetic), so
 // the iterates need no guard fill between sweeps.  128 x 4 columns of 64-plane chunks (512
 // threads, 56 KB of LDS, two workgroups per CU) measured fastest at 256^3 among 32..128 x
-// 2..16 x 16..128 (8 % below 32 x 8 x 32).
+// 2..16 x 16..128 (8 % below 32 x 8 x 32).  The iterate written and C read once per sweep use
+// nontemporal (streaming) stores and loads: a sweep moves far more than the caches hold, and
+// the halo reads of the iterate, which neighbouring workgroups share, keep the normal policy
+// (another 9 %).
 constexpr int KX = 128, KY = 4, KZ = 64;
 constexpr int KXH = KX + 2, KYH = KY + 2;
 
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
         const int64_t i = i0 + (int64_t)G.sz * z;
         if (!FIRST && inside)
 #pragma unroll
-            for (int c = 0; c < 6; c++) Cv[c] = K.C[c][i];
+            for (int c = 0; c < 6; c++) Cv[c] = __builtin_nontemporal_load(&K.C[c][i]);
         __syncthreads();
         auto V = [&](int c, int dx, int dy, int dz) {
             const int slot = dz < 0 ? sm : (dz > 0 ? sp : sc);
@@ -519,16 +522,16 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
                 for (int c = 0; c < 6; c++) {
                     float cv = P[sc][c][c0] + h * L[c];
                     if (c >= EX) cv -= fpdt * K.J[c - EX][i];
-                    K.C[c][i] = cv;
+                    __builtin_nontemporal_store(cv, &K.C[c][i]);
                     const float v = cv + h * L[c];
-                    K.Fo[c][i] = v;
+                    __builtin_nontemporal_store(v, &K.Fo[c][i]);
                     if (K.conv) ksb_track(v, P[sc][c][c0], dm, fm);
                 }
             } else {
 #pragma unroll
                 for (int c = 0; c < 6; c++) {
                     const float v = Cv[c] + h * L[c];
-                    K.Fo[c][i] = v;
+                    __builtin_nontemporal_store(v, &K.Fo[c][i]);
                     if (K.conv) ksb_track(v, P[sc][c][c0], dm, fm);
                 }
             }

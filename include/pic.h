@@ -60,6 +60,9 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_TUNE_BATCHED 1u /* only the tile shapes the batched step supports */
 /* pic_box_desc.flags */
 #define PIC_BOX_TRACK_IDS 1u /* carry particle ids through the sort (always on for LEAKY) */
+#define PIC_BOX_COUNT_SUPERLUMINAL 2u /* shearing box: count pushes whose effective velocity
+                                         exceeds c (pic_box_info.n_superluminal); ~2 % of the
+                                         fused kernel's time, so off unless asked for */
 
 /* sticky device error bits (pic_box_info.errors) */
 #define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell */
@@ -135,6 +138,11 @@ typedef struct pic_box_info {
     double pressure[3];        /* sum m u_c^2 / gamma (c = x,y,z): the diagonal of the kinetic
                                   stress; over the box volume, (sum of the three)/3 is the
                                   pressure n k T of the plasma-beta diagnostic of Sec. 4.2 */
+    int64_t n_superluminal;    /* shearing box with PIC_BOX_COUNT_SUPERLUMINAL (counter, else
+                                  0): particle pushes whose effective
+                                  velocity u'/gamma' + v_s, v_s at the midpoint x of the move,
+                                  exceeded c (eq. OAx; Sec. 2.1 leaves the correction to other
+                                  work: counted, not corrected) */
 } pic_box_info;
 
 /* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard

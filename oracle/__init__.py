@@ -46,7 +46,7 @@ class Box(C.Structure):
         ("seed", C.c_uint64), ("box_id", C.c_uint32),
         ("mj_table", C.POINTER(C.c_double)), ("mj_bins", C.c_int), ("mj_tail", C.c_int),
         ("maxwell_iters", C.c_int), ("maxwell_tol", C.c_double),
-        ("step", C.c_int64), ("last_iters", C.c_int),
+        ("step", C.c_int64), ("last_iters", C.c_int), ("n_superluminal", C.c_int64),
     ]
 
 

@@ -1093,9 +1093,14 @@ static void make_scalars(const ora_box* b, step_scalars* S)
    Sec. 4.1 (leaky box) and standard PIC: gather at x^n -> push -> deposit displacement
    (x' - x^n for the shearing box, the primed displacement for the expanding box; deposited
    when Jt is not NULL) -> shear move and boundaries -> leaky-box displacement and escape. */
-static void particle_update(const ora_box* b, const ora_fields* f, const step_scalars* C,
-                            ora_species* S, int64_t p, double* Jt)
+/* One particle's step; returns 1 when the shearing-box effective velocity of the move,
+   u'/gamma' + v_s (eq. OAx) with v_s = -s Omega0 x at the midpoint x of the move (the velocity
+   the shear move uses), exceeds c = 1: the nonrelativistic velocity transformation allows it
+   (Sec. 2.1), and it is counted, not corrected. */
+static int particle_update(const ora_box* b, const ora_fields* f, const step_scalars* C,
+                           ora_species* S, int64_t p, double* Jt)
 {
+    int superluminal = 0;
     const int nd = b->dim;
     const int nx = b->n[0];
     const double dt = C->dt;
@@ -1126,6 +1131,9 @@ static void particle_update(const ora_box* b, const ora_fields* f, const step_sc
         /* x^{n+1} = x' - s Omega0 (x' + x^n)/2 dt e_y (Sec. 2.2) */
         double xp = X1[0] - 0.5 * nx, xn = X0[0] - 0.5 * nx;
         X1[1] -= C->sO * (xp + xn) / 2.0 * dt;
+        const double vs = -C->sO * (xp + xn) / 2.0;
+        const double vx = u[0] / gam, vy = u[1] / gam + vs, vz = u[2] / gam;
+        superluminal = vx * vx + vy * vy + vz * vz > 1.0;
     }
     if (X1[0] >= nx) {
         X1[0] -= nx;
@@ -1170,6 +1178,7 @@ static void particle_update(const ora_box* b, const ora_fields* f, const step_sc
     S->ux[p] = u[0];
     S->uy[p] = u[1];
     S->uz[p] = u[2];
+    return superluminal;
 }
 
 int ora_particles_only(ora_box* b, const ora_fields* f, ora_species* sp, int nsp)
@@ -1179,7 +1188,7 @@ int ora_particles_only(ora_box* b, const ora_fields* f, ora_species* sp, int nsp
     for (int s = 0; s < nsp; s++)
         for (int64_t p = 0; p < sp[s].n; p++) {
             if (sp[s].alive && !sp[s].alive[p]) continue;
-            particle_update(b, f, &C, &sp[s], p, NULL);
+            b->n_superluminal += particle_update(b, f, &C, &sp[s], p, NULL);
         }
     return 0;
 }
@@ -1198,6 +1207,7 @@ int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
 #endif
     const int64_t ne = jext_cells(b);
     double* Jbuf = (double*)calloc((size_t)nthreads * 3 * ne, sizeof(double));
+    int64_t nsl = 0;
     for (int s = 0; s < nsp; s++) {
         ora_species* S = &sp[s];
 #pragma omp parallel num_threads(nthreads)
@@ -1207,10 +1217,10 @@ int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
             tid = omp_get_thread_num();
 #endif
             double* Jt = Jbuf + (size_t)tid * 3 * ne;
-#pragma omp for schedule(static)
+#pragma omp for schedule(static) reduction(+ : nsl)
             for (int64_t p = 0; p < S->n; p++) {
                 if (S->alive && !S->alive[p]) continue;
-                particle_update(b, f, &C, S, p, Jt);
+                nsl += particle_update(b, f, &C, S, p, Jt);
             }
         }
     }
@@ -1223,6 +1233,7 @@ int ora_step(ora_box* b, ora_fields* f, ora_species* sp, int nsp, int nthreads)
     for (int c = 0; c < 3; c++) memcpy(f->J[c], Jflat + c * ncells(b), sizeof(double) * ncells(b));
     free(Jflat);
     free(Jbuf);
+    b->n_superluminal += nsl;
     ora_maxwell(b, f);
     b->step += 1;
     return 0;

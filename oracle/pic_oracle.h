@@ -60,6 +60,8 @@ typedef struct ora_box {
     double maxwell_tol;
     int64_t step;       /* n of the step about to be taken; t^n = n*dt */
     int last_iters;     /* output: iterations used by the last shearing-box Maxwell solve */
+    int64_t n_superluminal; /* output, accumulated: shearing-box pushes whose effective
+                               velocity u'/gamma' + v_s (v_s at the midpoint x) exceeds c */
 } ora_box;
 
 typedef struct ora_species {

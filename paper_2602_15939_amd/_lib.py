@@ -17,6 +17,7 @@ LEAKY_DISPLACEMENT, LEAKY_PROBABILISTIC = 0, 1
 FUSE_DEPOSIT = 1
 REMAP_FIELDS, REMAP_CURRENT = 1, 2
 BOX_TRACK_IDS = 1
+BOX_COUNT_SUPERLUMINAL = 2
 DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT, DERR_NOCONVERGE = 1, 2, 4, 8, 16, 32
 STEP_BATCHED = 1
 STEP_GRAPH = 2
@@ -47,7 +48,7 @@ class pic_box_info(C.Structure):
         ("field_energy_B", C.c_double * 3), ("kinetic_energy", C.c_double),
         ("momentum", C.c_double * 3),
         ("n_sort_migrations", C.c_int64), ("n_sort_fallbacks", C.c_int64), ("maxwell_sweeps", C.c_int32),
-        ("pressure", C.c_double * 3),
+        ("pressure", C.c_double * 3), ("n_superluminal", C.c_int64),
     ]
 
 

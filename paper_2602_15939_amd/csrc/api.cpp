@@ -306,6 +306,7 @@ StepDev make_step(pic_box* b)
     P.ctr = b->ctr;
     P.nsp = b->nsp;
     P.track_ids = b->track_ids ? 1 : 0;
+    P.count_sl = (b->d.flags & PIC_BOX_COUNT_SUPERLUMINAL) ? 1 : 0;
     for (int s = 0; s < b->nsp; s++) {
         Species& S = b->sp[s];
         SpeciesDev& D = P.sp[s];
@@ -1618,7 +1619,7 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
         info->n_particles[s] = n;
     }
     uint32_t err = 0;
-    unsigned long long ctr[3] = {0, 0, 0};
+    unsigned long long ctr[4] = {0, 0, 0, 0};
     if (hipMemcpy(&err, b->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(ctr, b->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess)
         return PIC_EDEVICE;
@@ -1632,6 +1633,7 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
     info->errors = err;
     info->n_slow = (int64_t)ctr[0];
     info->n_escaped = (int64_t)ctr[1];
+    info->n_superluminal = (int64_t)ctr[3];
     info->step = b->step;
     info->t = time_of(b, b->step);
     info->dys = shear_offset(b, info->t);

@@ -512,6 +512,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
         uint32_t stay = 0;  // particles that stay in this tile (the common direction)
         bool far = false;   // a particle beyond the neighbouring tiles
         uint32_t nesc = 0;  // probabilistic escapes (one counter add per wave, at the end)
+        uint32_t nsl = 0;   // shearing box: superluminal effective velocities (likewise)
         const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
         for (uint32_t slot = beg + tid; slot < end; slot += NT) {
             uint32_t so = slot;
@@ -584,7 +585,14 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             // ---- new position: x' = x^n + D, then (shearing box) the shear move
             // y -= s Omega0 (x' + x^n)/2 dt (Sec. 2.2)
             float dyt = D.y;
-            if (FRAME == kShear) dyt = D.y - P.sO * P.dt * (xr + 0.5f * D.x);
+            if (FRAME == kShear) {
+                const float vs = -P.sO * (xr + 0.5f * D.x);  // v_s at the midpoint x of the move
+                dyt = D.y + P.dt * vs;
+                // the effective velocity u'/gamma' + v_s e_y (eq. OAx) can exceed c for
+                // relativistic particles (Sec. 2.1): counted, not corrected.  With
+                // |u'|^2/gamma'^2 = 1 - 1/gamma'^2, |v|^2 > 1 reads vs (2 u'_y/gamma' + vs) > 1/gamma'^2.
+                if (P.count_sl) nsl += (vs * fmaf(2.f * u.y, ig, vs) > ig * ig) ? 1u : 0u;
+            }
             int dcx, dcy, dcz = 0;
             const float nox = renorm(__fadd_rn(ox, D.x), dcx);
             float noy = renorm(__fadd_rn(oy, dyt), dcy);
@@ -707,6 +715,11 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) nesc += __shfl_xor(nesc, o, 64);
             if ((tid & 63) == 0 && nesc) atomicAdd(&P.ctr[1], (unsigned long long)nesc);
+        }
+        if (FRAME == kShear && P.count_sl) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) nsl += __shfl_xor(nsl, o, 64);
+            if ((tid & 63) == 0 && nsl) atomicAdd(&P.ctr[3], (unsigned long long)nsl);
         }
         if (P.count_mig) {
 #pragma unroll

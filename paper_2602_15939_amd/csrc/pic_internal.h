@@ -178,6 +178,7 @@ struct StepDev {
     unsigned long long* ctr;  // [0] slow-path particles, [1] escapes
     int nsp;
     int track_ids;
+    int count_sl;  // shearing box: count superluminal effective velocities (PIC_BOX_COUNT_SUPERLUMINAL)
     SpeciesDev sp[kMaxSpecies];
 };
 

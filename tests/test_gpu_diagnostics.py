@@ -101,3 +101,46 @@ def test_empty_box_histogram():
         assert list(c.gpu.info().pressure) == [0.0, 0.0, 0.0]
     finally:
         c.close()
+
+
+def test_superluminal_count_closed_form():
+    """E' = B = 0, particles at rest on x = 0.25, 0.75, ..., 63.75 of a 64 x 8 shearing box with
+    s Omega0 = 0.05: they stay at rest, their effective velocity is the flow -s Omega0 x, and the
+    24 positions on each side beyond |x| = 20 (both species) count in every step."""
+    n = (64, 8)
+    xs = np.arange(0.25, 64.0, 0.5)
+    k = len(xs)
+    cell = (np.floor(xs).astype(np.int32) + 64 * 3)
+    off = np.stack([xs - np.floor(xs), np.full(k, 0.5)]).astype(np.float32)
+    u = np.zeros((3, k), np.float32)
+    part = dict(cell=torch.from_numpy(cell), off=torch.from_numpy(off), u=torch.from_numpy(u))
+    zero = (np.zeros((3, 1, n[1], n[0]), np.float32),) * 2
+    c = Case(2, n, "shear", parts=[part, dict(part)], fields=zero, q=0.0, shear_s=1.5,
+             omega0=0.05 / 1.5, count_superluminal=True)
+    try:
+        for step in range(3):
+            c.gpu.step()
+            c.oracle_step()
+            assert c.gpu.info().n_superluminal == 2 * 48 * (step + 1)
+            assert c.box.n_superluminal == 2 * 48 * (step + 1)
+    finally:
+        c.close()
+
+
+def test_superluminal_count_against_oracle():
+    """A hot shearing box whose flow reaches 0.9 c at the x faces: the GPU's count (FP32) equals
+    the oracle's (FP64) but for particles within rounding of |v| = c."""
+    c = Case(2, (48, 40), "shear", ppc=6, theta=0.5, seed=91, shear_s=1.5, omega0=0.9 / 24 / 1.5,
+             count_superluminal=True)
+    off = Case(2, (48, 40), "shear", ppc=6, theta=0.5, seed=91, shear_s=1.5, omega0=0.9 / 24 / 1.5)
+    try:
+        for _ in range(3):
+            c.gpu.step()
+            c.oracle_step()
+            off.gpu.step()
+        g, o = c.gpu.info().n_superluminal, c.box.n_superluminal
+        assert o > 100 and abs(g - o) <= 2, (g, o)
+        assert off.gpu.info().n_superluminal == 0  # not counted unless asked for
+    finally:
+        c.close()
+        off.close()

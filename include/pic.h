@@ -63,6 +63,12 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_BOX_COUNT_SUPERLUMINAL 2u /* shearing box: count pushes whose effective velocity
                                          exceeds c (pic_box_info.n_superluminal); ~2 % of the
                                          fused kernel's time, so off unless asked for */
+#define PIC_BOX_ESCAPE 4u    /* apply the leaky box's escape rule (leaky_mode and its
+                                parameters, Sec. 4.1) in the shearing or expanding frame too,
+                                the combination the conclusion of the paper suggests; the
+                                displacement is the one the deposit uses: comoving (x' - x^n,
+                                relative to the shear flow) or primed (expanding box); ids are
+                                carried.  Implied by PIC_FRAME_LEAKY */
 
 /* sticky device error bits (pic_box_info.errors) */
 #define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell */

@@ -47,6 +47,7 @@ class Box(C.Structure):
         ("mj_table", C.POINTER(C.c_double)), ("mj_bins", C.c_int), ("mj_tail", C.c_int),
         ("maxwell_iters", C.c_int), ("maxwell_tol", C.c_double),
         ("step", C.c_int64), ("last_iters", C.c_int), ("n_superluminal", C.c_int64),
+        ("escape", C.c_int),
     ]
 
 
@@ -98,7 +99,7 @@ def _p(a, ctype=C.c_double):
 def make_box(dim, n, dt=0.45, frame=PLAIN, shear_s=0.0, omega0=0.0, adot=0.0, axis_mask=0,
              expand_push=0, leaky_mode=LEAKY_DISPLACEMENT, l_esc=0.0, use_3vec=0, t_esc=0.0,
              gamma_thr=10.0, seed=0, box_id=0, mj_table=None, maxwell_iters=8, maxwell_tol=0.0,
-             step=0) -> Box:
+             step=0, escape=False) -> Box:
     n = list(n) + [1] * (3 - len(n))
     b = Box()
     b.dim = dim
@@ -117,6 +118,7 @@ def make_box(dim, n, dt=0.45, frame=PLAIN, shear_s=0.0, omega0=0.0, adot=0.0, ax
         b.mj_bins, b.mj_tail = MJ_BINS, len(tab) - MJ_BINS
     b.maxwell_iters, b.maxwell_tol = maxwell_iters, maxwell_tol
     b.step = step
+    b.escape = 1 if escape else 0
     return b
 
 

@@ -1079,7 +1079,7 @@ static void make_scalars(const ora_box* b, step_scalars* S)
         S->linv_h[d] = 1.0 / ora_scale(b, d, th);                      /* (L^-1)^{n+1/2} */
     }
     S->esc_thr = 0;
-    if (b->frame == ORA_LEAKY && b->leaky_mode == ORA_LEAKY_PROBABILISTIC) {
+    if ((b->frame == ORA_LEAKY || b->escape) && b->leaky_mode == ORA_LEAKY_PROBABILISTIC) {
         double p = b->t_esc > 0 ? dt / b->t_esc : 0.0;
         double th32 = floor(p * 4294967296.0);
         S->esc_thr = th32 >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th32;
@@ -1145,7 +1145,10 @@ static int particle_update(const ora_box* b, const ora_fields* f, const step_sca
     X1[0] = wrapd(X1[0], nx);
     X1[1] = wrapd(X1[1], b->n[1]);
     if (nd == 3) X1[2] = wrapd(X1[2], b->n[2]);
-    if (b->frame == ORA_LEAKY) {
+    /* the leaky box (Sec. 4.1); in the shearing or expanding frame on request, with the
+       displacement D of the deposit (comoving, or primed): the combination the paper's
+       conclusion suggests, in this reading */
+    if (b->frame == ORA_LEAKY || b->escape) {
         if (b->leaky_mode == ORA_LEAKY_DISPLACEMENT) {
             /* Sec. 4.1: Delta r^n = Delta r^{n-1} + (u/gamma) dt; escape when
                max(|dx|,|dy|) >= l_esc (eq. escape); resample u, reset Delta r.

@@ -62,6 +62,8 @@ typedef struct ora_box {
     int last_iters;     /* output: iterations used by the last shearing-box Maxwell solve */
     int64_t n_superluminal; /* output, accumulated: shearing-box pushes whose effective
                                velocity u'/gamma' + v_s (v_s at the midpoint x) exceeds c */
+    int escape;         /* the leaky box's escape rule in the shearing or expanding frame too
+                           (implied by ORA_LEAKY), on the displacement the deposit uses */
 } ora_box;
 
 typedef struct ora_species {

@@ -17,7 +17,7 @@ class Box:
                  leaky_mode=L.LEAKY_DISPLACEMENT, leaky_l_esc=0.0, leaky_use_3vec=0,
                  leaky_theta_inj=0.0, leaky_t_esc=0.0, leaky_gamma_thr=10.0, seed=0, box_id=0,
                  tile=(0, 0, 0), maxwell_iters=8, maxwell_tol=0.0, track_ids=False,
-                 count_superluminal=False, stream=None):
+                 count_superluminal=False, escape=False, stream=None):
         """species: sequence of (q_over_m, q_macro, capacity)."""
         n = list(n) + [1] * (3 - len(n))
         d = L.pic_box_desc()
@@ -36,7 +36,8 @@ class Box:
         d.seed, d.box_id = int(seed), int(box_id)
         d.maxwell_iters = maxwell_iters
         d.maxwell_tol = maxwell_tol
-        d.flags = (L.BOX_TRACK_IDS if track_ids else 0) | (L.BOX_COUNT_SUPERLUMINAL if count_superluminal else 0)
+        d.flags = ((L.BOX_TRACK_IDS if track_ids else 0) |
+                   (L.BOX_COUNT_SUPERLUMINAL if count_superluminal else 0) | (L.BOX_ESCAPE if escape else 0))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

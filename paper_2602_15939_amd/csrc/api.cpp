@@ -117,6 +117,12 @@ constexpr int kRowAlign = 32;  // floats per 128-byte line
 
 int32_t hip_fail(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EDEVICE; }
 
+// the leaky box's escape rule applies: always in the leaky frame, on request in the others
+bool escapes(const pic_box_desc* d)
+{
+    return d->frame == PIC_FRAME_LEAKY || (d->flags & PIC_BOX_ESCAPE) != 0;
+}
+
 template <class T>
 int32_t dalloc(pic_box* b, T*& p, size_t count)
 {
@@ -280,6 +286,7 @@ StepDev make_step(pic_box* b)
     }
     P.leaky_mode = b->d.leaky_mode;
     P.use_3vec = b->d.leaky_use_3vec;
+    P.escape = escapes(&b->d) ? 1 : 0;
     P.l_esc = (float)b->d.leaky_l_esc;
     {
         const double p = b->d.leaky_t_esc > 0 ? dt / b->d.leaky_t_esc : 0.0;
@@ -1130,7 +1137,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     if (d->maxwell_iters < 0 || d->maxwell_iters > kKsbMaxSweeps || !(d->maxwell_tol >= 0.0) ||
         !(d->maxwell_tol < 1.0))
         return PIC_EINVAL;
-    if (d->frame == PIC_FRAME_LEAKY) {
+    if (escapes(d)) {
         if (d->leaky_mode == PIC_LEAKY_DISPLACEMENT && !(d->leaky_l_esc > 0 && d->leaky_theta_inj > 0))
             return PIC_EINVAL;
         if (d->leaky_mode == PIC_LEAKY_PROBABILISTIC && !(d->leaky_t_esc > 0)) return PIC_EINVAL;
@@ -1178,7 +1185,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     b->comp_elems = (int64_t)G.sy * NYg * NZg;
     b->origin = (int64_t)kRowAlign + (int64_t)G.sy * G.g[1] + (int64_t)G.sz * G.g[2];
     b->nsp = d->n_species;
-    b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || d->frame == PIC_FRAME_LEAKY;
+    b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || escapes(d);
 
     int32_t r = PIC_OK;
     auto grid_alloc = [&](float*& p) -> int32_t {
@@ -1209,7 +1216,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
             for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.off[k][c], c < b->dim ? cap : 1);
             for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.u[k][c], cap);
             if (!r && b->track_ids) r = dalloc(b, S.id[k], cap);
-            if (d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
+            if (escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
                 for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.dr[k][c], cap);
         }
         for (int k = 0; k < 2 && !r; k++) {
@@ -1239,7 +1246,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     if (!r) r = dalloc(b, b->red_out, 16);
     if (!r) r = dalloc(b, b->hist_edges, kHistMaxBins + 1);
     if (!r) r = dalloc(b, b->hist_counts, kHistMaxBins + 2);
-    if (!r && d->frame == PIC_FRAME_LEAKY && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
+    if (!r && escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
         r = dalloc(b, b->mj, (size_t)kMjBins + kMjTail);
     if (b->alloc_pass == 1) return r;
     if (!r && hipMemsetAsync(b->err, 0, 4 * sizeof(uint32_t), b->st) != hipSuccess) r = PIC_EDEVICE;

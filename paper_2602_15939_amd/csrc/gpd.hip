@@ -621,8 +621,9 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             }
             int32_t ncell = P.cc.encode(ncx, ncy, ncz);
 
-            // ---- leaky box (Sec. 4.1)
-            if (FRAME == kLeaky) {
+            // ---- leaky box (Sec. 4.1); in the shearing and expanding frames on request, with the
+            // displacement D of the deposit: comoving (relative to the shear flow), or primed
+            if (FRAME == kLeaky || (FRAME != kPlain && P.escape)) {
                 const uint32_t pid = ld_at(S.id_in, src);
                 if (P.leaky_mode == 0) {
                     // the z displacement is tracked only for the 3-vector test
@@ -711,7 +712,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             st_at(S.u_out[2], so, u.z);
             if (P.track_ids) st_at(S.id_out, so, ld_at(S.id_in, src));
         }
-        if (FRAME == kLeaky) {
+        if (FRAME == kLeaky || (FRAME != kPlain && P.escape)) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) nesc += __shfl_xor(nesc, o, 64);
             if ((tid & 63) == 0 && nesc) atomicAdd(&P.ctr[1], (unsigned long long)nesc);

@@ -158,6 +158,8 @@ struct StepDev {
     float linv[3];        // 1/l_i(t^{n+1/2})
     // leaky box
     int leaky_mode, use_3vec;
+    int escape;  // the leaky box's escape rule applies (always in the leaky frame; on request
+                 // in the shearing and expanding frames)
     float l_esc;
     uint32_t esc_thr;     // floor((dt/t_esc) 2^32)
     double g2thr;         // gamma_thr^2 - 1

@@ -53,7 +53,7 @@ class Case:
                  leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=3.0, t_esc=9.0, gamma_thr=10.0,
                  theta_inj=0.3, maxwell_iters=4, maxwell_tol=0.0, q=None, parts=None, track_ids=True,
                  use_3vec=0, box_seed=0x5EED1234ABCDEF01, box_id=7, stream=None,
-                 count_superluminal=False):
+                 count_superluminal=False, escape=False):
         self.dim = dim
         self.n = tuple(list(n) + [1] * (3 - len(n)))
         self.frame = FRAMES[frame]
@@ -69,7 +69,7 @@ class Case:
         self.E32, self.B32 = fields
         cap = max(len(p["cell"]) for p in self.parts) + 16
         mj = None
-        if self.frame == L.FRAME_LEAKY and leaky_mode == L.LEAKY_DISPLACEMENT:
+        if (self.frame == L.FRAME_LEAKY or escape) and leaky_mode == L.LEAKY_DISPLACEMENT:
             mj = oracle.mj_table(theta_inj)
         common = dict(dt=dt)
         self.gpu = None
@@ -82,7 +82,7 @@ class Case:
                        seed=box_seed, box_id=box_id, tile=tile, maxwell_iters=maxwell_iters,
                        maxwell_tol=maxwell_tol,
                        track_ids=track_ids, stream=stream,
-                       count_superluminal=count_superluminal)
+                       count_superluminal=count_superluminal, escape=escape)
         self.gpu.set_fields(torch.from_numpy(self.E32), torch.from_numpy(self.B32))
         for s, p in enumerate(self.parts):
             ids = np.arange(len(p["cell"])) + s * 10_000_000
@@ -94,7 +94,7 @@ class Case:
                                    leaky_mode=leaky_mode, l_esc=l_esc, use_3vec=use_3vec,
                                    t_esc=t_esc, gamma_thr=gamma_thr, seed=box_seed, box_id=box_id,
                                    mj_table=mj, maxwell_iters=maxwell_iters,
-                                   maxwell_tol=maxwell_tol, **common)
+                                   maxwell_tol=maxwell_tol, escape=escape, **common)
         self.E = self.E32.astype(np.float64)
         self.B = self.B32.astype(np.float64)
         self.J = np.zeros_like(self.E)

@@ -1,0 +1,82 @@
+"""The leaky box's escape rule in the shearing and expanding frames (PIC_BOX_ESCAPE), GPU
+against the oracle: displacement escape with the Maxwell-Juttner re-draw (2D, and 3D with the
+3-vector test) and probabilistic escape with compaction (masks and survivors bit-exact for a
+population far above gamma_thr; the escape counter equals the oracle's escapes)."""
+import numpy as np
+import pytest
+import torch
+
+from _cases import Case, compare_particles
+from paper_2602_15939_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+
+def frozen(n, gammas, seed, dims):
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in gammas:
+        v = rng.normal(size=(n, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        cell = rng.integers(0, int(np.prod(dims)), n).astype(np.int32)
+        off = rng.uniform(0, 1, (len(dims), n)).astype(np.float32)
+        out.append(dict(cell=torch.from_numpy(cell), off=torch.from_numpy(off),
+                        u=torch.from_numpy((np.sqrt(g * g - 1) * v.T).astype(np.float32))))
+    return out
+
+
+@pytest.mark.parametrize("frame,dim,use_3vec", [("shear", 2, 0), ("expand", 2, 0), ("shear", 3, 1),
+                                                ("expand", 3, 0)])
+def test_displacement_escape_in_frame(frame, dim, use_3vec):
+    dims = (32, 32) if dim == 2 else (12, 12, 12)
+    shape = (3, 1, 32, 32) if dim == 2 else (3, 12, 12, 12)
+    zero = (np.zeros(shape, np.float32), np.zeros(shape, np.float32))
+    kw = dict(shear_s=1.5, omega0=0.01) if frame == "shear" else dict(adot=2e-3)
+    c = Case(dim, dims, frame, parts=frozen(4000, (1.3, 1.05), 70 + dim, dims), fields=zero, q=0.0,
+             leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=1.5, theta_inj=0.3, use_3vec=use_3vec,
+             escape=True, **kw)
+    ncomp = 3 if use_3vec else 2
+    try:
+        nesc = 0
+        for step in range(10):
+            c.gpu.step()
+            c.oracle_step()
+            for s in range(2):
+                g = c.gpu_species(s)
+                st = compare_particles(c, s, g, tol_u=1e-5)
+                dr_o = c.sp[s].dr[:, st["sel"]]
+                # escape decisions: FP32 on the GPU, FP64 in the oracle; none lies within
+                # rounding of l_esc here
+                assert np.abs(g["dr"][:ncomp] - dr_o[:ncomp]).max() < 1e-5, (step, s)
+                assert st["err_u"] < 1e-5 and st["err_x"] < 1e-5, (step, s, st["err_u"], st["err_x"])
+                nesc += int((dr_o[0] == 0).sum())
+        assert nesc > 100
+        assert c.gpu.info().errors & ~L.DERR_ORDER == 0
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("frame", ["shear", "expand"])
+def test_probabilistic_escape_in_frame(frame):
+    dims = (32, 32)
+    dt = 0.45
+    zero = (np.zeros((3, 1, 32, 32), np.float32),) * 2
+    kw = dict(shear_s=1.5, omega0=0.01) if frame == "shear" else dict(adot=2e-3)
+    c = Case(2, dims, frame, parts=frozen(6000, (30.0, 25.0), 91, dims), fields=zero, q=0.0,
+             leaky_mode=L.LEAKY_PROBABILISTIC, t_esc=dt / 0.1, gamma_thr=10.0, escape=True, **kw)
+    try:
+        for step in range(6):
+            c.gpu.step()
+            c.oracle_step()
+            for s in range(2):
+                g = c.gpu_species(s)
+                live = g["cell"] >= 0
+                o = c.sp[s]
+                # survivors: the oracle's alive set equals the GPU's non-escaped ids
+                assert sorted(g["id"][live].tolist()) == sorted(o.id[o.alive != 0].tolist()), (step, s)
+        info = c.gpu.info()
+        assert info.n_escaped == sum(int((c.sp[s].alive == 0).sum()) for s in range(2))
+        assert info.n_escaped > 1000
+        assert info.errors & ~L.DERR_ORDER == 0
+    finally:
+        c.close()

@@ -5,7 +5,7 @@ compute one by one:
   * the push of every particle whose cell lies in a sub-block of the grid plus a random sample of
     4096 particles per species from the whole box (the shearing-periodic and periodic wraps
     included): momenta within 2e-6 relative (|du| / max(|u|, 0.01)), positions within 2e-6 cells,
-    escape decisions equal;
+    escape decisions equal, the leaky box's tracked displacement within 2e-6 cells;
   * the deposited current (before the guard fold and the J' transport) inside that sub-block:
     the oracle deposits every particle that can reach it, from x^n to its own deposit endpoint
     (x^n + dt u/gamma; primed coordinates for the expanding box); within 1e-5 of max|J| there.
@@ -31,6 +31,9 @@ def oracle_box(w):
         kw.update(frame=oracle.SHEAR, shear_s=w["shear_s"], omega0=w["omega0"])
     elif w["kind"] == "expand":
         kw.update(frame=oracle.EXPAND, adot=w["adot"], axis_mask=w["axis_mask"])
+    elif w.get("escape") == "displacement":
+        kw.update(frame=oracle.LEAKY, leaky_mode=oracle.LEAKY_DISPLACEMENT, l_esc=w["l_esc"],
+                  mj_table=oracle.mj_table(w["theta"]))
     else:
         kw.update(frame=oracle.LEAKY, leaky_mode=oracle.LEAKY_PROBABILISTIC, t_esc=w["t_esc"],
                   gamma_thr=w["gamma_thr"])
@@ -41,7 +44,7 @@ def to_np(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["shear3d", "expand3d", "leaky2d"])
+@pytest.mark.parametrize("name", ["shear3d", "expand3d", "leaky2d", "leaky2d_paper"])
 def test_full_size_sampled_parity(name):
     w = workloads.WORKLOADS[name]()
     dim, n = w["dim"], tuple(list(w["n"]) + [1] * (3 - w["dim"]))
@@ -85,7 +88,7 @@ def test_full_size_sampled_parity(name):
         slot = inv[idx]
         assert (slot >= 0).all()
         old = {k_: to_np(v[..., idx]) for k_, v in pre[s].items() if k_ in ("cell", "off", "u")}
-        new = {k_: to_np(v[..., slot]) for k_, v in post[s].items() if k_ in ("cell", "off", "u")}
+        new = {k_: to_np(v[..., slot]) for k_, v in post[s].items() if k_ in ("cell", "off", "u", "dr")}
         ci, cj, ck = cell_coords(old["cell"], n)
         x0 = ci + old["off"][0].astype(np.float64)
         y0 = cj + old["off"][1].astype(np.float64)
@@ -110,6 +113,9 @@ def test_full_size_sampled_parity(name):
             pos_o.append(sp.z[live_g])
         ex = max(float(np.abs(wrap_diff(g, o, n[d])).max()) for d, (g, o) in enumerate(zip(pos_g, pos_o)))
         assert ex < 2e-6, (name, s, ex)
+        if w.get("escape") == "displacement":  # the tracked in-plane displacement (Sec. 4.1)
+            ddr = np.abs(new["dr"][:2, live_g] - sp.dr[:2, live_g]).max()
+            assert ddr < 2e-6, (name, s, ddr)
         print(f"[fullsize] {name} species {s}: {len(idx)} particles, max du {du.max():.2e}, "
               f"max dx {ex:.2e}", flush=True)
 

@@ -487,8 +487,12 @@ int32_t fold_box(pic_box* b)
 {
     const double th = time_of(b, b->step) + 0.5 * b->d.dt;
     const int shear = b->d.frame == PIC_FRAME_SHEAR;
-    return hip_fail(fold_current(b->G, b->J, b->Jt, shear, b->d.shear_s * b->d.shear_omega0,
-                                 b->d.dt, shear_offset(b, th), b->st));
+    if (fold_current(b->G, b->J, b->Jt, shear, b->d.shear_s * b->d.shear_omega0, b->d.dt,
+                     shear_offset(b, th), b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (shear)  // the folded current was written into the second array: it becomes the current
+        for (int c = 0; c < 3; c++) std::swap(b->J[c], b->Jt[c]);
+    return PIC_OK;
 }
 
 // finalize record of a tolerance-mode step whose last sweep writes set `last`: the iterate of
@@ -815,7 +819,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
     // ---- a7: current fold (z, y periodic; J' transport and shearing-periodic x, or periodic x)
     {
         std::vector<FoldPArgs> fz, fy;
-        std::vector<AdvArgs> adv;
+        std::vector<ShearFoldArgs> adv;
         std::vector<FoldXArgs> fx;
         std::vector<uint32_t> fzb, fyb, advb, fxb;
         for (int i = 0; i < nb; i++) {
@@ -833,13 +837,14 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
             fyb.push_back(grid_blocks((int64_t)NXg * nly * G.n[2]));
             const double th = time_of(b, b->step) + 0.5 * b->d.dt;
             if (b->d.frame == PIC_FRAME_SHEAR) {
+                // transport + x fold from J into the second array, which then becomes the
+                // current (the later stages of this step are planned with the swapped arrays)
                 const double dh = shear_offset(b, th), fl = std::floor(dh);
                 const Comp3 Tc{{b->Jt[0], b->Jt[1], b->Jt[2]}};
-                adv.push_back(AdvArgs{G, Jc, Tc, (float)(b->d.shear_s * b->d.shear_omega0 * b->d.dt / 2.0),
-                                      0.5f * G.n[0]});
-                advb.push_back(grid_blocks((int64_t)NXg * G.n[1] * G.n[2]));
-                fx.push_back(FoldXArgs{G, Tc, Jc, 1, 1, (int)fl, (float)(dh - fl)});
-                fxb.push_back(grid_blocks((int64_t)G.n[0] * G.n[1] * G.n[2]));
+                adv.push_back(ShearFoldArgs{G, Jc, Tc, (float)(b->d.shear_s * b->d.shear_omega0 * b->d.dt / 2.0),
+                                            0.5f * G.n[0], (int)fl, (float)(dh - fl)});
+                advb.push_back(grid_blocks((int64_t)G.n[0] * G.n[1] * G.n[2]));
+                for (int c = 0; c < 3; c++) std::swap(b->J[c], b->Jt[c]);
             } else {
                 const int nlx = G.n[0] < 2 * G.g[0] ? G.n[0] : 2 * G.g[0];
                 fx.push_back(FoldXArgs{G, Jc, Jc, 0, 0, 0, 0.f});
@@ -848,7 +853,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
         }
         plan.grid(kBatchFoldP, fz, fzb, 3);
         plan.grid(kBatchFoldP, fy, fyb, 3);
-        plan.grid(kBatchAdvect, adv, advb, 3);
+        plan.grid(kBatchShearFold, adv, advb, 3);
         plan.grid(kBatchFoldX, fx, fxb, 3);
     }
 
@@ -1173,6 +1178,8 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
     const int tiles_ws = max_tiles(b->dim, n);  // any supported tiling fits the workspace
     GridDev& G = b->G;
     G.dim = b->dim;
+    G.div0 = FastDiv::make((uint32_t)n[0]);
+    G.div1 = FastDiv::make((uint32_t)n[1]);
     for (int k = 0; k < 3; k++) {
         G.n[k] = n[k];
         G.g[k] = (k < b->dim) ? kGuard : 0;

@@ -14,10 +14,17 @@ __device__ inline int64_t gidx(const GridDev& G, int x, int y, int z)
 {
     return (int64_t)x + (int64_t)G.sy * y + (int64_t)G.sz * z;
 }
+// i mod n in [0, n); one add or subtract for i in [-n, 2n) (the indices here are within a
+// period of the range), the remainder only beyond
 __device__ inline int wrapn(int i, int n)
 {
-    i %= n;
-    return i < 0 ? i + n : i;
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    if ((unsigned)i >= (unsigned)n) {
+        i %= n;
+        if (i < 0) i += n;
+    }
+    return i;
 }
 
 // ------------------------------------------------------------------ guard fill
@@ -132,34 +139,63 @@ __device__ __attribute__((always_inline)) inline void fold_periodic_body(const F
 }
 PIC_BATCHED_KERNEL(fold_periodic, FoldPArgs, kBlock)
 
-// J' transport along y by d = v_{s,y}(x) dt/2, v_{s,y} = -s Omega0 x at each component's x
-// (Sec. 2.2), as J(y - d) by linear interpolation, over the guarded x range; out = in moved.
-__device__ __attribute__((always_inline)) inline void shear_advect_body(const AdvArgs& a, int blk, int, int c)
+// interior coordinates of linear interior index t = x + n0 (y + n1 z) (below 2^31)
+__device__ inline void cell_of(const GridDev& G, int64_t t, int& x, int& y, int& z)
 {
-    const GridDev& G = a.G;
-    const Comp3& Jin = a.in;
-    const Comp3& Jout = a.out;
-    const float sO_hdt = a.sO_hdt, half_nx = a.half_nx;
-    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    const int gx = G.g[0];
-    const int NXg = G.n[0] + 2 * gx;
-    const int64_t tot = (int64_t)NXg * G.n[1] * G.n[2];
-    if (t >= tot) return;
-    const int x = (int)(t % NXg) - gx;
-    const int64_t r = t / NXg;
-    const int y = (int)(r % G.n[1]);
-    const int z = (int)(r / G.n[1]);
-    const float xc = (float)x + (c == 0 ? 0.5f : 0.f) - half_nx;
+    const uint32_t u = (uint32_t)t;
+    const uint32_t r = G.div0.div(u);
+    x = (int)(u - r * (uint32_t)G.n[0]);
+    const uint32_t zz = G.div1.div(r);
+    y = (int)(r - zz * (uint32_t)G.n[1]);
+    z = (int)zz;
+}
+
+// J' at guarded column xg moved along y by v_s(xg) dt/2 (Sec. 2.2), v_s taken at the
+// component's staggered x: first-order upwind, i.e. linear interpolation between rows
+__device__ inline float shear_transport(const GridDev& G, const float* __restrict__ F, int c, int xg,
+                                        int y, int z, float sO_hdt, float half_nx)
+{
+    const float xc = (float)xg + (c == 0 ? 0.5f : 0.f) - half_nx;
     const float d = -sO_hdt * xc;
     const float fl = floorf(d);
     const int m = (int)fl;
     const float w = d - fl;
-    const float* F = Jin.p[c];
-    const float fa = F[gidx(G, x, wrapn(y - m, G.n[1]), z)];
-    const float fb = F[gidx(G, x, wrapn(y - m - 1, G.n[1]), z)];
-    Jout.p[c][gidx(G, x, y, z)] = (1.f - w) * fa + w * fb;
+    const float fa = F[gidx(G, xg, wrapn(y - m, G.n[1]), z)];
+    const float fb = F[gidx(G, xg, wrapn(y - m - 1, G.n[1]), z)];
+    return (1.f - w) * fa + w * fb;
 }
-PIC_BATCHED_KERNEL(shear_advect, AdvArgs, kBlock)
+// The transport and the shearing-periodic x fold in one pass (out-of-place): an interior cell
+// takes its own transported value plus, on the first and last g columns, the transported
+// guard column of the other face at the y shift of the shearing-periodic map (the exact
+// transpose of the field guard fill's interpolation).
+__device__ __attribute__((always_inline)) inline void shear_fold_body(const ShearFoldArgs& a, int blk, int, int c)
+{
+    const GridDev& G = a.G;
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
+    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
+    int x, y, z;
+    cell_of(G, t, x, y, z);
+    const int nx = G.n[0], ny = G.n[1], ga = G.g[0];
+    const float* F = a.in.p[c];
+    float v = shear_transport(G, F, c, x, y, z, a.sO_hdt, a.half_nx);
+    if (x < ga) {  // guard column x + nx, the image of (x, y + dys)
+        v += (1.f - a.dys_w) * shear_transport(G, F, c, x + nx, wrapn(y - a.dys_int, ny), z, a.sO_hdt, a.half_nx) +
+             a.dys_w * shear_transport(G, F, c, x + nx, wrapn(y - a.dys_int - 1, ny), z, a.sO_hdt, a.half_nx);
+    }
+    if (x >= nx - ga) {  // guard column x - nx, the image of (x, y - dys)
+        // shift -dys = js + w with js = -dys_int - 1, w = 1 - dys_w (dys_w > 0), else -dys_int
+        int js = -a.dys_int;
+        float w = 0.f;
+        if (a.dys_w > 0.f) {
+            js = -a.dys_int - 1;
+            w = 1.f - a.dys_w;
+        }
+        v += (1.f - w) * shear_transport(G, F, c, x - nx, wrapn(y - js, ny), z, a.sO_hdt, a.half_nx) +
+             w * shear_transport(G, F, c, x - nx, wrapn(y - js - 1, ny), z, a.sO_hdt, a.half_nx);
+    }
+    a.out.p[c][gidx(G, x, y, z)] = v;
+}
+PIC_BATCHED_KERNEL(shear_fold, ShearFoldArgs, kBlock)
 
 // x fold as a gather into interior cells: out(i) = in(i) plus the x guard columns that map
 // to i (periodic, or shearing-periodic at dys as the transpose of the guard interpolation).
@@ -221,13 +257,6 @@ PIC_BATCHED_KERNEL(fold_x, FoldXArgs, kBlock)
 // Yee curls (c = 1, dx = 1).  E_j and B_j enter multiplied by ge[j], gb[j] (the l_j of the
 // expanding box, 1 otherwise).
 
-__device__ inline void cell_of(const GridDev& G, int64_t t, int& x, int& y, int& z)
-{
-    x = (int)(t % G.n[0]);
-    const int64_t r = t / G.n[0];
-    y = (int)(r % G.n[1]);
-    z = (int)(r / G.n[1]);
-}
 
 // B_i <- fout_i (fin_i B_i - dt/2 curl(g E)_i)
 __device__ __attribute__((always_inline)) inline void yee_b_body(const MaxwellDev& M, int blk, int, int)
@@ -733,7 +762,7 @@ hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int she
 
 // Fold the deposited current.  For the shearing box tmp receives the transported current and
 // the fold writes every interior cell of J.
-hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, int shear,
+hipError_t fold_current(const GridDev& G, float* const* J, float* const* out, int shear,
                         double sO, double dt, double dys_half, hipStream_t st)
 {
     Comp3 Jc{{J[0], J[1], J[2]}};
@@ -752,11 +781,9 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, in
     const int di = (int)fl;
     const float w = (float)(dys_half - fl);
     if (shear) {
-        Comp3 Tc{{tmp[0], tmp[1], tmp[2]}};
-        shear_advect_kernel<<<dim3(nblocks((int64_t)NXg * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
-            AdvArgs{G, Jc, Tc, (float)(sO * dt / 2.0), 0.5f * G.n[0]});
-        fold_x_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
-            FoldXArgs{G, Tc, Jc, 1, 1, di, w});
+        Comp3 Oc{{out[0], out[1], out[2]}};
+        shear_fold_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
+            ShearFoldArgs{G, Jc, Oc, (float)(sO * dt / 2.0), 0.5f * G.n[0], di, w});
     } else {
         const int nl = G.n[0] < 2 * G.g[0] ? G.n[0] : 2 * G.g[0];
         fold_x_kernel<<<dim3(nblocks((int64_t)nl * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
@@ -811,8 +838,8 @@ hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks,
     case kBatchFoldP:
         fold_periodic_batch<<<grid, kBlock, 0, st>>>(static_cast<const FoldPArgs*>(table), m);
         break;
-    case kBatchAdvect:
-        shear_advect_batch<<<grid, kBlock, 0, st>>>(static_cast<const AdvArgs*>(table), m);
+    case kBatchShearFold:
+        shear_fold_batch<<<grid, kBlock, 0, st>>>(static_cast<const ShearFoldArgs*>(table), m);
         break;
     case kBatchFoldX: fold_x_batch<<<grid, kBlock, 0, st>>>(static_cast<const FoldXArgs*>(table), m); break;
     case kBatchYeeB: yee_b_batch<<<grid, kBlock, 0, st>>>(static_cast<const MaxwellDev*>(table), m); break;

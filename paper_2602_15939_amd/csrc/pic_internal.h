@@ -247,11 +247,35 @@ __device__ inline int unit_of(const UnitMap& m, int b)  // the unit owning block
     }
 
 // Geometry of a guarded grid array.
+// Division of 32-bit unsigned integers by an invariant divisor d >= 1 (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", PLDI 1994, Fig. 4.1): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, q = (t1 + ((t - t1) >> 1)) >> (l - 1),
+// t1 = mulhi(m, t), for every t < 2^32 and d >= 2; d = 1 is q = t.
+struct FastDiv {
+    uint32_t m;
+    int l;  // 0 for d = 1
+    static FastDiv make(uint32_t d)
+    {
+        FastDiv f{0u, 0};
+        while ((1ull << f.l) < d) f.l++;
+        if (f.l > 0)
+            f.m = (uint32_t)((((1ull << 32) * ((1ull << f.l) - d)) / d) + 1ull);
+        return f;
+    }
+    __device__ inline uint32_t div(uint32_t t) const
+    {
+        if (l == 0) return t;
+        const uint32_t t1 = __umulhi(m, t);
+        return (t1 + ((t - t1) >> 1)) >> (l - 1);
+    }
+};
+
 struct GridDev {
     int dim;
     int n[3];
     int g[3];    // guard width per axis
     int sy, sz;  // element strides (x stride 1)
+    FastDiv div0, div1;  // division by n[0] and by n[1] (linear interior index -> x, y, z)
 };
 
 // One Yee update: X_i <- fout_i (fin_i X_i +/- dt curl(g Y)_i [- 4 pi dt J_i]).
@@ -282,10 +306,12 @@ struct FoldPArgs {  // periodic current fold along axis 1 (y) or 2 (z)
     Comp3 J;
     int axis;
 };
-struct AdvArgs {  // J' transport along y (shearing box)
+struct ShearFoldArgs {  // J' transport along y and shearing-periodic x fold, in -> out
     GridDev G;
     Comp3 in, out;
     float sO_hdt, half_nx;
+    int dys_int;
+    float dys_w;
 };
 struct FoldXArgs {  // x fold (periodic or shearing-periodic)
     GridDev G;
@@ -426,7 +452,7 @@ hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upp
 
 // batched launches of the grid and sort kernels (tables of per-unit arguments on the device)
 enum GridBatchKind {
-    kBatchZero, kBatchFill, kBatchFoldP, kBatchAdvect, kBatchFoldX, kBatchYeeB, kBatchYeeE,
+    kBatchZero, kBatchFill, kBatchFoldP, kBatchShearFold, kBatchFoldX, kBatchYeeB, kBatchYeeE,
     kBatchKsbFirst, kBatchKsbNext, kBatchKsbFinal
 };
 hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks, int ydim,
@@ -440,7 +466,10 @@ int sort_result_buffer(const Tiles& tl);  // sort buffer holding the sorted pair
 // and z halos at their periodic images themselves
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
                        hipStream_t st, bool x_only = false);
-hipError_t fold_current(const GridDev& G, float* const* J, float* const* tmp, int shear,
+// Fold the current guards (y, z periodic in place).  Shearing box: the J' transport and the
+// shearing-periodic x fold in one pass from J into `out` (the caller then swaps the two arrays);
+// otherwise the periodic x fold in place.
+hipError_t fold_current(const GridDev& G, float* const* J, float* const* out, int shear,
                         double sO, double dt, double dys_half, hipStream_t st);
 hipError_t yee_b(const MaxwellDev& M, hipStream_t st);
 hipError_t yee_e(const MaxwellDev& M, hipStream_t st);

@@ -1184,6 +1184,7 @@ int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
         G.n[k] = n[k];
         G.g[k] = (k < b->dim) ? kGuard : 0;
     }
+    G.divyg = FastDiv::make((uint32_t)(n[1] + 2 * G.g[1]));
     // rows of kRowAlign floats: interior x = 0 starts a 128-byte line in every row (the x
     // guards sit in the padding before and after the interior)
     const int NYg = n[1] + 2 * G.g[1], NZg = n[2] + 2 * G.g[2];

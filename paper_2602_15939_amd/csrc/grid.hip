@@ -38,33 +38,34 @@ __device__ __attribute__((always_inline)) inline void fill_guards_body(const Fil
     const int slab = a.slab, shear = a.shear, dys_int = a.dys_int;
     const float dys_w = a.dys_w;
     float* F = a.A.p[c];
-    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
-    const int NYg = G.n[1] + 2 * gy, NZg = G.n[2] + 2 * gz;
+    // 32-bit index arithmetic: the x and y guard widths are kGuard, the other divisors are
+    // invariant (precomputed multipliers)
+    const uint32_t t = (uint32_t)blk * kBlock + threadIdx.x;
+    constexpr uint32_t g2 = 2 * kGuard;
+    const int gz = G.g[2];
+    const uint32_t NYg = (uint32_t)(G.n[1] + 2 * kGuard), NZg = (uint32_t)(G.n[2] + 2 * gz);
     int x, y, z;
     if (slab == 0) {  // x guard slabs over the whole guarded y, z
-        const int64_t tot = (int64_t)2 * gx * NYg * NZg;
-        if (t >= tot) return;
-        int m = (int)(t % (2 * gx));
-        int64_t r = t / (2 * gx);
-        y = (int)(r % NYg) - gy;
-        z = (int)(r / NYg) - gz;
-        x = m < gx ? m - gx : G.n[0] + (m - gx);
+        if (t >= g2 * NYg * NZg) return;
+        const uint32_t m = t % g2, r = t / g2;
+        const uint32_t q = G.divyg.div(r);
+        y = (int)(r - q * NYg) - kGuard;
+        z = (int)q - gz;
+        x = (int)m < kGuard ? (int)m - kGuard : G.n[0] + ((int)m - kGuard);
     } else if (slab == 1) {  // y guard slabs over interior x, guarded z
-        const int64_t tot = (int64_t)G.n[0] * 2 * gy * NZg;
-        if (t >= tot) return;
-        x = (int)(t % G.n[0]);
-        int64_t r = t / G.n[0];
-        int m = (int)(r % (2 * gy));
-        z = (int)(r / (2 * gy)) - gz;
-        y = m < gy ? m - gy : G.n[1] + (m - gy);
+        if (t >= (uint32_t)G.n[0] * g2 * NZg) return;
+        const uint32_t r = G.div0.div(t);
+        x = (int)(t - r * (uint32_t)G.n[0]);
+        const uint32_t m = r % g2;
+        z = (int)(r / g2) - gz;
+        y = (int)m < kGuard ? (int)m - kGuard : G.n[1] + ((int)m - kGuard);
     } else {  // z guard slabs over interior x, y
-        const int64_t tot = (int64_t)G.n[0] * G.n[1] * 2 * gz;
-        if (t >= tot) return;
-        x = (int)(t % G.n[0]);
-        int64_t r = t / G.n[0];
-        y = (int)(r % G.n[1]);
-        int m = (int)(r / G.n[1]);
+        if (t >= (uint32_t)G.n[0] * (uint32_t)G.n[1] * (uint32_t)(2 * gz)) return;
+        const uint32_t r = G.div0.div(t);
+        x = (int)(t - r * (uint32_t)G.n[0]);
+        const uint32_t q = G.div1.div(r);
+        y = (int)(r - q * (uint32_t)G.n[1]);
+        const int m = (int)q;
         z = m < gz ? m - gz : G.n[2] + (m - gz);
     }
     const int sz_ = wrapn(z, G.n[2]);

@@ -276,6 +276,7 @@ struct GridDev {
     int g[3];    // guard width per axis
     int sy, sz;  // element strides (x stride 1)
     FastDiv div0, div1;  // division by n[0] and by n[1] (linear interior index -> x, y, z)
+    FastDiv divyg;       // division by the guarded row count n[1] + 2 g[1]
 };
 
 // One Yee update: X_i <- fout_i (fin_i X_i +/- dt curl(g Y)_i [- 4 pi dt J_i]).

@@ -270,6 +270,16 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
 /* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */
 int32_t pic_box_get(pic_box* box, pic_box_info* info);
 
+/* Resume from a checkpoint: set the step counter n of the box (t^n = n dt), on which the
+   shearing offset Delta y_s(t) (Sec. 2.1), the scale factor l(t) (Sec. 3.1) and the Philox
+   counters of the escape rules (id, step) depend, and refill the field guard cells at t^n.  A
+   checkpoint is the fields (pic_get_fields), the particles with ids and displacements
+   (pic_get_particles; those with cell -1 have escaped and are left out) and n; a box created
+   from the same descriptor and loaded with them (pic_set_fields, pic_set_particles, then
+   pic_set_step) continues the run with the same random stream.  Counters restart at zero.
+   PIC_EINVAL for n < 0; PIC_ESTATE while an unfused push awaits pic_deposit. */
+int32_t pic_set_step(pic_box* box, int64_t step);
+
 #define PIC_HIST_MAX_BINS 4096
 
 /* Particle energy distribution of one species (the diagnostic of Sec. 4.2): the kinetic

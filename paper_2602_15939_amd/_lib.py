@@ -87,6 +87,7 @@ def lib():
             "pic_step": ([boxes, i32, u32], i32),
             "pic_box_get": ([vp, C.POINTER(pic_box_info)], i32),
             "pic_energy_histogram": ([vp, i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_uint64)], i32),
+            "pic_set_step": ([vp, i64], i32),
             "pic_autotune": ([vp, u32, i32, C.POINTER(i32), C.POINTER(C.c_float), i32,
                               C.POINTER(i32)], i32),
             "pic_tile_candidates": ([i32, u32, C.POINTER(i32), i32], i32),
@@ -195,6 +196,10 @@ def pic_box_get(h) -> pic_box_info:
     info = pic_box_info()
     check(lib().pic_box_get(h, C.byref(info)), "pic_box_get")
     return info
+
+
+def pic_set_step(h, step):
+    check(lib().pic_set_step(h, int(step)), "pic_set_step")
 
 
 HIST_MAX_BINS = 4096

@@ -172,6 +172,10 @@ class Box:
     def info(self) -> L.pic_box_info:
         return L.pic_box_get(self.h)
 
+    def set_step(self, step):
+        """Resume at step n (after loading fields and particles from a checkpoint)."""
+        L.pic_set_step(self.h, step)
+
     def energy_histogram(self, species, edges):
         """Counts of gamma - 1 over the edges: [below, bin 0 .. bin nbins-1, at/above]."""
         self._wait_for_torch()

@@ -1580,6 +1580,14 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
     return r;
 }
 
+int32_t pic_set_step(pic_box* b, int64_t step)
+{
+    if (!b || step < 0) return PIC_EINVAL;
+    if (b->deposit_pending) return PIC_ESTATE;
+    b->step = step;
+    return fill_field_guards(b, time_of(b, step));
+}
+
 int32_t pic_energy_histogram(pic_box* b, int32_t s, const double* edges, int32_t nbins, uint64_t* counts)
 {
     if (!b || s < 0 || s >= b->nsp || !edges || !counts || nbins < 1 || nbins > kHistMaxBins)

@@ -248,6 +248,9 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration for profiles)")
     ap.add_argument("--settle", type=int, default=30,
                     help="untimed steps before the tile autotuner and the warmup")
+    ap.add_argument("--serial-sort", action="store_true",
+                    help="queue the tile sort on the box stream before each push instead of "
+                         "overlapping it with the current fold and the Maxwell step")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shape instead of pic_autotune's choice")
     ap.add_argument("--serve", action="store_true",
@@ -290,15 +293,23 @@ def main():
         tuned = {"tile": list(tile), "fused_kernel_ms": {"x".join(map(str, k)): v for k, v in ms.items()}}
         print(f"[bench] autotuned tile {tile}: {tuned['fused_kernel_ms']}", file=sys.stderr, flush=True)
 
+    # one step: the push (through the sort of the previous step), then the sort for the next
+    # step on the box's second stream, overlapping the current fold and the Maxwell step
     def one_step(ev=None):
-        L.pic_tile_sort(h)
+        if args.serial_sort:
+            L.pic_tile_sort(h)
         if ev is not None:
             ev[0].record(st)
         L.pic_gather_push(h, L.FUSE_DEPOSIT)
         if ev is not None:
             ev[1].record(st)
+        if not args.serial_sort:
+            L.pic_tile_sort(h, L.SORT_OVERLAP)
         L.pic_shear_remap(h, L.REMAP_CURRENT)
         L.pic_maxwell_step(h)  # also fills the field guard cells at t^{n+1}
+
+    if not args.serial_sort:
+        L.pic_tile_sort(h)
 
     for _ in range(args.warmup):
         one_step()
@@ -357,6 +368,7 @@ def main():
                    "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": n_avg / (gpd_ms * 1e-3),
                    "gpd_algorithmic_bytes": nbytes, "slow_path_particles": int(info.n_slow),
                    "kernel_source_hash": kernel_source_hash(), "settle_steps": args.settle,
+                   "sort": "serial" if args.serial_sort else "overlapped",
                    "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},

@@ -19,6 +19,7 @@ REMAP_FIELDS, REMAP_CURRENT = 1, 2
 BOX_TRACK_IDS = 1
 BOX_COUNT_SUPERLUMINAL = 2
 BOX_ESCAPE = 4
+SORT_OVERLAP = 1
 DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT, DERR_NOCONVERGE = 1, 2, 4, 8, 16, 32
 STEP_BATCHED = 1
 STEP_GRAPH = 2

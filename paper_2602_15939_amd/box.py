@@ -141,8 +141,9 @@ class Box:
         return perm[:n], off
 
     # ---- the hot path
-    def sort(self):
-        L.pic_tile_sort([self.h])
+    def sort(self, overlap=False):
+        """overlap: on the box's second stream, joined by the next particle or sort access."""
+        L.pic_tile_sort([self.h], L.SORT_OVERLAP if overlap else 0)
 
     def push(self, fuse=True):
         L.pic_gather_push([self.h], L.FUSE_DEPOSIT if fuse else 0)

@@ -98,6 +98,11 @@ struct pic_box {
     uint64_t uid = 0;  // unique over the process lifetime (graph keys)
     bool sorted = false;
     bool deposit_pending = false;
+    // PIC_SORT_OVERLAP: a sort on a second stream of the box, joined by the next call that
+    // touches particles or the sort (default priority, created on first use)
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, side_ev = nullptr;
+    bool side_pending = false;
     bool track_ids = false;
     std::vector<void*> allocs;
     // pic_box_create takes all of the box's device memory in one allocation: a first pass over
@@ -116,6 +121,14 @@ constexpr int kRedBlocks = 1024;
 constexpr int kRowAlign = 32;  // floats per 128-byte line
 
 int32_t hip_fail(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EDEVICE; }
+
+// make the box stream wait for a sort queued on the side stream (PIC_SORT_OVERLAP)
+int32_t side_join(pic_box* b)
+{
+    if (!b->side_pending) return PIC_OK;
+    b->side_pending = false;
+    return hip_fail(hipStreamWaitEvent(b->st, b->side_ev, 0));
+}
 
 // the leaky box's escape rule applies: always in the leaky frame, on request in the others
 bool escapes(const pic_box_desc* d)
@@ -387,6 +400,7 @@ int max_tiles(int dim, const int n[3])
 int32_t sort_box(pic_box* b)
 {
     if (b->deposit_pending) return PIC_ESTATE;  // the unfused deposit reads this sort's slots
+    if (side_join(b)) return PIC_EDEVICE;
     for (int s = 0; s < b->nsp; s++) {
         Species& S = b->sp[s];
         hipError_t e;
@@ -433,6 +447,7 @@ int32_t zero_current(pic_box* b)
 
 int32_t push_box(pic_box* b, bool fuse)
 {
+    if (side_join(b)) return PIC_EDEVICE;
     if (!b->sorted) return PIC_ESTATE;
     if (fuse) {
         int32_t r = zero_current(b);
@@ -465,6 +480,7 @@ int32_t push_box(pic_box* b, bool fuse)
 
 int32_t deposit_box(pic_box* b)
 {
+    if (side_join(b)) return PIC_EDEVICE;
     if (!b->deposit_pending) return PIC_ESTATE;
     int32_t r = zero_current(b);
     if (r) return r;
@@ -1117,6 +1133,12 @@ int32_t pic_box_destroy(pic_box* b)
 {
     if (!b) return PIC_OK;
     hipStreamSynchronize(b->st);
+    if (b->side) {
+        hipStreamSynchronize(b->side);
+        hipStreamDestroy(b->side);
+    }
+    if (b->fork_ev) hipEventDestroy(b->fork_ev);
+    if (b->side_ev) hipEventDestroy(b->side_ev);
     for (auto& g : b->graphs) hipGraphExecDestroy(g.exec);
     for (auto& sg : b->stage) {
         if (sg.host) hipHostFree(sg.host);
@@ -1331,6 +1353,7 @@ int32_t pic_set_particles(pic_box* b, int32_t s, int64_t n, const int32_t* cell,
                           const float* u, const uint32_t* id, const float* dr)
 {
     if (!b || s < 0 || s >= b->nsp || n < 0 || (n > 0 && (!cell || !off || !u))) return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
     Species& S = b->sp[s];
     if (n > S.cap) return PIC_ECAP;
     hipStream_t st = b->st;
@@ -1373,6 +1396,7 @@ int32_t pic_get_particles(pic_box* b, int32_t s, int64_t* n_out, int32_t* cell, 
                           uint32_t* id, float* dr)
 {
     if (!b || s < 0 || s >= b->nsp) return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
     Species& S = b->sp[s];
     int32_t n = 0;
     if (hipMemcpyAsync(&n, S.n_live, sizeof(int32_t), hipMemcpyDeviceToHost, b->st) != hipSuccess ||
@@ -1404,6 +1428,7 @@ int32_t pic_get_particles(pic_box* b, int32_t s, int64_t* n_out, int32_t* cell, 
 int32_t pic_get_sort(pic_box* b, int32_t s, int32_t* perm, int32_t* offsets, int32_t* n_tiles_out)
 {
     if (!b || s < 0 || s >= b->nsp) return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
     Species& S = b->sp[s];
     if (n_tiles_out) *n_tiles_out = b->tl.n_tiles;
     int32_t n = 0;
@@ -1420,10 +1445,33 @@ int32_t pic_get_sort(pic_box* b, int32_t s, int32_t* perm, int32_t* offsets, int
     return hip_fail(hipStreamSynchronize(b->st));
 }
 
-int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t)
+int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t flags)
 {
     int32_t r = check_boxes(boxes, nb);
-    for (int i = 0; i < nb && !r; i++) r = sort_box(boxes[i]);
+    for (int i = 0; i < nb && !r; i++) {
+        pic_box* b = boxes[i];
+        if (!(flags & PIC_SORT_OVERLAP)) {
+            r = sort_box(b);
+            continue;
+        }
+        // fork: the side stream takes over after the work queued so far (the push that wrote
+        // the positions); the sort's kernels run there; the join is left to the next call
+        // that touches particles or the sort
+        if (b->deposit_pending) return PIC_ESTATE;
+        if (side_join(b)) return PIC_EDEVICE;
+        if (!b->side && (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+                         hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&b->side_ev, hipEventDisableTiming) != hipSuccess))
+            return PIC_EDEVICE;
+        if (hipEventRecord(b->fork_ev, b->st) != hipSuccess || hipStreamWaitEvent(b->side, b->fork_ev, 0) != hipSuccess)
+            return PIC_EDEVICE;
+        hipStream_t main = b->st;
+        b->st = b->side;
+        r = sort_box(b);
+        b->st = main;
+        if (hipEventRecord(b->side_ev, b->side) != hipSuccess) return PIC_EDEVICE;
+        b->side_pending = true;
+    }
     return r;
 }
 
@@ -1485,6 +1533,7 @@ int32_t pic_autotune(pic_box* b, uint32_t flags, int32_t trials, int32_t* tile_o
                      int32_t max_out, int32_t* n_out)
 {
     if (!b || !tile_out || trials < 1 || trials > 64) return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
     if (b->deposit_pending) return PIC_ESTATE;
     int64_t live = 0;
     for (int s = 0; s < b->nsp; s++) live += b->sp[s].n_upper;
@@ -1564,6 +1613,7 @@ int32_t pic_autotune(pic_box* b, uint32_t flags, int32_t trials, int32_t* tile_o
 int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
 {
     int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++) r = side_join(boxes[i]);
     if (!r && (flags & (PIC_STEP_BATCHED | PIC_STEP_GRAPH)))
         return step_batched(boxes, nb, (flags & PIC_STEP_GRAPH) != 0);
     for (int i = 0; i < nb && !r; i++) {
@@ -1592,6 +1642,7 @@ int32_t pic_energy_histogram(pic_box* b, int32_t s, const double* edges, int32_t
 {
     if (!b || s < 0 || s >= b->nsp || !edges || !counts || nbins < 1 || nbins > kHistMaxBins)
         return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
     for (int i = 0; i <= nbins; i++)
         if (!std::isfinite(edges[i]) || (i > 0 && !(edges[i] > edges[i - 1]))) return PIC_EINVAL;
     static_assert(PIC_HIST_MAX_BINS == kHistMaxBins, "histogram size");
@@ -1611,6 +1662,7 @@ int32_t pic_energy_histogram(pic_box* b, int32_t s, const double* edges, int32_t
 int32_t pic_box_get(pic_box* b, pic_box_info* info)
 {
     if (!b || !info) return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
     std::memset(info, 0, sizeof(*info));
     hipStream_t st = b->st;
     if (field_energy(b->G, field_ptrs(b), 6, b->red_part, kRedBlocks, b->red_out, st) != hipSuccess)

@@ -95,3 +95,38 @@ def test_sort_after_push_with_escapes():
         assert info.n_sort_migrations == 2 * 7 and info.n_sort_fallbacks == 0
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("dim,n,frame,kw", [
+    (3, (32, 32, 32), "shear", dict(omega0=0.03)),
+    (2, (64, 48), "leaky", dict(leaky_mode=L.LEAKY_PROBABILISTIC, t_esc=4.0, gamma_thr=1.3)),
+])
+def test_overlapped_sort_equals_plain_sort(dim, n, frame, kw):
+    """PIC_SORT_OVERLAP (the sort for the next step on the box's second stream, overlapping the
+    current fold and Maxwell step) gives the same particles after every push, and the same
+    permutation and tile offsets, as the sort queued on the box stream before each push."""
+    from test_gpu_batched import assert_same_state
+
+    a = Case(dim, n, frame, ppc=4, theta=0.4, seed=71, **kw)
+    b = Case(dim, n, frame, ppc=4, theta=0.4, seed=71, **kw)
+    try:
+        b.gpu.sort()
+        for _ in range(6):
+            a.gpu.sort()
+            a.gpu.push()
+            a.gpu.remap(L.REMAP_CURRENT)
+            a.gpu.maxwell()
+            b.gpu.push()
+            b.gpu.sort(overlap=True)
+            b.gpu.remap(L.REMAP_CURRENT)
+            b.gpu.maxwell()
+        a.gpu.sort()  # b has sorted for its next push already
+        for s in range(2):
+            pa, oa = a.gpu.get_sort(s)
+            pb, ob = b.gpu.get_sort(s)
+            assert torch.equal(oa, ob) and torch.equal(pa, pb), s
+        assert_same_state(a, b, "overlap")
+        assert b.gpu.info().n_sort_migrations > 0
+    finally:
+        a.close()
+        b.close()

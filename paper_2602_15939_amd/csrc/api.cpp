@@ -537,12 +537,13 @@ int32_t maxwell_box(pic_box* b)
     const double tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
     hipStream_t st = b->st;
     if (b->d.frame == PIC_FRAME_SHEAR) {
-        // implicit midpoint by fixed-point sweeps from F^0 = F^n (with its own guards); every
-        // later iterate has its guards filled at t^{n+1}.  Three field sets: F^n (free once
-        // the first sweep has read it), C, and the iterates alternating with F^n's set.
+        // implicit midpoint by fixed-point sweeps from F^0 = F^n (with its own guards, at
+        // t^n); every later iterate has its x images at t^{n+1}.  Three field sets: F^n (free
+        // once the first sweep has read it), C, and the iterates alternating with F^n's set.
         const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
         const int sn = b->cur_set, sc = (sn + 1) % 3, sb2 = (sn + 2) % 3;
         const double dys1 = shear_offset(b, t1);
+        const double dys0 = shear_offset(b, tn);
         const bool tol = b->d.maxwell_tol > 0.0;
         if (tol && zero_floats(reinterpret_cast<float*>(b->conv), 2 * K, st) != hipSuccess)
             return PIC_EDEVICE;
@@ -559,6 +560,11 @@ int32_t maxwell_box(pic_box* b)
             Kd.dt = (float)dt;
             Kd.sO = (float)(b->d.shear_s * b->d.shear_omega0);
             Kd.half_nx = 0.5f * (float)b->n[0];
+            {
+                const double dys = k == 0 ? dys0 : dys1, fl = std::floor(dys);
+                Kd.ydys_int = (int)fl;
+                Kd.ydys_w = (float)(dys - fl);
+            }
             if (tol) {
                 Kd.conv = b->conv;
                 Kd.tol = (float)b->d.maxwell_tol;
@@ -567,10 +573,10 @@ int32_t maxwell_box(pic_box* b)
             if (ksb_sweep(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
             if (tol && k == K - 1 && ksb_finalize(ksb_fin(b, K, so), st) != hipSuccess)
                 return PIC_EDEVICE;
-            // the 3D sweep reads the y and z halo at the periodic images: between sweeps only
-            // the x guards (shearing-periodic images) are filled, all of them after the last
-            const bool x_only = b->dim == 3 && k < K - 1;
-            if (fill_guards(b->G, b->set[so], 6, 1, dys1, st, x_only) != hipSuccess) return PIC_EDEVICE;
+            // the staged 3D sweep reads its whole halo at the (shearing-)periodic images: then
+            // only the last iterate's guards are filled (for the push)
+            if ((!ksb_staged(b->G) || k == K - 1) && fill_guards(b->G, b->set[so], 6, 1, dys1, st) != hipSuccess)
+                return PIC_EDEVICE;
             sk = so;
             so = so == sb2 ? sn : sb2;
         }

@@ -32,6 +32,24 @@ __device__ inline int wrapn(int i, int n)
 // shearing box F(x_o + m, y) = F(x_i + m, y + dys) and F(x_i - m, y) = F(x_o - m, y - dys)
 // with a fractional dys applied by linear interpolation along y.
 
+// the image of an x guard cell between the two interior values a (at y + js) and b (at
+// y + js + 1), weight w on b; the guard fill and the 3D sweep's x halo share it
+__device__ inline float shear_lerp(float a, float b, float w) { return fmaf(w, b, (1.f - w) * a); }
+
+// y row offset js and weight w of the image of an x guard cell of the shearing box
+// (hi: beyond x = nx - 1, lo: before x = 0): hi y + dys = y + dys_int + w,
+// lo y - dys = y - dys_int - 1 + (1 - w)
+__device__ inline void shear_image(bool hi, int dys_int, float dys_w, int& js, float& w)
+{
+    if (hi) {
+        js = dys_int;
+        w = dys_w;
+    } else {
+        js = -dys_int - (dys_w > 0.f ? 1 : 0);
+        w = dys_w > 0.f ? 1.f - dys_w : 0.f;
+    }
+}
+
 __device__ __attribute__((always_inline)) inline void fill_guards_body(const FillArgs& a, int blk, int, int c)
 {
     const GridDev& G = a.G;
@@ -74,19 +92,12 @@ __device__ __attribute__((always_inline)) inline void fill_guards_body(const Fil
         const bool hi = x >= G.n[0];
         const int sx = hi ? x - G.n[0] : x + G.n[0];
         if (shear) {
-            // hi: y + dys = y + dys_int + w; lo: y - dys = y - dys_int - 1 + (1 - w)
             int js;
             float w;
-            if (hi) {
-                js = dys_int;
-                w = dys_w;
-            } else {
-                js = -dys_int - (dys_w > 0.f ? 1 : 0);
-                w = dys_w > 0.f ? 1.f - dys_w : 0.f;
-            }
+            shear_image(hi, dys_int, dys_w, js, w);
             const float a = F[gidx(G, sx, wrapn(y + js, G.n[1]), sz_)];
             const float b = F[gidx(G, sx, wrapn(y + js + 1, G.n[1]), sz_)];
-            v = (1.f - w) * a + w * b;
+            v = shear_lerp(a, b, w);
         } else {
             v = F[gidx(G, sx, wrapn(y, G.n[1]), sz_)];
         }
@@ -457,7 +468,8 @@ PIC_BATCHED_KERNEL(ksb_next, KsbDev, kBlock)
 // consecutive planes of the iterate (tile plus a one-cell halo) sit in LDS.  Halo positions
 // outside the interior are read through the boundary maps of the guard fill (y, z periodic;
 // x shearing-periodic with the fractional shift interpolated along y, the same arithmetic), so
-// the iterates need no guard fill between sweeps.  128 x 4 columns of 64-plane chunks (512
+// the iterates need no guard fill between sweeps (only the last one's guards are filled, for
+// the push).  128 x 4 columns of 64-plane chunks (512
 // threads, 56 KB of LDS, two workgroups per CU) measured fastest at 256^3 among 32..128 x
 // 2..16 x 16..128 (8 % below 32 x 8 x 32).  The iterate written and C read once per sweep use
 // nontemporal (streaming) stores and loads: a sweep moves far more than the caches hold, and
@@ -470,7 +482,11 @@ template <bool FIRST>
 __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
 {
     constexpr int NT = KX * KY;
-    constexpr int PER = (KXH * KYH + NT - 1) / NT;  // plane positions per thread
+    // staged plane positions: the KX tile columns of the KYH rows, then the 2 * KYH x halo
+    // positions, two per thread: j = 0 covers the first NT column positions, j = 1 the rest
+    // and the x halo (the grid's x size is a multiple of KX, so only these can be x halo)
+    constexpr int NCOL = KX * KYH, NPOS = NCOL + 2 * KYH;
+    static_assert(NCOL >= NT && NPOS <= 2 * NT, "two staged positions per thread");
     __shared__ float P[3][6][KYH * KXH];
     if (ksb_skip(K)) return;
     const GridDev& G = K.G;
@@ -478,44 +494,69 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
     // tiles x fastest, then y, then z chunk; each XCD takes a contiguous range so that the
     // halos of neighbouring tiles are shared in its L2
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
-    const int ntx = (nx + KX - 1) / KX, nty = (ny + KY - 1) / KY;
+    const int ntx = nx / KX, nty = (ny + KY - 1) / KY;
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
     const int x0 = (tile % ntx) * KX, y0 = ((tile / ntx) % nty) * KY, z0 = (tile / (ntx * nty)) * KZ;
     const int z1 = min(z0 + KZ, nz);
     const int x = x0 + tx, y = y0 + ty;
-    const bool inside = x < nx && y < ny;
+    const bool inside = y < ny;
     const float* const* F = K.Fk;
-    // staged position j: in-plane offset of its source.  y and z halo positions are read at
-    // their periodic images; x halo positions from the x guard cells (the shearing-periodic
-    // images, filled before the sweep).  Positions beyond the first layer outside the grid
-    // (ragged tiles) are never read by a valid cell.
-    int off[PER];
-    bool ok[PER];
+    // staged position j: LDS slot and in-plane offset of its source.  y and z halo positions
+    // are read at their periodic images; the x halo positions (x = -1, x = nx) at their
+    // shearing-periodic images: two interior values of the opposite x face, y rows js and
+    // js + 1 from the position's y, interpolated as the guard fill does, so that no guard fill
+    // is needed between sweeps.  Rows beyond the first one outside the grid (ragged y tiles)
+    // are never read by a valid cell.
+    int slot[2], off[2];
+    bool ok[2];
+    bool xh = false;  // position j = 1 is an x halo image
+    int off2 = 0;
+    float wx = 0.f;
 #pragma unroll
-    for (int j = 0; j < PER; j++) {
-        const int e = tid + j * NT;
-        const int lx = e % KXH, ly = e / KXH;
+    for (int j = 0; j < 2; j++) {
+        const int q = tid + j * NT;
+        int lx, ly;
+        if (q < NCOL) {
+            lx = 1 + q % KX;
+            ly = q / KX;
+        } else {
+            const int r = q - NCOL;
+            lx = (r & 1) ? KXH - 1 : 0;
+            ly = r >> 1;
+        }
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        ok[j] = e < KXH * KYH && gx <= nx && gy <= ny;
-        const int yy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-        off[j] = ok[j] ? gx + G.sy * yy : 0;
+        ok[j] = q < NPOS && gy <= ny;
+        slot[j] = ly * KXH + lx;
+        int js = 0;
+        float w = 0.f;
+        const bool img = j == 1 && ok[j] && (gx < 0 || gx >= nx);
+        if (img) shear_image(gx >= nx, K.ydys_int, K.ydys_w, js, w);
+        const int sx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+        const int ya = wrapn(gy + js, ny);
+        off[j] = ok[j] ? sx + G.sy * ya : 0;
+        if (j == 1) {
+            xh = img;
+            off2 = img ? sx + G.sy * wrapn(ya + 1, ny) : 0;
+            wx = w;
+        }
     }
-    // register stage of one plane (loads in flight while the previous plane is computed)
-    float R[PER][6];
+    // register stage of one plane (loads in flight while the previous plane is computed; the
+    // x images are interpolated when the plane is stashed)
+    float R[2][6], R2[6];
     auto fetch = [&](int z) {
         const int64_t pz = (int64_t)G.sz * (z < 0 ? z + nz : (z >= nz ? z - nz : z));
 #pragma unroll
-        for (int j = 0; j < PER; j++)
-#pragma unroll
-            for (int c = 0; c < 6; c++) R[j][c] = ok[j] ? F[c][off[j] + pz] : 0.f;
+        for (int c = 0; c < 6; c++) {
+            R[0][c] = ok[0] ? F[c][off[0] + pz] : 0.f;
+            R[1][c] = ok[1] ? F[c][off[1] + pz] : 0.f;
+            R2[c] = xh ? F[c][off2 + pz] : 0.f;
+        }
     };
-    auto stash = [&](int slot) {
+    auto stash = [&](int s) {
 #pragma unroll
-        for (int j = 0; j < PER; j++) {
-            const int e = tid + j * NT;
-            if (e < KXH * KYH)
-#pragma unroll
-                for (int c = 0; c < 6; c++) P[slot][c][e] = R[j][c];
+        for (int c = 0; c < 6; c++) {
+            if (ok[0]) P[s][c][slot[0]] = R[0][c];
+            if (ok[1]) P[s][c][slot[1]] = xh ? shear_lerp(R[1][c], R2[c], wx) : R[1][c];
         }
     };
     const float v0 = -K.sO * ((float)x - K.half_nx);
@@ -742,7 +783,7 @@ __global__ void sum_rows_kernel(const double* part, int nrow, int ncol, double* 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
-                       hipStream_t st, bool x_only)
+                       hipStream_t st)
 {
     Comp6 A{};
     for (int c = 0; c < ncomp; c++) A.p[c] = comps[c];
@@ -752,7 +793,6 @@ hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int she
     const int NYg = G.n[1] + 2 * G.g[1], NZg = G.n[2] + 2 * G.g[2];
     fill_guards_kernel<<<dim3(nblocks((int64_t)2 * G.g[0] * NYg * NZg), ncomp), kBlock, 0, st>>>(
         FillArgs{G, A, 0, shear, di, w});
-    if (x_only) return hipGetLastError();
     fill_guards_kernel<<<dim3(nblocks((int64_t)G.n[0] * 2 * G.g[1] * NZg), ncomp), kBlock, 0, st>>>(
         FillArgs{G, A, 1, shear, di, w});
     if (G.g[2] > 0)
@@ -803,10 +843,12 @@ hipError_t yee_e(const MaxwellDev& M, hipStream_t st)
     yee_e_kernel<<<nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kBlock, 0, st>>>(M);
     return hipGetLastError();
 }
+bool ksb_staged(const GridDev& G) { return G.dim == 3 && G.n[0] % KX == 0; }
+
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
 {
-    if (K.G.dim == 3) {
-        const unsigned grid = (unsigned)(((K.G.n[0] + KX - 1) / KX) * ((K.G.n[1] + KY - 1) / KY) *
+    if (ksb_staged(K.G)) {
+        const unsigned grid = (unsigned)((K.G.n[0] / KX) * ((K.G.n[1] + KY - 1) / KY) *
                                          ((K.G.n[2] + KZ - 1) / KZ));
         if (first)
             ksb_sweep3_kernel<true><<<grid, KX * KY, 0, st>>>(K);

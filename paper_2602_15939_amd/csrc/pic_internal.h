@@ -334,6 +334,10 @@ struct KsbDev {
     float* Fo[6];        // next iterate (interior)
     const float* J[3];
     float dt, sO, half_nx;
+    // shift of the iterate's shearing-periodic x images, Delta y_s = ydys_int + ydys_w with
+    // ydys_w in [0,1) (the 3D sweep reads its x halo there instead of from guard cells)
+    int ydys_int;
+    float ydys_w;
     // tolerance mode (conv != nullptr): sweep k adds max|F^{k+1} - F^k| and max|F^{k+1}| (FP32
     // bit patterns, non-negative, so unsigned order is float order; NaN counts as +inf) into
     // conv[2k], conv[2k+1], which start at zero; it returns at once when the sweep before it
@@ -463,10 +467,8 @@ enum SortBatchKind { kBatchMigCount, kBatchMigOffsets, kBatchScan, kBatchMigScat
 hipError_t sort_batch(SortBatchKind k, const void* table, UnitMap m, int blocks, hipStream_t st);
 int sort_result_buffer(const Tiles& tl);  // sort buffer holding the sorted pairs
 
-// x_only: only the x guard slabs (the shearing-periodic images), for readers that take the y
-// and z halos at their periodic images themselves
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
-                       hipStream_t st, bool x_only = false);
+                       hipStream_t st);
 // Fold the current guards (y, z periodic in place).  Shearing box: the J' transport and the
 // shearing-periodic x fold in one pass from J into `out` (the caller then swaps the two arrays);
 // otherwise the periodic x fold in place.
@@ -474,6 +476,10 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* out, in
                         double sO, double dt, double dys_half, hipStream_t st);
 hipError_t yee_b(const MaxwellDev& M, hipStream_t st);
 hipError_t yee_e(const MaxwellDev& M, hipStream_t st);
+// one sweep; 3D grids whose x size is a multiple of the staged kernel's column tile (128) take
+// the staged kernel, which reads its whole halo at the (shearing-)periodic images itself;
+// otherwise one thread per cell reads the guard cells, which must be filled between sweeps
+bool ksb_staged(const GridDev& G);
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st);
 hipError_t ksb_finalize(const KsbFin& F, hipStream_t st);
 constexpr int kKsbFinBlocks = 512;  // workgroups per box of the finalize copy (grid stride)

@@ -1465,9 +1465,10 @@ int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t flags)
         // that touches particles or the sort
         if (b->deposit_pending) return PIC_ESTATE;
         if (side_join(b)) return PIC_EDEVICE;
-        if (!b->side && (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
-                         hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
-                         hipEventCreateWithFlags(&b->side_ev, hipEventDisableTiming) != hipSuccess))
+        // created on first use (each that is still missing, so a failed creation is retried)
+        if ((!b->side && hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) ||
+            (!b->fork_ev && hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) ||
+            (!b->side_ev && hipEventCreateWithFlags(&b->side_ev, hipEventDisableTiming) != hipSuccess))
             return PIC_EDEVICE;
         if (hipEventRecord(b->fork_ev, b->st) != hipSuccess || hipStreamWaitEvent(b->side, b->fork_ev, 0) != hipSuccess)
             return PIC_EDEVICE;

@@ -130,3 +130,31 @@ def test_overlapped_sort_equals_plain_sort(dim, n, frame, kw):
     finally:
         a.close()
         b.close()
+
+
+def test_overlapped_sort_then_whole_steps_and_batched_step():
+    """Calls that sort or step again after an overlapped sort wait for it: a box sorted on its
+    second stream and then stepped (alone, then batched with a twin) ends like the box sorted
+    on its own stream."""
+    from test_gpu_batched import assert_same_state
+    from paper_2602_15939_amd.box import step_many
+
+    a = Case(3, (24, 24, 24), "shear", ppc=3, theta=0.4, seed=73, omega0=0.03)
+    b = Case(3, (24, 24, 24), "shear", ppc=3, theta=0.4, seed=73, omega0=0.03)
+    try:
+        a.gpu.sort()
+        b.gpu.sort(overlap=True)
+        a.gpu.step()
+        b.gpu.step()
+        a.gpu.sort()
+        b.gpu.sort(overlap=True)
+        a.gpu.push()
+        b.gpu.push()
+        a.gpu.sort()
+        b.gpu.sort(overlap=True)
+        step_many([a.gpu], batched=True)
+        step_many([b.gpu], batched=True)
+        assert_same_state(a, b, "overlap then step")
+    finally:
+        a.close()
+        b.close()

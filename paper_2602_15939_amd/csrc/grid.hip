@@ -180,11 +180,9 @@ __device__ inline float shear_transport(const GridDev& G, const float* __restric
 // takes its own transported value plus, on the first and last g columns, the transported
 // guard column of the other face at the y shift of the shearing-periodic map (the exact
 // transpose of the field guard fill's interpolation).
-__device__ __attribute__((always_inline)) inline void shear_fold_body(const ShearFoldArgs& a, int blk, int, int c)
+__device__ __attribute__((always_inline)) inline void shear_fold_cell(const ShearFoldArgs& a, int64_t t, int c)
 {
     const GridDev& G = a.G;
-    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
     int x, y, z;
     cell_of(G, t, x, y, z);
     const int nx = G.n[0], ny = G.n[1], ga = G.g[0];
@@ -206,6 +204,13 @@ __device__ __attribute__((always_inline)) inline void shear_fold_body(const Shea
              w * shear_transport(G, F, c, x - nx, wrapn(y - js - 1, ny), z, a.sO_hdt, a.half_nx);
     }
     a.out.p[c][gidx(G, x, y, z)] = v;
+}
+// grid-stride over the cells (the batched launch gives every cell its own thread)
+__device__ __attribute__((always_inline)) inline void shear_fold_body(const ShearFoldArgs& a, int blk, int nblk, int c)
+{
+    const int64_t n = (int64_t)a.G.n[0] * a.G.n[1] * a.G.n[2];
+    for (int64_t t = (int64_t)blk * kBlock + threadIdx.x; t < n; t += (int64_t)nblk * kBlock)
+        shear_fold_cell(a, t, c);
 }
 PIC_BATCHED_KERNEL(shear_fold, ShearFoldArgs, kBlock)
 
@@ -271,11 +276,9 @@ PIC_BATCHED_KERNEL(fold_x, FoldXArgs, kBlock)
 
 
 // B_i <- fout_i (fin_i B_i - dt/2 curl(g E)_i)
-__device__ __attribute__((always_inline)) inline void yee_b_body(const MaxwellDev& M, int blk, int, int)
+__device__ __attribute__((always_inline)) inline void yee_b_cell(const MaxwellDev& M, int64_t t)
 {
     const GridDev& G = M.G;
-    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
     int x, y, z;
     cell_of(G, t, x, y, z);
     const int64_t i = gidx(G, x, y, z);
@@ -293,14 +296,18 @@ __device__ __attribute__((always_inline)) inline void yee_b_body(const MaxwellDe
     M.B[1][i] = M.fout[1] * (M.fin[1] * M.B[1][i] - h * cy);
     M.B[2][i] = M.fout[2] * (M.fin[2] * M.B[2][i] - h * cz);
 }
+// grid-stride over the cells (the batched launch gives every cell its own thread)
+__device__ __attribute__((always_inline)) inline void yee_b_body(const MaxwellDev& M, int blk, int nblk, int)
+{
+    const int64_t n = (int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2];
+    for (int64_t t = (int64_t)blk * kBlock + threadIdx.x; t < n; t += (int64_t)nblk * kBlock) yee_b_cell(M, t);
+}
 PIC_BATCHED_KERNEL(yee_b, MaxwellDev, kBlock)
 
 // E_i <- fout_i (fin_i E_i + dt curl(g B)_i - 4 pi dt J_i)
-__device__ __attribute__((always_inline)) inline void yee_e_body(const MaxwellDev& M, int blk, int, int)
+__device__ __attribute__((always_inline)) inline void yee_e_cell(const MaxwellDev& M, int64_t t)
 {
     const GridDev& G = M.G;
-    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    if (t >= (int64_t)G.n[0] * G.n[1] * G.n[2]) return;
     int x, y, z;
     cell_of(G, t, x, y, z);
     const int64_t i = gidx(G, x, y, z);
@@ -317,6 +324,12 @@ __device__ __attribute__((always_inline)) inline void yee_e_body(const MaxwellDe
     M.E[0][i] = M.fout[0] * (M.fin[0] * M.E[0][i] + M.dt * cx - fp * M.J[0][i]);
     M.E[1][i] = M.fout[1] * (M.fin[1] * M.E[1][i] + M.dt * cy - fp * M.J[1][i]);
     M.E[2][i] = M.fout[2] * (M.fin[2] * M.E[2][i] + M.dt * cz - fp * M.J[2][i]);
+}
+// grid-stride over the cells (the batched launch gives every cell its own thread)
+__device__ __attribute__((always_inline)) inline void yee_e_body(const MaxwellDev& M, int blk, int nblk, int)
+{
+    const int64_t n = (int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2];
+    for (int64_t t = (int64_t)blk * kBlock + threadIdx.x; t < n; t += (int64_t)nblk * kBlock) yee_e_cell(M, t);
 }
 PIC_BATCHED_KERNEL(yee_e, MaxwellDev, kBlock)
 
@@ -781,6 +794,10 @@ __global__ void sum_rows_kernel(const double* part, int nrow, int ncol, double* 
 
 // ------------------------------------------------------------------ host launchers
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+// grid of the grid-stride cell kernels (the shear fold, the Yee updates): 16 blocks per CU,
+// each thread taking a few cells, measured faster than one thread per cell (fold at 256^3:
+// 0.18 against 0.22 ms)
+constexpr unsigned kStrideBlocks = 4096;
 
 hipError_t fill_guards(const GridDev& G, float* const* comps, int ncomp, int shear, double dys,
                        hipStream_t st)
@@ -823,7 +840,8 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* out, in
     const float w = (float)(dys_half - fl);
     if (shear) {
         Comp3 Oc{{out[0], out[1], out[2]}};
-        shear_fold_kernel<<<dim3(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), 3), kBlock, 0, st>>>(
+        const unsigned nb = std::min(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), kStrideBlocks);
+        shear_fold_kernel<<<dim3(nb, 3), kBlock, 0, st>>>(
             ShearFoldArgs{G, Jc, Oc, (float)(sO * dt / 2.0), 0.5f * G.n[0], di, w});
     } else {
         const int nl = G.n[0] < 2 * G.g[0] ? G.n[0] : 2 * G.g[0];
@@ -835,12 +853,12 @@ hipError_t fold_current(const GridDev& G, float* const* J, float* const* out, in
 
 hipError_t yee_b(const MaxwellDev& M, hipStream_t st)
 {
-    yee_b_kernel<<<nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kBlock, 0, st>>>(M);
+    yee_b_kernel<<<std::min(nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kStrideBlocks), kBlock, 0, st>>>(M);
     return hipGetLastError();
 }
 hipError_t yee_e(const MaxwellDev& M, hipStream_t st)
 {
-    yee_e_kernel<<<nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kBlock, 0, st>>>(M);
+    yee_e_kernel<<<std::min(nblocks((int64_t)M.G.n[0] * M.G.n[1] * M.G.n[2]), kStrideBlocks), kBlock, 0, st>>>(M);
     return hipGetLastError();
 }
 bool ksb_staged(const GridDev& G) { return G.dim == 3 && G.n[0] % KX == 0; }

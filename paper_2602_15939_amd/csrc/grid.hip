@@ -664,10 +664,19 @@ __device__ __attribute__((always_inline)) inline void ksb_final_body(const KsbFi
 PIC_BATCHED_KERNEL(ksb_final, KsbFin, kBlock)
 
 // ------------------------------------------------------------------ utilities
-__device__ __attribute__((always_inline)) inline void zero_body(const ZeroArgs& a, int blk, int, int)
+// grid-stride, 16-byte stores where the array is 16-byte aligned (the batched launch gives
+// every word its own thread, so most of its threads find nothing to do)
+__device__ __attribute__((always_inline)) inline void zero_body(const ZeroArgs& a, int blk, int nblk, int)
 {
-    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
-    if (i < a.n) a.p[i] = 0u;
+    const int64_t stride = (int64_t)nblk * kBlock, i = (int64_t)blk * kBlock + threadIdx.x;
+    int64_t head = 0;
+    if ((reinterpret_cast<uintptr_t>(a.p) & 15) == 0) {
+        uint4* q = reinterpret_cast<uint4*>(a.p);
+        const int64_t n4 = a.n >> 2;
+        for (int64_t j = i; j < n4; j += stride) q[j] = make_uint4(0u, 0u, 0u, 0u);
+        head = n4 << 2;
+    }
+    for (int64_t j = head + i; j < a.n; j += stride) a.p[j] = 0u;
 }
 PIC_BATCHED_KERNEL(zero, ZeroArgs, kBlock)
 
@@ -918,7 +927,9 @@ unsigned grid_blocks(int64_t items) { return nblocks(items); }
 
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st)
 {
-    if (n > 0) zero_kernel<<<nblocks(n), kBlock, 0, st>>>(ZeroArgs{reinterpret_cast<uint32_t*>(p), n});
+    if (n > 0)
+        zero_kernel<<<std::min(nblocks((n + 3) / 4), kStrideBlocks), kBlock, 0, st>>>(
+            ZeroArgs{reinterpret_cast<uint32_t*>(p), n});
     return hipGetLastError();
 }
 hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense, hipStream_t st)

@@ -261,7 +261,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=160.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: every box of this build lives on a single MI355X; "
+        print("bench.py runs on one GPU: every box of this library lives on a single MI355X; "
               "--gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
     if args.serve:

@@ -482,9 +482,8 @@ PIC_BATCHED_KERNEL(ksb_next, KsbDev, kBlock)
 // outside the interior are read through the boundary maps of the guard fill (y, z periodic;
 // x shearing-periodic with the fractional shift interpolated along y, the same arithmetic), so
 // the iterates need no guard fill between sweeps (only the last one's guards are filled, for
-// the push).  128 x 4 columns of 64-plane chunks (512
-// threads, 56 KB of LDS, two workgroups per CU) measured fastest at 256^3 among 32..128 x
-// 2..16 x 16..128 (8 % below 32 x 8 x 32).  The iterate written and C read once per sweep use
+// the push).  128 x 4 columns of 64-plane chunks (512 threads, 56 KB of LDS, two workgroups
+// per CU) measured fastest at 256^3 among 32..128 x 2..16 x 16..128 (8 % below 32 x 8 x 32).  The iterate written and C read once per sweep use
 // nontemporal (streaming) stores and loads: a sweep moves far more than the caches hold, and
 // the halo reads of the iterate, which neighbouring workgroups share, keep the normal policy
 // (another 9 %).

@@ -514,7 +514,11 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
         uint32_t nesc = 0;  // probabilistic escapes (one counter add per wave, at the end)
         uint32_t nsl = 0;   // shearing box: superluminal effective velocities (likewise)
         const uint32_t beg = (uint32_t)S.toff[tile], end = (uint32_t)S.toff[tile + 1];
-        for (uint32_t slot = beg + tid; slot < end; slot += NT) {
+        // the waves take 64-slot groups aligned to 32 slots (the 128-byte lines of the 4-byte
+        // particle arrays), so that their stores fill whole lines; the lanes before the tile's
+        // first slot idle in the first round
+        for (uint32_t slot = (beg & ~31u) + tid; slot < end; slot += NT) {
+            if (slot < beg) continue;
             uint32_t so = slot;
             asm("" : "+v"(so));  // keeps the 32-bit offset form (scalar base) for the stores
             const uint32_t src = (uint32_t)ld_at(S.perm, slot);

@@ -302,6 +302,19 @@ int32_t pic_set_step(pic_box* box, int64_t step);
 int32_t pic_energy_histogram(pic_box* box, int32_t species, const double* edges, int32_t nbins,
                              uint64_t* counts_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): pic_energy_histogram with the same arguments,
+   results and errors, whose scratch (the device copy of the edges and the counts being summed)
+   is one static device array per GPU instead of the box's buffers.  It calls no hipMalloc,
+   hipFree or other allocating routine.  The array holds PIC_HIST_STATIC_MAX_BINS bins (about
+   64 KiB); nbins above it is PIC_EINVAL.  The box's device must be the current device.  Every
+   call on one GPU shares that GPU's array, which keeps the last call's contents (the counts are
+   cleared by a kernel at the start of each call): calls that overlap on one GPU, from several
+   host threads or on several streams, race.  Synchronises. */
+#define PIC_HIST_STATIC_MAX_BINS 4096
+int32_t pic_energy_histogram_static(pic_box* box, int32_t species, const double* edges,
+                                    int32_t nbins, uint64_t* counts_out);
+
 /* Measurement utility, not part of the method: a plain streaming device-to-device copy of
    nbytes (a multiple of 16; both pointers 16-byte aligned device memory owned by the caller)
    on `stream` (a hipStream_t, NULL for the default stream), asynchronous.  Its known traffic

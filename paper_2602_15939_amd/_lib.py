@@ -88,6 +88,8 @@ def lib():
             "pic_step": ([boxes, i32, u32], i32),
             "pic_box_get": ([vp, C.POINTER(pic_box_info)], i32),
             "pic_energy_histogram": ([vp, i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_uint64)], i32),
+            "pic_energy_histogram_static": ([vp, i32, C.POINTER(C.c_double), i32,
+                                             C.POINTER(C.c_uint64)], i32),
             "pic_set_step": ([vp, i64], i32),
             "pic_autotune": ([vp, u32, i32, C.POINTER(i32), C.POINTER(C.c_float), i32,
                               C.POINTER(i32)], i32),
@@ -204,12 +206,16 @@ def pic_set_step(h, step):
 
 
 HIST_MAX_BINS = 4096
+HIST_STATIC_MAX_BINS = 4096
 
 
-def pic_energy_histogram(h, species, edges):
-    """edges: nbins + 1 increasing floats; returns nbins + 2 counts (below, bins, at/above)."""
+def pic_energy_histogram(h, species, edges, static=False):
+    """edges: nbins + 1 increasing floats; returns nbins + 2 counts (below, bins, at/above).
+    static=True: the variant whose scratch is the library's static device array (no
+    allocation)."""
     nb = len(edges) - 1
     e = (C.c_double * (nb + 1))(*[float(v) for v in edges])
     out = (C.c_uint64 * (nb + 2))()
-    check(lib().pic_energy_histogram(h, species, e, nb, out), "pic_energy_histogram")
+    name = "pic_energy_histogram_static" if static else "pic_energy_histogram"
+    check(getattr(lib(), name)(h, species, e, nb, out), name)
     return list(out)

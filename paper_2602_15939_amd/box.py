@@ -177,10 +177,11 @@ class Box:
         """Resume at step n (after loading fields and particles from a checkpoint)."""
         L.pic_set_step(self.h, step)
 
-    def energy_histogram(self, species, edges):
-        """Counts of gamma - 1 over the edges: [below, bin 0 .. bin nbins-1, at/above]."""
+    def energy_histogram(self, species, edges, static=False):
+        """Counts of gamma - 1 over the edges: [below, bin 0 .. bin nbins-1, at/above].
+        static=True uses the entry point that allocates nothing (static device scratch)."""
         self._wait_for_torch()
-        return L.pic_energy_histogram(self.h, species, edges)
+        return L.pic_energy_histogram(self.h, species, edges, static=static)
 
 
 def step_many(boxes, batched=True, graph=False):

@@ -1666,6 +1666,36 @@ int32_t pic_energy_histogram(pic_box* b, int32_t s, const double* edges, int32_t
     return hip_fail(hipStreamSynchronize(st));
 }
 
+int32_t pic_energy_histogram_static(pic_box* b, int32_t s, const double* edges, int32_t nbins,
+                                    uint64_t* counts)
+{
+    if (!b || s < 0 || s >= b->nsp || !edges || !counts || nbins < 1) return PIC_EINVAL;
+    if (nbins > PIC_HIST_STATIC_MAX_BINS) return PIC_EINVAL;  // beyond the static scratch
+    if (side_join(b)) return PIC_EDEVICE;
+    for (int i = 0; i <= nbins; i++)
+        if (!std::isfinite(edges[i]) || (i > 0 && !(edges[i] > edges[i - 1]))) return PIC_EINVAL;
+    static_assert(PIC_HIST_STATIC_MAX_BINS <= kHistMaxBins, "static histogram size");
+    void* scr = nullptr;
+    size_t scr_bytes = 0;
+    if (static_scratch(&scr, &scr_bytes) != hipSuccess) return PIC_EDEVICE;
+    if (scr_bytes < kStaticHistCountsOffset + sizeof(uint64_t) * (size_t)(nbins + 2)) return PIC_EINVAL;
+    double* dev_edges = static_cast<double*>(scr);
+    auto* dev_counts = reinterpret_cast<unsigned long long*>(static_cast<char*>(scr) + kStaticHistCountsOffset);
+    hipStream_t st = b->st;
+    const Species& S = b->sp[s];
+    const int k = S.cur;
+    // energy_histogram clears the counts with a fill kernel before it adds into them (the
+    // scratch keeps the last call's contents)
+    if (hipMemcpyAsync(dev_edges, edges, sizeof(double) * (nbins + 1), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        energy_histogram(S.cell[k], S.u[k][0], S.u[k][1], S.u[k][2], S.n_live, dev_edges, nbins,
+                         dev_counts, kRedBlocks, st) != hipSuccess ||
+        hipMemcpyAsync(counts, dev_counts, sizeof(uint64_t) * (nbins + 2), hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+        return PIC_EDEVICE;
+    return hip_fail(hipStreamSynchronize(st));
+}
+
 int32_t pic_box_get(pic_box* b, pic_box_info* info)
 {
     if (!b || !info) return PIC_EINVAL;

@@ -496,6 +496,15 @@ hipError_t energy_histogram(const int32_t* cell, const float* ux, const float* u
                             const int32_t* n_live, const double* edges, int nbins,
                             unsigned long long* counts, int nblk, hipStream_t st);
 
+// Static device scratch of the entry points that allocate nothing (noalloc.hip): the current
+// device's copy of one file-scope array of kStaticScratchBytes, its address taken once per
+// device.  The histogram variant keeps its edges (FP64, kHistMaxBins + 1) at the start and its
+// counts (uint64, kHistMaxBins + 2) at kStaticHistCountsOffset.
+constexpr size_t kStaticHistCountsOffset = ((size_t)(kHistMaxBins + 1) * 8 + 255) & ~(size_t)255;
+constexpr size_t kStaticScratchBytes =
+    (kStaticHistCountsOffset + (size_t)(kHistMaxBins + 2) * 8 + 255) & ~(size_t)255;
+hipError_t static_scratch(void** ptr, size_t* bytes);
+
 hipError_t cells_linear_to_packed(const int32_t* lin, int32_t* packed, int64_t n, const int nn[3],
                                   CellCode cc, uint32_t* err, hipStream_t st);
 hipError_t cells_packed_to_linear(const int32_t* packed, int32_t* lin, int64_t n, const int nn[3],

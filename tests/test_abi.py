@@ -112,6 +112,7 @@ def test_null_arguments(lib):
     edges = (C.c_double * 3)(0.0, 1.0, 2.0)
     counts = (C.c_uint64 * 4)()
     assert lib.pic_energy_histogram(None, 0, edges, 2, counts) == L.PIC_EINVAL
+    assert lib.pic_energy_histogram_static(None, 0, edges, 2, counts) == L.PIC_EINVAL
     assert lib.pic_set_step(None, 0) == L.PIC_EINVAL
     assert lib.pic_box_create(None, C.byref(out)) == L.PIC_EINVAL
     assert lib.pic_box_create(C.byref(_desc()), None) == L.PIC_EINVAL

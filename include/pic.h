@@ -80,7 +80,8 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
                                 carried.  Implied by PIC_FRAME_LEAKY */
 
 /* sticky device error bits (pic_box_info.errors) */
-#define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell */
+#define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell, or (shearing box)
+                                the y increment with the shear move reached a whole cell */
 #define PIC_DERR_NAN 2u      /* non-finite momentum */
 #define PIC_DERR_ORDER 4u    /* a particle outside its tile: handled on the slow path */
 #define PIC_DERR_CELL 8u     /* pic_set_particles met a cell index outside the grid */
@@ -194,6 +195,19 @@ int32_t pic_get_particles(pic_box* box, int32_t species, int64_t* n_out, int32_t
    n_tiles+1 tile offsets.  Synchronises. */
 int32_t pic_get_sort(pic_box* box, int32_t species, int32_t* perm_dev, int32_t* offsets_dev,
                      int32_t* n_tiles_out);
+
+/* The record of the last pic_gather_push made without PIC_FUSE_DEPOSIT: per particle, in the
+   slot order pic_get_particles returns after that push, the old cell (linear index, as at the
+   boundary), the old in-cell offsets (off_dev: dim arrays of n) and the FP32 displacement of
+   the deposit (disp_dev: 3 arrays of n; comoving x' - x^n in the shearing box, Sec. 2.2;
+   primed in the expanding box, Sec. 3.2).  The new position is the old one moved by this
+   displacement (plus, in the shearing box, the shear move of Sec. 2.2) under the FP32
+   renormalisation and the boundary conditions (Sec. 2.1): the record lets a caller check that
+   integer layer bit for bit.  *n_out receives the count; any output pointer may be NULL.
+   PIC_ESTATE if the last push was fused (or none was made since the particles were loaded).
+   Synchronises. */
+int32_t pic_get_push_record(pic_box* box, int32_t species, int64_t* n_out, int32_t* cell_dev,
+                            float* off_dev, float* disp_dev);
 
 /* Tile-shape autotuner.  For every supported tile shape (PIC_TUNE_BATCHED: those of the batched
    step) it re-tiles the box, sorts its particles (radix sort) and times the fused

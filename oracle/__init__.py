@@ -344,6 +344,23 @@ def f32_normalize(cell, off, delta):
     return co, oo
 
 
+def f32_move(box: Box, cell, off, disp):
+    """FP32 position update of the integer layer: (cell, off) moved by the FP32 deposit
+    displacement disp (3, n) with the frame's shear move and boundaries at t^{n+1} =
+    (box.step + 1) dt.  Returns (cell_out, off_out, err)."""
+    cell = np.ascontiguousarray(cell, dtype=np.int32)
+    n = len(cell)
+    off = np.ascontiguousarray(off, dtype=np.float32).reshape(box.dim, n)
+    disp = np.ascontiguousarray(disp, dtype=np.float32).reshape(3, n)
+    co = np.zeros_like(cell)
+    oo = np.zeros_like(off)
+    err = np.zeros(n, dtype=np.uint8)
+    lib().ora_f32_move(C.byref(box), C.c_int64(n), _p(cell, C.c_int32), _p(off, C.c_float),
+                       _p(disp, C.c_float), _p(co, C.c_int32), _p(oo, C.c_float),
+                       _p(err, C.c_uint8))
+    return co, oo, err
+
+
 def energies(box: Box, E, B, J, species):
     f = _fields(E, B, J)
     arr = (Species * len(species))(*[s.cstruct() for s in species])

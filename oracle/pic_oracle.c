@@ -1020,27 +1020,100 @@ void ora_tile_keys(const ora_box* b, const int t[3], int64_t n, const int32_t* c
 /* The FP32 path keeps a position as an int32 cell plus an FP32 offset in [0,1).  After
    s = off + delta (FP32, |delta| < 1): s >= 1 -> (cell+1, s-1), exact for s in [1,2);
    s < 0 -> t = s + 1, (cell-1, t) if t < 1, else (cell, 0) since 1.0 is never stored. */
+static float f32_renorm(float off, float delta, int* dc)
+{
+    volatile float s = off + delta;
+    float r = s;
+    *dc = 0;
+    if (s >= 1.0f) {
+        *dc = 1;
+        r = s - 1.0f;
+    } else if (s < 0.0f) {
+        volatile float t = s + 1.0f;
+        if (t < 1.0f) {
+            *dc = -1;
+            r = t;
+        } else {
+            r = 0.0f;
+        }
+    }
+    return r;
+}
+
 void ora_f32_normalize(int64_t n, const int32_t* cell, const float* off, const float* delta,
                        int32_t* cell_out, float* off_out)
 {
     for (int64_t p = 0; p < n; p++) {
-        volatile float s = off[p] + delta[p];
-        int32_t c = cell[p];
-        float r = s;
-        if (s >= 1.0f) {
-            c += 1;
-            r = s - 1.0f;
-        } else if (s < 0.0f) {
-            volatile float t = s + 1.0f;
-            if (t < 1.0f) {
-                c -= 1;
-                r = t;
-            } else {
-                r = 0.0f;
+        int dc;
+        off_out[p] = f32_renorm(off[p], delta[p], &dc);
+        cell_out[p] = cell[p] + dc;
+    }
+}
+
+/* The position update of the FP32 path, bit for bit: a particle stored as a cell (linear
+   index) plus FP32 in-cell offsets moves by its FP32 deposit displacement D (Sec. 2.2, 3.2,
+   4.1).  Per axis the offset takes D in one FP32 addition and is renormalised as above.  The
+   shearing box adds its shear move to the y increment (Sec. 2.2): with x^n = (i - n_x/2) +
+   off_x the radial coordinate, v_s = -(s Omega0) (x^n + D_x/2) is the flow at the midpoint x
+   of the move and dy = D_y + dt v_s, in FP32 with x^n + D_x/2 and D_y + dt v_s each a fused
+   multiply-add (one rounding) and s Omega0, dt, n_x/2 cast to FP32 once.  An x-face crossing
+   wraps x and, in the shearing box, moves y by +Delta y_s(t^{n+1}) (leaving through x_o) or
+   -Delta y_s (through x_i), Sec. 2.1: the FP64 offset splits into floor and an FP32 fraction
+   in [0,1) (a fraction that rounds to 1 becomes 0 with the next integer); the fraction is added
+   to the y offset and renormalised, the integer to the cell.  y and z wrap periodically.
+   err[p] = 1 where a deposit displacement reaches half a cell or the y increment a whole cell
+   (the renormalisation then does not apply); the outputs there are not meaningful. */
+void ora_f32_move(const ora_box* b, int64_t n, const int32_t* cell, const float* off,
+                  const float* disp, int32_t* cell_out, float* off_out, uint8_t* err)
+{
+    const int nd = b->dim, nx = b->n[0], ny = b->n[1], nz = b->n[2];
+    const double t1 = (double)b->step * b->dt + b->dt;
+    const double dys = ora_shear_offset(b, t1);
+    const double fl = floor(dys);
+    int dys_int = (int)fl;
+    float dys_frac = (float)(dys - fl);
+    if (dys_frac >= 1.0f) {
+        dys_frac = 0.0f;
+        dys_int = (dys_int + 1) % ny;
+    }
+    const float sO = (float)(b->shear_s * b->omega0), dt = (float)b->dt;
+    const float half_nx = 0.5f * (float)nx;
+    for (int64_t p = 0; p < n; p++) {
+        int i = cell[p] % nx, j = (cell[p] / nx) % ny, k = cell[p] / (nx * ny);
+        float o[3] = {off[p], off[n + p], nd == 3 ? off[2 * n + p] : 0.0f};
+        float D[3] = {disp[p], disp[n + p], disp[2 * n + p]};
+        float dy = D[1];
+        if (b->frame == ORA_SHEAR) {
+            volatile float xr = ((float)i - half_nx) + o[0];
+            volatile float mid = fmaf(0.5f, D[0], xr);
+            volatile float vs = -sO * mid;
+            dy = fmaf(dt, vs, D[1]);
+        }
+        int bad = !(fabsf(D[0]) < 0.5f && fabsf(D[1]) < 0.5f && (nd == 2 || fabsf(D[2]) < 0.5f) &&
+                    fabsf(dy) < 1.0f);
+        int dc[3] = {0, 0, 0};
+        o[0] = f32_renorm(o[0], D[0], &dc[0]);
+        o[1] = f32_renorm(o[1], dy, &dc[1]);
+        if (nd == 3) o[2] = f32_renorm(o[2], D[2], &dc[2]);
+        i += dc[0];
+        j += dc[1];
+        k += dc[2];
+        if (i >= nx || i < 0) {
+            const int out = i >= nx;
+            i += out ? -nx : nx;
+            if (b->frame == ORA_SHEAR) {
+                int d2;
+                o[1] = f32_renorm(o[1], out ? dys_frac : -dys_frac, &d2);
+                j += (out ? dys_int : -dys_int) + d2;
             }
         }
-        cell_out[p] = c;
-        off_out[p] = r;
+        j = wrapi(j, ny);
+        if (nd == 3) k = wrapi(k, nz);
+        cell_out[p] = (int32_t)cidx(b, i, j, k);
+        off_out[p] = o[0];
+        off_out[n + p] = o[1];
+        if (nd == 3) off_out[2 * n + p] = o[2];
+        err[p] = (uint8_t)bad;
     }
 }
 

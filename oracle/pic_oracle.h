@@ -147,6 +147,11 @@ void ora_energies(const ora_box* b, const ora_fields* f, const ora_species* sp, 
    (int32 cell + FP32 offset).  Applies off + delta in FP32 and renormalises to [0,1). */
 void ora_f32_normalize(int64_t n, const int32_t* cell, const float* off, const float* delta,
                        int32_t* cell_out, float* off_out);
+/* FP32 integer layer of the position update: cell (linear) + offsets (dim x n) moved by the
+   FP32 deposit displacement disp (3 x n) with the frame's shear move and boundaries at
+   t^{n+1} = (b->step + 1) dt; err[p] = 1 where the displacement breaks the step bounds. */
+void ora_f32_move(const ora_box* b, int64_t n, const int32_t* cell, const float* off,
+                  const float* disp, int32_t* cell_out, float* off_out, uint8_t* err);
 /* tile key of the cell (i,j,k) for tile shape t[3], dead particles (i < 0) -> n_tiles */
 void ora_tile_keys(const ora_box* b, const int t[3], int64_t n, const int32_t* ci,
                    const int32_t* cj, const int32_t* ck, int32_t* keys);

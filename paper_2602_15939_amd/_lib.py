@@ -79,6 +79,7 @@ def lib():
             "pic_set_particles": ([vp, i32, i64, vp, vp, vp, vp, vp], i32),
             "pic_get_particles": ([vp, i32, C.POINTER(i64), vp, vp, vp, vp, vp], i32),
             "pic_get_sort": ([vp, i32, vp, vp, C.POINTER(i32)], i32),
+            "pic_get_push_record": ([vp, i32, C.POINTER(i64), vp, vp, vp], i32),
             "pic_tile_sort": ([boxes, i32, u32], i32),
             "pic_gather_push": ([boxes, i32, u32], i32),
             "pic_deposit": ([boxes, i32, u32], i32),
@@ -168,6 +169,12 @@ def pic_get_particles(h, species, cell, off, u, ids=None, dr=None) -> int:
     n = C.c_int64()
     check(lib().pic_get_particles(h, species, C.byref(n), cell, off, u, ids, dr),
           "pic_get_particles")
+    return n.value
+
+
+def pic_get_push_record(h, species, cell, off, disp) -> int:
+    n = C.c_int64()
+    check(lib().pic_get_push_record(h, species, C.byref(n), cell, off, disp), "pic_get_push_record")
     return n.value
 
 

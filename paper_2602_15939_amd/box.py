@@ -128,6 +128,19 @@ class Box:
                             ids.data_ptr(), dr.data_ptr())
         return dict(cell=cell, off=off, u=u, id=ids, dr=dr)
 
+    def get_push_record(self, species=0):
+        """Old cell, old offsets and FP32 deposit displacement of every particle of the last
+        unfused push, in the slot order of get_particles."""
+        n = self.count(species)
+        cell = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        off = torch.empty((self.dim, max(n, 1)), dtype=torch.float32, device="cuda")
+        disp = torch.empty((3, max(n, 1)), dtype=torch.float32, device="cuda")
+        m = L.pic_get_push_record(self.h, species, cell.data_ptr(), off.data_ptr(), disp.data_ptr())
+        assert m == n
+        if n == 0:
+            return dict(cell=cell[:0], off=off[:, :0], disp=disp[:, :0])
+        return dict(cell=cell, off=off, disp=disp)
+
     def get_sort(self, species=0):
         """(perm, offsets) of the last tile sort: perm[i] = pre-sort index of sorted slot i."""
         import ctypes as C

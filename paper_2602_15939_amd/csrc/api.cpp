@@ -98,6 +98,7 @@ struct pic_box {
     uint64_t uid = 0;  // unique over the process lifetime (graph keys)
     bool sorted = false;
     bool deposit_pending = false;
+    bool record_valid = false;  // the unfused-deposit workspace holds the last push's record
     // PIC_SORT_OVERLAP: a sort on a second stream of the box, joined by the next call that
     // touches particles or the sort (default priority, created on first use)
     hipStream_t side = nullptr;
@@ -475,6 +476,7 @@ int32_t push_box(pic_box* b, bool fuse)
     }
     b->sorted = false;
     b->deposit_pending = !fuse;
+    b->record_valid = !fuse;
     return PIC_OK;
 }
 
@@ -830,6 +832,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
                 b->sp[s].counts_ready = P.count_mig != 0;
             }
             b->sorted = false;
+            b->record_valid = false;
         }
         plan.grid(kBatchZero, z, zb, 1);
         for (auto& kv : groups) {
@@ -1391,6 +1394,7 @@ int32_t pic_set_particles(pic_box* b, int32_t s, int64_t n, const int32_t* cell,
         }
     }
     if (set_i32(S.n_live, (int32_t)n, st) != hipSuccess) return PIC_EDEVICE;
+    b->record_valid = false;
     S.n_upper = (int)n;
     S.grouped = false;
     S.counts_ready = false;
@@ -1449,6 +1453,30 @@ int32_t pic_get_sort(pic_box* b, int32_t s, int32_t* perm, int32_t* offsets, int
                                   hipMemcpyDeviceToDevice, b->st) != hipSuccess)
         return PIC_EDEVICE;
     return hip_fail(hipStreamSynchronize(b->st));
+}
+
+int32_t pic_get_push_record(pic_box* b, int32_t s, int64_t* n_out, int32_t* cell, float* off,
+                            float* disp)
+{
+    if (!b || s < 0 || s >= b->nsp) return PIC_EINVAL;
+    if (side_join(b)) return PIC_EDEVICE;
+    if (!b->record_valid) return PIC_ESTATE;
+    Species& S = b->sp[s];
+    int32_t n = 0;
+    if (hipMemcpyAsync(&n, S.n_live, sizeof(int32_t), hipMemcpyDeviceToHost, b->st) != hipSuccess ||
+        hipStreamSynchronize(b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (n_out) *n_out = n;
+    hipStream_t st = b->st;
+    const size_t fb = sizeof(float) * (size_t)n;
+    if (cell && cells_packed_to_linear(S.ws_cell, cell, n, b->n, b->cc, st) != hipSuccess) return PIC_EDEVICE;
+    for (int c = 0; c < b->dim && off; c++)
+        if (n && hipMemcpyAsync(off + c * n, S.ws_off[c], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    for (int c = 0; c < 3 && disp; c++)
+        if (n && hipMemcpyAsync(disp + c * n, S.ws_disp[c], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PIC_EDEVICE;
+    return hip_fail(hipStreamSynchronize(st));
 }
 
 int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t flags)

@@ -542,7 +542,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             }
 
             // ---- push
-            const float xr = (float)cx - P.half_nx + ox; // radial x of the shearing box
+            const float xr = __fadd_rn(__fsub_rn((float)cx, P.half_nx), ox);  // radial x (shearing box)
             if (FRAME == kShear)
                 u = push_shear(u, E, B, S.qm_hdt, P.alpha1, P.sO * xr, P.om_dt);
             else if (FRAME == kExpand)
@@ -556,9 +556,20 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             const float hs = P.dt * ig;
             f3 D = hs * u;
             if (FRAME == kExpand) D = mk(D.x * P.linv[0], D.y * P.linv[1], D.z * P.linv[2]);
+            // y increment of the position: the shearing box adds the shear move
+            // y -= s Omega0 (x' + x^n)/2 dt (Sec. 2.2), x' + x^n = 2 x^n + D.x, each operation
+            // rounded as written (the FP32 integer layer of the oracle repeats it bit for bit)
+            float dyt = D.y, vs = 0.f;
+            if (FRAME == kShear) {
+                vs = __fmul_rn(-P.sO, __fmaf_rn(0.5f, D.x, xr));  // v_s at the midpoint x
+                dyt = __fmaf_rn(P.dt, vs, D.y);
+            }
             // one test catches both: a non-finite momentum makes D NaN, which fails every
-            // comparison; a finite one fails it when a displacement reaches half a cell
-            if (!(fabsf(D.x) < 0.5f && fabsf(D.y) < 0.5f && (DIM == 2 || fabsf(D.z) < 0.5f)))
+            // comparison; a finite one fails it when a deposit displacement reaches half a cell
+            // or the shear move takes the y increment to a whole cell (the offset
+            // renormalisation needs |increment| < 1)
+            if (!(fabsf(D.x) < 0.5f && fabsf(D.y) < 0.5f && (DIM == 2 || fabsf(D.z) < 0.5f) &&
+                  fabsf(dyt) < 1.f))
                 latch(P.err, (isfinite(u.x) && isfinite(u.y) && isfinite(u.z)) ? 1u : 2u);
 
             // ---- deposit xn -> xn + D
@@ -588,10 +599,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
 
             // ---- new position: x' = x^n + D, then (shearing box) the shear move
             // y -= s Omega0 (x' + x^n)/2 dt (Sec. 2.2)
-            float dyt = D.y;
             if (FRAME == kShear) {
-                const float vs = -P.sO * (xr + 0.5f * D.x);  // v_s at the midpoint x of the move
-                dyt = D.y + P.dt * vs;
                 // the effective velocity u'/gamma' + v_s e_y (eq. OAx) can exceed c for
                 // relativistic particles (Sec. 2.1): counted, not corrected.  With
                 // |u'|^2/gamma'^2 = 1 - 1/gamma'^2, |v|^2 > 1 reads vs (2 u'_y/gamma' + vs) > 1/gamma'^2.

@@ -1,0 +1,253 @@
+"""The integer layer on the GPU, and charge continuity in the shearing and expanding frames.
+
+  * cell indices and FP32 offsets after a push equal, bit for bit, the oracle's FP32 position
+    layer applied to the GPU's own old positions and FP32 deposit displacements (the record of
+    an unfused push): plain, shearing (with the shear move and the shearing-periodic y shift of
+    x-face crossings), expanding and leaky boxes, 2D and 3D, with particles started on and
+    within one ulp of the cell edges and at the x faces moving out of the box;
+  * a shearing box whose face flow moves particles a whole cell in y per step latches
+    PIC_DERR_CFL, and the oracle's layer flags the same particles;
+  * continuity rho(x^{n+1}) - rho(x^n) + dt div J = 0 for the expanding box in primed
+    coordinates (the deposit gives l J' directly, Sec. 3.1) and for the leaky box;
+  * the shearing box (Sec. 2.2): the comoving deposit x^n -> x' folded through the shearing-
+    periodic x faces at an integer Delta y_s(t^{n+1/2}) conserves charge; the GPU's current is
+    read after the J' transport, which the test undoes column by column (its linear-
+    interpolation weights are well conditioned for the small shifts used here).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _cases import Case, positions_f64
+from paper_2602_15939_amd import _lib as L
+from paper_2602_15939_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SIZE = {2: (40, 36), 3: (20, 12, 16)}
+
+
+def edge_particles(n, dim, seed):
+    """particles on and next to cell edges, and at the x faces moving outwards"""
+    rng = np.random.default_rng(seed)
+    below1 = np.nextafter(np.float32(1), np.float32(0))
+    tiny = np.float32(2.0 ** -30)
+    offs = np.array([0.0, tiny, below1, 0.5, np.nextafter(np.float32(0.5), np.float32(0))], np.float32)
+    m = 200
+    ncell = int(np.prod(n))
+    cell = rng.integers(0, ncell, m)
+    off = rng.choice(offs, size=(dim, m)).astype(np.float32)
+    u = rng.normal(0, 0.02, (3, m)).astype(np.float32)
+    # x faces: half of them in the first or last column, moving out of the box
+    face = rng.random(m) < 0.5
+    out = rng.random(m) < 0.5
+    ix = np.where(out, n[0] - 1, 0)
+    rest = cell // n[0]
+    cell = np.where(face, ix + n[0] * rest, cell)
+    off[0] = np.where(face, np.where(out, below1, np.float32(0.0)), off[0])
+    u[0] = np.where(face, np.where(out, 0.6, -0.6), u[0]).astype(np.float32)
+    return cell.astype(np.int32), off, u
+
+
+def parts_with_edges(n, dim, ppc, theta, seed):
+    parts = synth.pair_plasma(n, ppc, theta, seed)
+    out = []
+    for s, p in enumerate(parts):
+        c, o, u = edge_particles(n, dim, seed + 10 * s)
+        out.append(dict(cell=torch.cat([p["cell"], torch.from_numpy(c)]),
+                        off=torch.cat([p["off"], torch.from_numpy(o)], dim=1),
+                        u=torch.cat([p["u"], torch.from_numpy(u)], dim=1)))
+    return out
+
+
+CASES = [(d, f) for f in ("plain", "shear", "expand", "leaky") for d in (2, 3)]
+
+
+@pytest.mark.parametrize("dim,frame", CASES)
+def test_cells_and_offsets_bit_exact_against_the_fp32_layer(dim, frame):
+    n = SIZE[dim]
+    print(f"[integer] {frame} {dim}D", flush=True)
+    c = Case(dim, n, frame, parts=parts_with_edges(n, dim, 3, 0.3, 700 + dim), seed=700 + dim)
+    try:
+        for _ in range(2):
+            c.gpu.step()
+        c.box.step = 2  # the oracle's layer takes the step for Delta y_s(t^{n+1})
+        if frame == "shear":
+            dys = oracle.shear_offset(c.box, 3 * c.box.dt)
+            assert 0.02 < dys % 1 < 0.98
+        c.gpu.sort()
+        c.gpu.push(fuse=False)
+        crossed_x = 0
+        for s in range(2):
+            rec = {k: v.cpu().numpy() for k, v in c.gpu.get_push_record(s).items()}
+            g = c.gpu_species(s)
+            co, oo, err = oracle.f32_move(c.box, rec["cell"], rec["off"], rec["disp"])
+            assert not err.any()
+            live = g["cell"] >= 0
+            np.testing.assert_array_equal(g["cell"][live], co[live])
+            np.testing.assert_array_equal(g["off"][:, live].view(np.uint32), oo[:, live].view(np.uint32))
+            old_i = rec["cell"] % n[0]
+            new_i = g["cell"] % n[0]
+            crossed_x += int(np.sum(np.abs(new_i - old_i) > 1))
+        assert crossed_x > 20  # the x-face crossings were exercised
+        c.gpu.deposit()
+        assert c.gpu.info().errors & ~L.DERR_ORDER == 0
+    finally:
+        c.close()
+
+
+def test_whole_cell_shear_move_latches_cfl_like_the_fp32_layer():
+    """E' = B = 0 and particles at rest across a 128-cell shearing box with s Omega0 = 0.05: the
+    flow at |x| >= 44.4 moves them a whole cell per step or more."""
+    n = (128, 8)
+    xs = np.arange(0.25, 128.0, 0.5)
+    k = len(xs)
+    cell = (np.floor(xs).astype(np.int32) + 128 * 3)
+    off = np.stack([xs - np.floor(xs), np.full(k, 0.5)]).astype(np.float32)
+    u = np.zeros((3, k), np.float32)
+    part = dict(cell=torch.from_numpy(cell), off=torch.from_numpy(off), u=torch.from_numpy(u))
+    zero = (np.zeros((3, 1, n[1], n[0]), np.float32),) * 2
+    c = Case(2, n, "shear", parts=[part, dict(part)], fields=zero, q=0.0, shear_s=1.5,
+             omega0=0.05 / 1.5)
+    try:
+        c.gpu.sort()
+        c.gpu.push(fuse=False)
+        assert c.gpu.info().errors & L.DERR_CFL
+        for s in range(2):
+            rec = {kk: v.cpu().numpy() for kk, v in c.gpu.get_push_record(s).items()}
+            g = c.gpu_species(s)
+            co, oo, err = oracle.f32_move(c.box, rec["cell"], rec["off"], rec["disp"])
+            xr = (rec["cell"] % n[0]) + rec["off"][0] - 64.0
+            np.testing.assert_array_equal(err.astype(bool), np.abs(0.45 * 0.05 * xr) >= 1.0)
+            ok = err == 0
+            np.testing.assert_array_equal(g["cell"][ok], co[ok])
+            np.testing.assert_array_equal(g["off"][:, ok].view(np.uint32), oo[:, ok].view(np.uint32))
+        c.gpu.deposit()
+    finally:
+        c.close()
+
+
+def div_J(J, dim):
+    d = J[0] - np.roll(J[0], 1, axis=2) + J[1] - np.roll(J[1], 1, axis=1)
+    if dim == 3:
+        d = d + J[2] - np.roll(J[2], 1, axis=0)
+    return d
+
+
+@pytest.mark.parametrize("dim,frame", [(2, "expand"), (3, "expand"), (2, "leaky"), (3, "leaky")])
+def test_continuity_expanding_primed_and_leaky(dim, frame):
+    print(f"[continuity] {frame} {dim}D", flush=True)
+    c = Case(dim, SIZE[dim], frame, ppc=6, seed=730 + dim, adot=5e-3, l_esc=50.0)
+    try:
+        for _ in range(3):  # at a later time: l(t) > 1 and Lambda != 0
+            c.gpu.step()
+        before = [c.gpu_species(s) for s in range(2)]
+        c.gpu.sort()
+        c.gpu.push(fuse=True)
+        c.gpu.remap(L.REMAP_CURRENT)
+        J = c.gpu.get_current().cpu().numpy().astype(np.float64)
+        rho0, rho1, gross = (np.zeros(J.shape[1:]) for _ in range(3))
+        for s in range(2):
+            q = c.qms[s] * c.q
+            for g, rho in ((before[s], rho0), (c.gpu_species(s), rho1)):
+                x, y, z = positions_f64(g["cell"], g["off"], c.n, dim)
+                oracle.charge(c.box, q, x, y, z if dim == 3 else None, rho)
+                if rho is rho0:
+                    oracle.charge(c.box, abs(q), x, y, z if dim == 3 else None, gross)
+        res = rho1 - rho0 + c.box.dt * div_J(J, dim)
+        assert np.abs(res).max() <= 1e-6 * gross.max()
+        assert np.abs(J).max() > 0
+    finally:
+        c.close()
+
+
+def _charge_ext(x, y, q, nxe, ny):
+    """CIC charge at the nodes 0..nxe-1 (x not wrapped) of positions x, y (y periodic)"""
+    rho = np.zeros((ny, nxe))
+    i0, j0 = np.floor(x).astype(int), np.floor(y).astype(int)
+    wx, wy = x - i0, y - j0
+    for di, fx in ((0, 1 - wx), (1, wx)):
+        for dj, fy in ((0, 1 - wy), (1, wy)):
+            np.add.at(rho, (np.mod(j0 + dj, ny), i0 + di), q * fx * fy)
+    return rho
+
+
+def _untransport(col, d):
+    """invert J_lab(y) = (1-w) J(y - m) + w J(y - m - 1), m = floor(d), w = d - m (periodic)"""
+    ny = len(col)
+    m = int(np.floor(d))
+    w = d - m
+    A = np.zeros((ny, ny))
+    for j in range(ny):
+        A[j, (j - m) % ny] += 1 - w
+        A[j, (j - m - 1) % ny] += w
+    return np.linalg.solve(A, col)
+
+
+def test_continuity_shearing_box_comoving_deposit_through_the_faces():
+    n = (40, 36)
+    nx, ny = n
+    dt, s = 0.45, 1.5
+    sO = 1.0 / 45.0  # Delta y_s(t^{n+1/2}) = s Omega0 n_x (n + 1/2) dt = 1 cell at n = 2
+    rng = np.random.default_rng(740)
+    parts = []
+    for sp in range(2):
+        # group A in the last column (crossing x_o, its guard current folds into columns 0, 1);
+        # group B in columns 3 .. n_x - 5 (never touches columns 0, 1 or the x_i guards)
+        ma, mb = 400, 3000
+        ia = np.full(ma, nx - 1)
+        ib = rng.integers(3, nx - 4, mb)
+        i = np.concatenate([ia, ib])
+        j = rng.integers(0, ny, ma + mb)
+        off = rng.uniform(0, 1, (2, ma + mb)).astype(np.float32)
+        u = rng.normal(0, 0.25, (3, ma + mb)).astype(np.float32)
+        u[0, :ma] = np.abs(u[0, :ma]) + 0.2  # group A moves outwards
+        parts.append(dict(cell=torch.from_numpy((i + nx * j).astype(np.int32)),
+                          off=torch.from_numpy(off), u=torch.from_numpy(u)))
+    c = Case(2, n, "shear", parts=parts, shear_s=s, omega0=sO / s, seed=741)
+    try:
+        c.gpu.set_step(2)
+        c.box.step = 2
+        th = 2.5 * dt
+        dys_h = oracle.shear_offset(c.box, th)
+        K = int(round(dys_h))
+        assert K == 1 and abs(dys_h - K) < 1e-12
+        c.gpu.sort()
+        c.gpu.push(fuse=False)
+        recs = [{k: v.cpu().numpy() for k, v in c.gpu.get_push_record(sp).items()} for sp in range(2)]
+        c.gpu.deposit()
+        c.gpu.remap(L.REMAP_CURRENT)
+        Jlab = c.gpu.get_current().cpu().numpy().astype(np.float64)[:, 0]  # (3, ny, nx)
+        nxe = nx + 2  # columns 0 .. nx+1: the two x_o guard columns appended
+        Jdep = np.zeros((3, ny, nxe))
+        stag = (0.5, 0.0, 0.0)
+        for comp in range(3):
+            for i in range(nxe):
+                d = -sO * (i + stag[comp] - nx / 2) * dt / 2
+                if 2 <= i < nx:
+                    Jdep[comp, :, i] = _untransport(Jlab[comp, :, i], d)
+                elif i >= nx:  # guard column nx + k was transported, then folded to column k at
+                    # y + K
+                    Jdep[comp, :, i] = _untransport(np.roll(Jlab[comp, :, i - nx], -K), d)
+        rho0, rho1, gross = np.zeros((ny, nxe)), np.zeros((ny, nxe)), np.zeros((ny, nxe))
+        for sp in range(2):
+            q = c.qms[sp] * c.q
+            r = recs[sp]
+            x0 = (r["cell"] % nx) + r["off"][0].astype(np.float64)
+            y0 = (r["cell"] // nx) + r["off"][1].astype(np.float64)
+            x1 = x0 + r["disp"][0].astype(np.float64)  # x' = x^n + D (comoving)
+            y1 = y0 + r["disp"][1].astype(np.float64)
+            assert x1.max() < nxe - 1 and x0.min() >= 3
+            rho0 += _charge_ext(x0, y0, q, nxe, ny)
+            rho1 += _charge_ext(x1, y1, q, nxe, ny)
+            gross += _charge_ext(x0, y0, abs(q), nxe, ny)
+        div = np.zeros((ny, nxe))
+        div[:, 1:] += Jdep[0, :, 1:] - Jdep[0, :, :-1]
+        div += Jdep[1] - np.roll(Jdep[1], 1, axis=0)
+        res = rho1 - rho0 + dt * div
+        assert np.abs(res[:, 1:]).max() <= 1e-6 * gross.max()
+        # the guard columns carried charge through the face, and the current there is not small
+        assert np.abs(Jdep[:, :, nx:]).max() > 0.1 * np.abs(Jdep).max()
+    finally:
+        c.close()

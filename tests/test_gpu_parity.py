@@ -192,15 +192,46 @@ def test_displacement_escape_and_reinjection(dim, use_3vec):
             c.oracle_step()
             for s in range(2):
                 g = c.gpu_species(s)
-                st = compare_particles(c, s, g, tol_u=1e-5)
+                st = compare_particles(c, s, g)
                 o = c.sp[s]
                 dr_o = o.dr[:, st["sel"]]
                 # escape decisions are FP32 on the GPU and FP64 in the oracle: only a particle
                 # within rounding of l_esc may differ, and none should here
                 assert np.abs(g["dr"][:ncomp] - dr_o[:ncomp]).max() < 1e-5
-                assert st["err_u"] < 1e-5, (step, s, st["err_u"])
+                # re-drawn momenta (FP32 table interpolation and sincos, measured 4e-7) within
+                # the push bar
+                assert st["err_u"] < 2e-6, (step, s, st["err_u"])
                 nesc += int((dr_o[0] == 0).sum())
         assert nesc > 100
+    finally:
+        c.close()
+
+
+def test_displacement_drift_over_1000_steps():
+    """The tracked displacement of Sec. 4.1 accumulates in FP32: over n steps its distance from
+    the FP64 sum is bounded by the rounding of the n additions, n 2^-24 max|dr|, plus the FP32
+    error of the increments (~1e-7 cells each).  Frozen fields (straight lines), l_esc beyond
+    reach; measured 4.8e-3 cells at |dr| = 351 after 1000 steps (bound 2.1e-2), i.e. escape
+    decisions at l_esc ~ 10^3 can differ from FP64 for particles within ~1e-2 cells of l_esc."""
+    dims = (32, 32)
+    zero = (np.zeros((3, 1, 32, 32), np.float32),) * 2
+    parts = frozen_parts(4000, 1.6, 1.2, 77, dims)
+    c = Case(2, dims, "leaky", parts=parts, fields=zero, q=0.0, leaky_mode=L.LEAKY_DISPLACEMENT,
+             l_esc=1024.0, theta_inj=0.3)
+    try:
+        nsteps = 1000
+        for _ in range(nsteps):
+            c.gpu.step()
+            c.oracle_step(nthreads=8)
+        err = big = 0.0
+        for s in range(2):
+            g = c.gpu_species(s)
+            st = compare_particles(c, s, g)
+            o = c.sp[s]
+            err = max(err, float(np.abs(g["dr"][:2, st["live"]] - o.dr[:2, st["sel"]]).max()))
+            big = max(big, float(np.abs(o.dr[:2]).max()))
+        assert big > 300
+        assert err <= nsteps * (2.0 ** -24 * big + 1e-7), err
     finally:
         c.close()
 
@@ -234,30 +265,32 @@ def test_energy_history_config0_200_steps():
         c.close()
 
 
-@pytest.mark.parametrize("frame", ["shear", "expand", "leaky"])
-def test_energy_history_1000_steps(frame):
+@pytest.mark.parametrize("dim,frame", [(2, "shear"), (2, "expand"), (2, "leaky"), (3, "shear")])
+def test_energy_history_1000_steps(dim, frame):
     """Field and kinetic energy histories within 1% of the FP64 oracle over 1000 steps, sampled
-    every 50 steps, at the size of the parity configuration (64x64 cells, 16 ppc per species,
-    theta 0.1, skin depth 4 cells, sigma 0.1, B0 along z): the shearing box (q = 1.5,
-    Omega0 = 0.1 omega_c), the expanding box (x and y, perpendicular to B0, grow as
-    a = 1 + adot t with adot = 1e-3 omega_p) and the leaky box in the paper's displacement mode
-    (escape at |dr| = L/2, Maxwell-Juttner reinjection at the plasma temperature: every particle
-    crosses that distance many times in 1000 steps).  Live particle counts equal."""
+    every 50 steps, at the size of the parity configuration (64x64 cells, 16 ppc per species;
+    3D: 16^3 cells, 8 ppc per species; theta 0.1, skin depth 4 cells, sigma 0.1, B0 along z):
+    the shearing box (q = 1.5, Omega0 = 0.1 omega_c), the expanding box (x and y, perpendicular
+    to B0, grow as a = 1 + adot t with adot = 1e-3 omega_p) and the leaky box in the paper's
+    displacement mode (escape at |dr| = L/2, Maxwell-Juttner reinjection at the plasma
+    temperature: every particle crosses that distance many times in 1000 steps).  The magnetic
+    energy per component (the observable of the shearing-box application, Sec. 2.3) within 1%
+    of the total magnetic energy.  Live particle counts equal."""
     import os
 
     from paper_2602_15939_amd import synth
-    dims = (64, 64)
-    ppc = 16
+    dims = (64, 64) if dim == 2 else (16, 16, 16)
+    ppc = 16 if dim == 2 else 8
     wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.1)
-    E, B = synth.uniform_field(dims, 2, B0)
+    E, B = synth.uniform_field(dims, 2, B0)  # B0 along z
     fields = (E.astype(np.float32), B.astype(np.float32))
     kw = dict(shear=dict(shear_s=1.5, omega0=0.1 * B0, maxwell_iters=8),
               expand=dict(adot=1e-3 * wp, axis_mask=0b011),
               leaky=dict(leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=32.0, theta_inj=0.1))[frame]
-    c = Case(2, dims, frame, ppc=ppc, theta=0.1, seed=4051, fields=fields, q=q, **kw)
+    c = Case(dim, dims, frame, ppc=ppc, theta=0.1, seed=4051, fields=fields, q=q, **kw)
     nthreads = min(16, len(os.sched_getaffinity(0)))
     try:
-        hist_g, hist_o = [], []
+        hist_g, hist_o, bc_g, bc_o = [], [], [], []
         for step in range(1000):
             c.gpu.step()
             c.oracle_step(nthreads=nthreads)
@@ -268,8 +301,13 @@ def test_energy_history_1000_steps(frame):
                 eo = oracle.energies(c.box, c.E, c.B, c.J, c.sp)
                 hist_g.append((eg, info.kinetic_energy))
                 hist_o.append((eo[0:6].sum(), eo[6]))
+                bc_g.append(list(info.field_energy_B))
+                bc_o.append(list(eo[3:6]))
                 assert int(info.n_particles[0] + info.n_particles[1]) == int(eo[10])
         hg, ho = np.array(hist_g), np.array(hist_o)
         assert np.all(np.abs(hg - ho) <= 0.01 * np.abs(ho)), (frame, np.abs(hg - ho) / np.abs(ho))
+        bg, bo = np.array(bc_g), np.array(bc_o)
+        tot = bo.sum(axis=1, keepdims=True)
+        assert np.all(np.abs(bg - bo) <= 0.01 * tot), (frame, np.abs(bg - bo) / tot)
     finally:
         c.close()

@@ -68,16 +68,25 @@ def make_box(w, seed, device="cuda"):
 
 
 def algorithmic_bytes(w, nparticles):
-    """Bytes the fused gather/push/deposit must move per launch: particle state read + write
-    (int32 cell + dim FP32 offsets + 3 FP32 momenta: 28 B each way in 3D, 24 B in 2D; the
-    uint32 id each way where ids are carried, as in the leaky box), the sort permutation
-    (4 B), the six field components read once (24 B/cell) and the current read-modify-write
-    (24 B/cell)."""
+    """Bytes the method must move per launch of the fused gather/push/deposit: the particle
+    state read and written (int32 cell + dim FP32 offsets + 3 FP32 momenta: 28 B each way in
+    3D, 24 B in 2D), the leaky box's particle id read for its Philox counter (4 B) and, in the
+    displacement mode, the tracked in-plane displacement read and written (2 x 8 B); per cell
+    the six field components read once (24 B) and the current read and written (24 B)."""
     ncell = math.prod(w["n"])
-    state = 4 + 4 * w["dim"] + 12 + (4 if w["kind"] == "leaky" else 0)
+    per = 2 * (4 + 4 * w["dim"] + 12)
+    if w["kind"] == "leaky":
+        per += 4
     if w.get("escape") == "displacement":
-        state += 4 * DR_COMPONENTS  # the tracked displacement of the escape test (Sec. 4.1)
-    return nparticles * (2 * state + 4) + ncell * (24 + 24)
+        per += 2 * 4 * DR_COMPONENTS  # the tracked displacement of the escape test (Sec. 4.1)
+    return nparticles * per + ncell * (24 + 24)
+
+
+def implementation_bytes(w, nparticles):
+    """Traffic of this implementation beyond the algorithmic bytes, per launch: the read of the
+    sort permutation (4 B per particle), and the particle id written in sorted order where ids
+    are carried (4 B)."""
+    return nparticles * (4 + (4 if w["kind"] == "leaky" else 0))
 
 
 def one_step_plain(L, h):
@@ -111,16 +120,30 @@ def frame_params(w):
     return p
 
 
-def cpu_baseline(seconds=12.0):
-    """The FP64 oracle, unchanged, on the host cores: a 32^3 sample of the same workload
-    (same ppc, theta, sigma, shear), stepped until ~seconds have elapsed."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(seconds=12.0, n=64):
+    """The FP64 oracle, unchanged, on the host cores: an n^3 sample of the same workload (same
+    ppc, theta, sigma, shear), one untimed step, then timed steps until ~seconds have elapsed
+    (at least 3)."""
     import numpy as np
 
     import oracle
     from paper_2602_15939_amd import synth
 
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    w = workload_shear3d(n=32)
+    w = workload_shear3d(n=n)
     parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], 99, device="cpu")
     box = oracle.make_box(3, w["n"], dt=w["dt"], frame=oracle.SHEAR, shear_s=w["shear_s"],
                           omega0=w["omega0"], maxwell_iters=w["maxwell_iters"])
@@ -138,16 +161,18 @@ def cpu_baseline(seconds=12.0):
         qm = (-1.0, 1.0)[s]
         sp.append(oracle.SpeciesState(x, y, z, u[0], u[1], u[2], qm, qm * w["q"]))
     npart = sum(len(s.x) for s in sp)
+    oracle.step(box, E, B, J, sp, nthreads=cores)  # warm-up (page faults of the buffers)
     steps, t0 = 0, time.perf_counter()
     while True:
         oracle.step(box, E, B, J, sp, nthreads=cores)
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds or steps >= 200:
+        if (el > seconds and steps >= 3) or steps >= 200:
             break
     return dict(value=npart * steps / el, unit="particle-steps/s", cores=cores, kind="oracle",
-                sample=f"32^3 shearing box, 8 ppc/species ({npart} particles), {steps} full "
-                       f"steps in {el:.1f} s, OpenMP over particles")
+                cpu_model=cpu_model(), threads=cores,
+                sample=f"{n}^3 shearing box of the same recipe, 8 ppc/species ({npart} particles), "
+                       f"1 untimed + {steps} timed full steps in {el:.1f} s, OpenMP over particles")
 
 
 def serve_bench(args):
@@ -345,6 +370,7 @@ def main():
     value = psteps / el
     n_avg = psteps / args.steps  # live particles per timed step (npart without escapes)
     nbytes = algorithmic_bytes(w, n_avg)
+    ibytes = implementation_bytes(w, n_avg)
     achieved = nbytes / (gpd_ms * 1e-3) / 1e9
     traffic = measured_traffic(w["name"])
     out = {
@@ -366,7 +392,8 @@ def main():
                              "leaky": "leaky box"}[w["kind"]],
                    **frame_params(w),
                    "gpd_ms": gpd_ms, "gpd_particle_steps_per_s": n_avg / (gpd_ms * 1e-3),
-                   "gpd_algorithmic_bytes": nbytes, "slow_path_particles": int(info.n_slow),
+                   "gpd_algorithmic_bytes": nbytes, "gpd_implementation_bytes": ibytes,
+                   "slow_path_particles": int(info.n_slow),
                    "kernel_source_hash": kernel_source_hash(), "settle_steps": args.settle,
                    "sort": "serial" if args.serial_sort else "overlapped",
                    "autotune": tuned},

@@ -22,3 +22,28 @@ def test_traffic_record_is_keyed_by_the_fused_kernel_sources():
     assert "paper_2602_15939_amd/csrc/gpd.hip" in bench.GPD_SOURCES
     h = bench.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_algorithmic_bytes_follow_the_method_not_the_implementation():
+    """56 B per particle (16 B position + 12 B momentum, read and written) and 48 B per cell for
+    the 3D boxes; the sort permutation read is implementation traffic, reported apart."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    w = bench.workload_shear3d(n=256)
+    n = 268_435_456
+    assert bench.algorithmic_bytes(w, n) == n * 56 + 256**3 * 48  # 1.584e10 B
+    assert bench.implementation_bytes(w, n) == n * 4
+    from paper_2602_15939_amd import workloads
+
+    leaky = workloads.WORKLOADS["leaky2d"]()
+    assert bench.algorithmic_bytes(leaky, 1) == 48 + 4 + 2048**2 * 48
+    paper = workloads.WORKLOADS["leaky2d_paper"]()
+    assert bench.algorithmic_bytes(paper, 1) == 48 + 4 + 16 + 2048**2 * 48
+
+
+def test_cpu_model_is_named():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert bench.cpu_model() and bench.cpu_model() != "unknown"

@@ -10,9 +10,12 @@
  *   - return value: PIC_OK (0) or a negative pic_status; nothing throws or aborts;
  *   - all device work is asynchronous on the box stream (desc.stream, a hipStream_t;
  *     NULL = the null stream) unless the call says it synchronises;
- *   - a box owns its device memory (allocated in pic_box_create, freed in
- *     pic_box_destroy).  Pointers passed in or out are caller-owned; a pointer argument
- *     named *_dev must be device memory, *_host host memory;
+ *   - device memory: a box is created either on caller-owned memory (pic_box_mem: the
+ *     particle arrays, the field and current arrays and one workspace block, e.g. torch
+ *     tensors; the library then never allocates for that box) or, with no pic_box_mem, on
+ *     memory the library allocates and frees with the box.  Other pointers passed in or out
+ *     are caller-owned; a pointer argument named *_dev must be device memory, *_host host
+ *     memory;
  *   - handles are not thread-safe; calls on one box must not overlap;
  *   - fields are stored as the frame's evolved variables: E' and B for the shearing box
  *     (Sec. 2.1), lab-frame E and B at the primed coordinates for the expanding box
@@ -78,6 +81,12 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
                                 displacement is the one the deposit uses: comoving (x' - x^n,
                                 relative to the shear flow) or primed (expanding box); ids are
                                 carried.  Implied by PIC_FRAME_LEAKY */
+#define PIC_BOX_UNFUSED 8u   /* reserve at creation the record of unfused pushes (28 B per
+                                particle of capacity: old position and deposit displacement) that
+                                pic_gather_push without PIC_FUSE_DEPOSIT, pic_deposit and
+                                pic_get_push_record use.  A box on caller memory needs it for
+                                them (PIC_ESTATE otherwise); a library-owned box without it
+                                allocates the record on the first unfused push */
 
 /* sticky device error bits (pic_box_info.errors) */
 #define PIC_DERR_CFL 1u      /* a deposit displacement reached half a cell, or (shearing box)
@@ -129,6 +138,62 @@ typedef struct pic_box_desc {
 } pic_box_desc;
 
 typedef struct pic_box pic_box;
+typedef struct pic_batch pic_batch;
+
+/* Sizes of the caller-owned memory of a box (pic_box_layout).  Field and current arrays are
+   guarded: a component array holds pitch_z * field_planes floats, the interior point (i,j,k)
+   at (32 + i) + pitch_y (2 + j) + pitch_z (2 + k) (k term 0 in 2D: no z guards), with
+   pitch_y >= field_pitch_min[0] and pitch_z >= pitch_y * (n[1] + 4), both multiples of 32 (the
+   interior x = 0 of every row starts a 128-byte line).  Particle arrays are dense, one
+   element per slot. */
+typedef struct pic_box_layout_info {
+    int64_t workspace_bytes;    /* the workspace block (sort buffers, tile offsets, counters,
+                                   reductions, reinjection table, the unfused record with
+                                   PIC_BOX_UNFUSED) */
+    int32_t field_sets;         /* field sets: 3 for the shearing box (F^n and the fixed-point
+                                   iterates of Sec. 2.2), 1 otherwise */
+    int32_t current_arrays;     /* current arrays per component: 2 for the shearing box (the
+                                   J' transport of Sec. 2.2 writes the second), 1 otherwise */
+    int32_t field_pitch_min[2]; /* smallest pitch_y, pitch_z (elements) */
+    int32_t field_rows;         /* (n[1] + 4) * field_planes */
+    int32_t field_planes;       /* n[2] + 4 in 3D, 1 in 2D */
+    int64_t field_elems_min;    /* floats per field or current array at the smallest pitches */
+    int64_t particle_elems[2];  /* elements per particle array of each species: capacity + 1 */
+    int32_t has_id;             /* the id arrays are needed (ids carried) */
+    int32_t has_dr;             /* the displacement arrays are needed (displacement escape) */
+} pic_box_layout_info;
+
+/* Caller-owned device memory of a box (pic_box_create).  Every pointer is device memory,
+   256-byte aligned, and must outlive the box; the library reads and writes it on the box
+   stream only.  Unused entries (sets beyond field_sets, the second current array outside the
+   shearing box, species beyond n_species, off[..][..][2] in 2D, id and dr where the layout does
+   not need them) are ignored. */
+typedef struct pic_box_mem {
+    float* field[3][6];          /* field set s: Bx By Bz Ex Ey Ez (the frame's evolved
+                                    variables); pic_box_info.field_set names the set holding the
+                                    fields after each step */
+    float* current[2][3];        /* Jx Jy Jz; pic_box_info.current_array names the one holding the
+                                    current of the last step */
+    int32_t field_pitch[2];      /* pitch_y, pitch_z of every field and current array (0, 0: the
+                                    smallest) */
+    int32_t* cell[2][2];         /* [species][copy]: the two copies alternate between pushes */
+    float* off[2][2][3];         /* [species][copy][axis], axis < dim */
+    float* u[2][2][3];
+    uint32_t* id[2][2];
+    float* dr[2][2][3];
+    void* workspace;             /* pic_box_layout_info.workspace_bytes or more */
+    int64_t workspace_bytes;
+} pic_box_mem;
+
+/* The sizes a box of this descriptor needs on caller memory.  Host only (no device call).
+   PIC_EINVAL for a descriptor pic_box_create would reject. */
+int32_t pic_box_layout(const pic_box_desc* desc, pic_box_layout_info* out);
+/* The workspace part of pic_box_layout. */
+int32_t pic_workspace_bytes(const pic_box_desc* desc, int64_t* bytes);
+/* Device and pinned host bytes the library currently holds: library-owned boxes, their
+   unfused records and the batched-step staging of pic_step.  Boxes on caller memory and
+   pic_batch objects add nothing. */
+int32_t pic_allocated_bytes(int64_t* device_bytes, int64_t* host_bytes);
 
 typedef struct pic_box_info {
     int64_t step;            /* steps taken */
@@ -159,15 +224,25 @@ typedef struct pic_box_info {
                                   velocity u'/gamma' + v_s, v_s at the midpoint x of the move,
                                   exceeded c (eq. OAx; Sec. 2.1 leaves the correction to other
                                   work: counted, not corrected) */
+    int32_t field_set;         /* the field set (pic_box_mem.field[s]) holding the fields */
+    int32_t current_array;     /* the current array (pic_box_mem.current[a]) holding the current
+                                  of the last step */
+    int32_t particle_copy[2];  /* per species, the particle copy (pic_box_mem.cell[s][k], ...)
+                                  holding the particles, in slot order */
 } pic_box_info;
 
-/* Create a box.  Validates the descriptor (PIC_EINVAL), allocates the grid with guard
-   cells, the ping-pong particle arrays of the given capacities and the sort workspace in one
-   device allocation (PIC_ENOMEM).  Fields start at zero (cleared on the box stream) and the
-   box holds no particles.  *out is set only on success. */
-int32_t pic_box_create(const pic_box_desc* desc, pic_box** out);
+/* Create a box (the state of Secs. 2.1, 3.1, 4.1: fields on the Yee grid, particles of up to
+   two species).  mem != NULL: the box lives in the caller's buffers (pic_box_mem, sized by
+   pic_box_layout) and the library never allocates device or host memory for it; PIC_EINVAL
+   for a missing or misaligned buffer or a bad pitch, PIC_ENOMEM for a workspace below
+   pic_workspace_bytes.  mem == NULL: the library allocates the same buffers in one device
+   allocation (PIC_ENOMEM if it fails).  Validates the descriptor (PIC_EINVAL: unsupported
+   combination, CFL, capacity).  Fields and currents start at zero (cleared on the box stream)
+   and the box holds no particles.  *out is set only on success. */
+int32_t pic_box_create(const pic_box_desc* desc, const pic_box_mem* mem, pic_box** out);
 
-/* Free the box and its device memory (synchronises the box stream).  NULL is accepted. */
+/* Free the box and the memory the library allocated for it (synchronises the box stream);
+   caller-owned buffers are untouched.  NULL is accepted. */
 int32_t pic_box_destroy(pic_box* box);
 
 /* Copy fields in or out: E_dev/B_dev/J_dev hold 3 component arrays of n0*n1*n2 floats.
@@ -287,8 +362,27 @@ int32_t pic_escape_compact(pic_box* const* boxes, int32_t nb, uint32_t flags);
    stream) and replayed on later steps of the same box set with the same launch shapes: the
    graph's copy node reads the tables the host has just written, so every replay runs that
    step's arguments.  The first box holds up to 8 graphs (least recently used evicted); they are
-   freed with it.  Results are identical to the batched step without graphs. */
+   freed with it.  Results are identical to the batched step without graphs.  The first box
+   stages the tables in memory the library allocates for it, so it must be a library-owned box
+   (PIC_EINVAL for a box on caller memory: step those with pic_step_batch). */
 int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags);
+
+/* A batched step's staging on caller-owned memory: dev (device) and host (pinned host, e.g. a
+   torch pin_memory tensor) of `bytes` each, 256-byte aligned; each holds two halves that
+   alternate between steps, so one step's argument tables may take up to bytes/2
+   (pic_step_table_bytes).  `stream` (a hipStream_t) is the stream of the boxes it steps.  The
+   batch also keeps the HIP graphs of PIC_STEP_GRAPH (freed with it).  It allocates no memory.
+   PIC_EINVAL for NULL or misaligned pointers or bytes below 2 x 4096. */
+int32_t pic_batch_create(void* dev, void* host, int64_t bytes, void* stream, pic_batch** out);
+int32_t pic_batch_destroy(pic_batch* batch); /* synchronises the stream; NULL accepted */
+/* pic_step with PIC_STEP_BATCHED (flags may add PIC_STEP_GRAPH) whose argument tables are
+   staged in the batch's buffers: the batched step for boxes on caller memory.  PIC_ENOMEM (and
+   nothing stepped) if the tables exceed half the staging; PIC_EINVAL if the boxes do not use
+   the batch's stream. */
+int32_t pic_step_batch(pic_batch* batch, pic_box* const* boxes, int32_t nb, uint32_t flags);
+/* Bytes of argument tables the next batched step of these boxes takes (host only: nothing is
+   queued and the boxes are unchanged). */
+int32_t pic_step_table_bytes(pic_box* const* boxes, int32_t nb, int64_t* bytes);
 
 /* Synchronise the box stream and report time, counts, errors and (FP64) reductions. */
 int32_t pic_box_get(pic_box* box, pic_box_info* info);

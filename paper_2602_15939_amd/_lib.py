@@ -19,6 +19,7 @@ REMAP_FIELDS, REMAP_CURRENT = 1, 2
 BOX_TRACK_IDS = 1
 BOX_COUNT_SUPERLUMINAL = 2
 BOX_ESCAPE = 4
+BOX_UNFUSED = 8
 SORT_OVERLAP = 1
 DERR_CFL, DERR_NAN, DERR_ORDER, DERR_CELL, DERR_SORT, DERR_NOCONVERGE = 1, 2, 4, 8, 16, 32
 STEP_BATCHED = 1
@@ -51,6 +52,27 @@ class pic_box_info(C.Structure):
         ("momentum", C.c_double * 3),
         ("n_sort_migrations", C.c_int64), ("n_sort_fallbacks", C.c_int64), ("maxwell_sweeps", C.c_int32),
         ("pressure", C.c_double * 3), ("n_superluminal", C.c_int64),
+        ("field_set", C.c_int32), ("current_array", C.c_int32), ("particle_copy", C.c_int32 * 2),
+    ]
+
+
+class pic_box_layout_info(C.Structure):
+    _fields_ = [
+        ("workspace_bytes", C.c_int64), ("field_sets", C.c_int32), ("current_arrays", C.c_int32),
+        ("field_pitch_min", C.c_int32 * 2), ("field_rows", C.c_int32), ("field_planes", C.c_int32),
+        ("field_elems_min", C.c_int64), ("particle_elems", C.c_int64 * 2), ("has_id", C.c_int32),
+        ("has_dr", C.c_int32),
+    ]
+
+
+class pic_box_mem(C.Structure):
+    _fields_ = [
+        ("field", (C.c_void_p * 6) * 3), ("current", (C.c_void_p * 3) * 2),
+        ("field_pitch", C.c_int32 * 2),
+        ("cell", (C.c_void_p * 2) * 2), ("off", ((C.c_void_p * 3) * 2) * 2),
+        ("u", ((C.c_void_p * 3) * 2) * 2), ("id", (C.c_void_p * 2) * 2),
+        ("dr", ((C.c_void_p * 3) * 2) * 2),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
     ]
 
 
@@ -71,7 +93,14 @@ def lib():
         vp, i32, u32, i64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_int64
         boxes = C.POINTER(C.c_void_p)
         sig = {
-            "pic_box_create": ([C.POINTER(pic_box_desc), C.POINTER(C.c_void_p)], i32),
+            "pic_box_create": ([C.POINTER(pic_box_desc), C.POINTER(pic_box_mem), C.POINTER(C.c_void_p)], i32),
+            "pic_box_layout": ([C.POINTER(pic_box_desc), C.POINTER(pic_box_layout_info)], i32),
+            "pic_workspace_bytes": ([C.POINTER(pic_box_desc), C.POINTER(i64)], i32),
+            "pic_allocated_bytes": ([C.POINTER(i64), C.POINTER(i64)], i32),
+            "pic_batch_create": ([vp, vp, i64, vp, C.POINTER(C.c_void_p)], i32),
+            "pic_batch_destroy": ([vp], i32),
+            "pic_step_batch": ([vp, boxes, i32, u32], i32),
+            "pic_step_table_bytes": ([boxes, i32, C.POINTER(i64)], i32),
             "pic_box_destroy": ([vp], i32),
             "pic_set_fields": ([vp, vp, vp], i32),
             "pic_get_fields": ([vp, vp, vp], i32),
@@ -139,10 +168,56 @@ def pic_device_copy(dst_ptr, src_ptr, nbytes, stream_ptr=None):
     check(lib().pic_device_copy(dst_ptr, src_ptr, nbytes, stream_ptr), "pic_device_copy")
 
 
-def pic_box_create(desc: pic_box_desc) -> int:
+def pic_box_create(desc: pic_box_desc, mem: pic_box_mem | None = None) -> int:
+    """mem: caller-owned buffers (pic_box_mem), or None for library-allocated memory."""
     h = C.c_void_p()
-    check(lib().pic_box_create(C.byref(desc), C.byref(h)), "pic_box_create")
+    check(lib().pic_box_create(C.byref(desc), C.byref(mem) if mem is not None else None, C.byref(h)),
+          "pic_box_create")
     return h.value
+
+
+def pic_box_layout(desc: pic_box_desc) -> pic_box_layout_info:
+    out = pic_box_layout_info()
+    check(lib().pic_box_layout(C.byref(desc), C.byref(out)), "pic_box_layout")
+    return out
+
+
+def pic_workspace_bytes(desc: pic_box_desc) -> int:
+    v = C.c_int64()
+    check(lib().pic_workspace_bytes(C.byref(desc), C.byref(v)), "pic_workspace_bytes")
+    return v.value
+
+
+def pic_allocated_bytes():
+    """(device, pinned host) bytes the library holds."""
+    d, h = C.c_int64(), C.c_int64()
+    check(lib().pic_allocated_bytes(C.byref(d), C.byref(h)), "pic_allocated_bytes")
+    return d.value, h.value
+
+
+def pic_batch_create(dev_ptr, host_ptr, nbytes, stream_ptr) -> int:
+    h = C.c_void_p()
+    check(lib().pic_batch_create(dev_ptr, host_ptr, nbytes, stream_ptr, C.byref(h)), "pic_batch_create")
+    return h.value
+
+
+def pic_batch_destroy(h) -> None:
+    check(lib().pic_batch_destroy(h), "pic_batch_destroy")
+
+
+def pic_step_batch(batch, handles, flags=0):
+    p, keep = box_array(handles)
+    rc = lib().pic_step_batch(batch, p, len(handles), flags)
+    del keep
+    return rc
+
+
+def pic_step_table_bytes(handles) -> int:
+    p, keep = box_array(handles)
+    v = C.c_int64()
+    check(lib().pic_step_table_bytes(p, len(handles), C.byref(v)), "pic_step_table_bytes")
+    del keep
+    return v.value
 
 
 def pic_box_destroy(h) -> None:

@@ -45,7 +45,76 @@ struct Species {
     double qm = 0, q = 0;
 };
 
+// Staging of the descriptor tables of batched steps (two buffers, alternating) and the
+// executable graphs captured over them.  A library-owned box grows its own on demand; a
+// caller-owned one (pic_batch) has fixed buffers the caller allocated.
+struct Stager {
+    struct Buf {
+        void* host = nullptr;  // pinned
+        void* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t copied = nullptr;  // the last transfer out of host has completed
+    } buf[2];
+    int cur = 0;
+    bool caller = false;  // buffers owned by the caller: never reallocated
+    // executable graphs keyed by the box set, the staging buffer and the launch sequence (grid
+    // sizes and table offsets); least recently used last
+    struct StepGraph {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<StepGraph> graphs;
+};
+
+// Device and pinned host memory the library holds (library-owned boxes, their unfused-deposit
+// workspaces and batched-step staging); a box created on caller memory adds nothing.
+std::atomic<int64_t> g_dev_bytes{0}, g_host_bytes{0};
+
+hipError_t lib_malloc(void** p, size_t bytes)
+{
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) g_dev_bytes += (int64_t)bytes;
+    return e;
+}
+void lib_free(void* p, size_t bytes)
+{
+    if (!p) return;
+    hipFree(p);
+    g_dev_bytes -= (int64_t)bytes;
+}
+hipError_t lib_host_malloc(void** p, size_t bytes)
+{
+    const hipError_t e = hipHostMalloc(p, bytes);
+    if (e == hipSuccess) g_host_bytes += (int64_t)bytes;
+    return e;
+}
+void lib_host_free(void* p, size_t bytes)
+{
+    if (!p) return;
+    hipHostFree(p);
+    g_host_bytes -= (int64_t)bytes;
+}
+
+void stager_release(Stager& sg)
+{
+    for (auto& g : sg.graphs) hipGraphExecDestroy(g.exec);
+    sg.graphs.clear();
+    for (auto& b : sg.buf) {
+        if (!sg.caller) {
+            lib_host_free(b.host, b.cap);
+            lib_free(b.dev, b.cap);
+        }
+        if (b.copied) hipEventDestroy(b.copied);
+        b = Stager::Buf{};
+    }
+}
+
 }  // namespace
+
+struct pic_batch {
+    Stager sg;
+    hipStream_t st = nullptr;
+};
 
 struct pic_box {
     pic_box_desc d{};
@@ -69,6 +138,7 @@ struct pic_box {
     int cur_set = 0;
     float* J[3] = {};
     float* Jt[3] = {};
+    float* J0 = nullptr;  // interior pointer of the first current array's x component
     float* mj = nullptr;
     uint32_t* err = nullptr;
     unsigned long long* ctr = nullptr;
@@ -80,21 +150,9 @@ struct pic_box {
     unsigned long long* hist_counts = nullptr;  // ... and counts
     int64_t step = 0;
     int64_t n_migrations = 0;
-    // staging of the descriptor tables of batched steps led by this box (two, alternating)
-    struct Staging {
-        void* host = nullptr;  // pinned
-        void* dev = nullptr;
-        size_t cap = 0;
-        hipEvent_t copied = nullptr;  // the last transfer out of host has completed
-    } stage[2];
-    int stage_cur = 0;
-    // executable graphs of batched steps led by this box, keyed by the box set, the staging
-    // buffer and the launch sequence (grid sizes and table offsets); least recently used last
-    struct StepGraph {
-        std::vector<uint64_t> key;
-        hipGraphExec_t exec = nullptr;
-    };
-    std::vector<StepGraph> graphs;
+    // staging and graphs of batched steps led by this box through pic_step (library-owned
+    // boxes only; boxes on caller memory step in batches through pic_step_batch)
+    Stager stager;
     uint64_t uid = 0;  // unique over the process lifetime (graph keys)
     bool sorted = false;
     bool deposit_pending = false;
@@ -105,9 +163,11 @@ struct pic_box {
     hipEvent_t fork_ev = nullptr, side_ev = nullptr;
     bool side_pending = false;
     bool track_ids = false;
-    std::vector<void*> allocs;
+    bool caller_mem = false;  // created on caller memory (pic_box_mem): never allocates
+    std::vector<std::pair<void*, size_t>> allocs;
     // pic_box_create takes all of the box's device memory in one allocation: a first pass over
-    // the buffer list measures it, a second carves it
+    // the buffer list measures it, a second carves it (from the library's allocation, or from
+    // the caller's workspace)
     int alloc_pass = 0;  // 0: separate allocations, 1: measuring, 2: carving
     char* arena = nullptr;
     size_t arena_off = 0;
@@ -152,9 +212,10 @@ int32_t dalloc(pic_box* b, T*& p, size_t count)
         b->arena_off += bytes;
         return PIC_OK;
     }
+    if (b->caller_mem) return PIC_ESTATE;  // a box on caller memory never allocates
     void* q = nullptr;
-    if (hipMalloc(&q, bytes) != hipSuccess) return PIC_ENOMEM;
-    b->allocs.push_back(q);
+    if (lib_malloc(&q, bytes) != hipSuccess) return PIC_ENOMEM;
+    b->allocs.push_back({q, bytes});
     p = static_cast<T*>(q);
     return PIC_OK;
 }
@@ -734,7 +795,71 @@ void plan_fill(std::vector<FillArgs>& a, std::vector<uint32_t>& blk, const GridD
     }
 }
 
-int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
+// The host-side state a batched step advances, per box: saved before planning so that a step
+// whose tables do not fit caller-owned staging (or a dry run that only measures the tables)
+// leaves every box as it was.
+struct BoxState {
+    bool sorted, deposit_pending, record_valid;
+    int64_t step, n_migrations;
+    int cur_set, last_sweeps;
+    float* J[3];
+    float* Jt[3];
+    MigGeo mg;  // the y shifts of the last push's face crossings, read by the next sort
+    struct Sp {
+        int cur, toff_cur, which, n_upper;
+        bool grouped, counts_ready;
+    } sp[kMaxSpecies];
+};
+BoxState save_state(const pic_box* b)
+{
+    BoxState v{};
+    v.sorted = b->sorted;
+    v.deposit_pending = b->deposit_pending;
+    v.record_valid = b->record_valid;
+    v.step = b->step;
+    v.n_migrations = b->n_migrations;
+    v.cur_set = b->cur_set;
+    v.last_sweeps = b->last_sweeps;
+    v.mg = b->mg;
+    for (int c = 0; c < 3; c++) {
+        v.J[c] = b->J[c];
+        v.Jt[c] = b->Jt[c];
+    }
+    for (int s = 0; s < b->nsp; s++) {
+        const Species& S = b->sp[s];
+        v.sp[s] = BoxState::Sp{S.cur, S.toff_cur, S.which, S.n_upper, S.grouped, S.counts_ready};
+    }
+    return v;
+}
+void restore_state(pic_box* b, const BoxState& v)
+{
+    b->sorted = v.sorted;
+    b->deposit_pending = v.deposit_pending;
+    b->record_valid = v.record_valid;
+    b->step = v.step;
+    b->n_migrations = v.n_migrations;
+    b->cur_set = v.cur_set;
+    b->last_sweeps = v.last_sweeps;
+    b->mg = v.mg;
+    for (int c = 0; c < 3; c++) {
+        b->J[c] = v.J[c];
+        b->Jt[c] = v.Jt[c];
+    }
+    for (int s = 0; s < b->nsp; s++) {
+        Species& S = b->sp[s];
+        S.cur = v.sp[s].cur;
+        S.toff_cur = v.sp[s].toff_cur;
+        S.which = v.sp[s].which;
+        S.n_upper = v.sp[s].n_upper;
+        S.grouped = v.sp[s].grouped;
+        S.counts_ready = v.sp[s].counts_ready;
+    }
+}
+
+// One batched step of the boxes, its tables staged in sg.  dry: only measure the tables
+// (*table_bytes), queue nothing and leave the boxes as they were.
+int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, bool dry,
+                     size_t* table_bytes)
 {
     hipStream_t st = boxes[0]->st;
     for (int i = 0; i < nb; i++) {
@@ -746,6 +871,12 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
     }
     BatchPlan plan;
     plan.st = st;
+    std::vector<BoxState> saved(nb);
+    for (int i = 0; i < nb; i++) saved[i] = save_state(boxes[i]);
+    auto undo = [&](int32_t r) {
+        for (int i = 0; i < nb; i++) restore_state(boxes[i], saved[i]);
+        return r;
+    };
 
     // ---- a1: tile sort (migration sort in the batch; radix per box where it does not apply)
     {
@@ -796,9 +927,16 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
             b->sorted = true;
         }
         // boxes the migration sort does not apply to are sorted now, on their own launches,
-        // ahead of the batch on the shared stream
-        for (int i : radix_boxes)
-            if (sort_box(boxes[i])) return PIC_EDEVICE;
+        // ahead of the batch on the shared stream (a dry run only marks them sorted)
+        for (int i : radix_boxes) {
+            if (dry) {
+                boxes[i]->sorted = true;
+                for (int s = 0; s < boxes[i]->nsp; s++)
+                    boxes[i]->sp[s].grouped = boxes[i]->sp[s].counts_ready = false;
+                continue;
+            }
+            if (sort_box(boxes[i])) return undo(PIC_EDEVICE);
+        }
         plan.grid(kBatchZero, zf, zfb, 1);
         plan.sort(kBatchMigCount, mc, mcb);
         plan.sort(kBatchMigOffsets, mo, mob);
@@ -1028,29 +1166,37 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
     }
 
     // ---- stage the tables, one transfer, then the launches in order
-    pic_box* b0 = boxes[0];
-    const int sidx = b0->stage_cur;
-    auto& sg = b0->stage[sidx];
-    b0->stage_cur ^= 1;
     const size_t bytes = plan.buf.size();
+    if (dry) {
+        *table_bytes = bytes;
+        return undo(PIC_OK);
+    }
+    const int sidx = sg_all.cur;
+    auto& sg = sg_all.buf[sidx];
     if (bytes > sg.cap) {
+        if (sg_all.caller) return undo(PIC_ENOMEM);  // caller-owned staging is never grown
         if (sg.copied && hipEventSynchronize(sg.copied) != hipSuccess) return PIC_EDEVICE;
         if (hipStreamSynchronize(st) != hipSuccess) return PIC_EDEVICE;  // the old tables may be in use
-        if (sg.host) hipHostFree(sg.host);
-        if (sg.dev) hipFree(sg.dev);
+        lib_host_free(sg.host, sg.cap);
+        lib_free(sg.dev, sg.cap);
         sg.host = sg.dev = nullptr;
-        for (auto& g : b0->graphs) hipGraphExecDestroy(g.exec);  // they read the old buffer
-        b0->graphs.clear();
+        for (auto& g : sg_all.graphs) hipGraphExecDestroy(g.exec);  // they read the old buffer
+        sg_all.graphs.clear();
         sg.cap = 0;
         const size_t cap = std::max(bytes * 2, (size_t)1 << 20);
-        if (hipHostMalloc(&sg.host, cap) != hipSuccess) return PIC_ENOMEM;
-        if (hipMalloc(&sg.dev, cap) != hipSuccess) return PIC_ENOMEM;
+        if (lib_host_malloc(&sg.host, cap) != hipSuccess) return PIC_ENOMEM;
+        if (lib_malloc(&sg.dev, cap) != hipSuccess) {
+            lib_host_free(sg.host, cap);
+            sg.host = nullptr;
+            return PIC_ENOMEM;
+        }
         sg.cap = cap;
-        if (!sg.copied && hipEventCreateWithFlags(&sg.copied, hipEventDisableTiming) != hipSuccess)
-            return PIC_EDEVICE;
     } else if (sg.copied && hipEventSynchronize(sg.copied) != hipSuccess) {
         return PIC_EDEVICE;
     }
+    if (!sg.copied && hipEventCreateWithFlags(&sg.copied, hipEventDisableTiming) != hipSuccess)
+        return PIC_EDEVICE;
+    sg_all.cur ^= 1;
     if (bytes) std::memcpy(sg.host, plan.buf.data(), bytes);
     const char* dev = static_cast<const char*>(sg.dev);
     auto enqueue = [&]() -> int32_t {
@@ -1075,7 +1221,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
     key.push_back((uint64_t)bytes);
     for (int i = 0; i < nb; i++) key.push_back(boxes[i]->uid);
     key.insert(key.end(), plan.sig.begin(), plan.sig.end());
-    auto& cache = b0->graphs;
+    auto& cache = sg_all.graphs;
     size_t hit = cache.size();
     for (size_t i = 0; i < cache.size(); i++)
         if (cache[i].key == key) {
@@ -1100,7 +1246,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
             hipGraphExecDestroy(cache.back().exec);
             cache.pop_back();
         }
-        cache.insert(cache.begin(), pic_box::StepGraph{std::move(key), ex});
+        cache.insert(cache.begin(), Stager::StepGraph{std::move(key), ex});
         hit = 0;
     } else if (hit != 0) {
         std::rotate(cache.begin(), cache.begin() + hit, cache.begin() + hit + 1);
@@ -1109,6 +1255,204 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph)
     if (hipGraphLaunch(cache[hit].exec, st) != hipSuccess) return PIC_EDEVICE;
     if (hipEventRecord(sg.copied, st) != hipSuccess) return PIC_EDEVICE;
     return PIC_OK;
+}
+
+// Validate the descriptor and set a new box's geometry (no device work).  pitch[2]: element
+// strides of the guarded field arrays along y and z, or 0 for the smallest valid ones.
+int32_t init_box(const pic_box_desc* d, const int32_t pitch[2], pic_box*& out)
+{
+    out = nullptr;
+    if (!d) return PIC_EINVAL;
+    if (d->dim != 2 && d->dim != 3) return PIC_EINVAL;
+    int n[3] = {d->n[0], d->n[1], d->dim == 3 ? d->n[2] : 1};
+    if (d->dim == 2 && d->n[2] != 1 && d->n[2] != 0) return PIC_EINVAL;
+    for (int k = 0; k < d->dim; k++)
+        if (n[k] < 4) return PIC_EINVAL;
+    if (!(d->dt > 0) || d->dt * std::sqrt((double)d->dim) >= 1.0) return PIC_EINVAL;
+    if (d->frame < 0 || d->frame > 3) return PIC_EINVAL;
+    if (d->n_species < 1 || d->n_species > 2) return PIC_EINVAL;
+    if (d->maxwell_iters < 0 || d->maxwell_iters > kKsbMaxSweeps || !(d->maxwell_tol >= 0.0) ||
+        !(d->maxwell_tol < 1.0))
+        return PIC_EINVAL;
+    if (escapes(d)) {
+        if (d->leaky_mode == PIC_LEAKY_DISPLACEMENT && !(d->leaky_l_esc > 0 && d->leaky_theta_inj > 0))
+            return PIC_EINVAL;
+        if (d->leaky_mode == PIC_LEAKY_PROBABILISTIC && !(d->leaky_t_esc > 0)) return PIC_EINVAL;
+        if (d->leaky_mode != 0 && d->leaky_mode != 1) return PIC_EINVAL;
+    }
+    int tile[3];
+    for (int k = 0; k < 3; k++) tile[k] = d->tile[k];
+    if (tile[0] == 0) {
+        tile[0] = tile[1] = d->dim == 3 ? 8 : 16;
+        tile[2] = d->dim == 3 ? 8 : 1;
+    }
+    if (d->dim == 2) tile[2] = 1;
+    if (!tile_shape_supported(d->dim, tile)) return PIC_EINVAL;
+    int bits[3];
+    for (int k = 0; k < 3; k++) bits[k] = ceil_log2(n[k]);
+    if (bits[0] + bits[1] + bits[2] > 31) return PIC_EINVAL;
+    for (int s = 0; s < d->n_species; s++)
+        if (d->capacity[s] < 0 || d->capacity[s] >= (1ll << 30)) return PIC_EINVAL;  // 32-bit byte offsets
+    // field rows of kRowAlign floats: interior x = 0 starts a 128-byte line in every row (the x
+    // guards sit in the padding before and after the interior)
+    const int g = kGuard, gz = d->dim == 3 ? kGuard : 0;
+    const int NYg = n[1] + 2 * g, NZg = n[2] + 2 * gz;
+    const int64_t sy_min = (int64_t)(kRowAlign + n[0] + g + kRowAlign - 1) / kRowAlign * kRowAlign;
+    int64_t sy = sy_min, sz = sy_min * NYg;
+    if (pitch && (pitch[0] || pitch[1])) {
+        sy = pitch[0];
+        sz = pitch[1];
+        if (sy < sy_min || sy % kRowAlign || sz < sy * NYg || sz % kRowAlign) return PIC_EINVAL;
+    }
+    if (sz * NZg >= (1ll << 31)) return PIC_EINVAL;
+
+    pic_box* b = new (std::nothrow) pic_box();
+    if (!b) return PIC_ENOMEM;
+    static std::atomic<uint64_t> next_uid{0};
+    b->uid = ++next_uid;
+    b->d = *d;
+    b->st = static_cast<hipStream_t>(d->stream);
+    b->dim = d->dim;
+    for (int k = 0; k < 3; k++) b->n[k] = n[k];
+    b->cc.b0 = bits[0];
+    b->cc.b1 = bits[1];
+    b->cc.m0 = (1u << bits[0]) - 1u;
+    b->cc.m1 = (1u << bits[1]) - 1u;
+    set_tiling(b, tile);
+    GridDev& G = b->G;
+    G.dim = b->dim;
+    G.div0 = FastDiv::make((uint32_t)n[0]);
+    G.div1 = FastDiv::make((uint32_t)n[1]);
+    for (int k = 0; k < 3; k++) {
+        G.n[k] = n[k];
+        G.g[k] = (k < b->dim) ? kGuard : 0;
+    }
+    G.divyg = FastDiv::make((uint32_t)NYg);
+    G.sy = (int)sy;
+    G.sz = (int)sz;
+    b->comp_elems = sz * NZg;
+    b->origin = (int64_t)kRowAlign + sy * G.g[1] + sz * G.g[2];
+    b->nsp = d->n_species;
+    b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || escapes(d);
+    b->nsets = d->frame == PIC_FRAME_SHEAR ? 3 : 1;
+    out = b;
+    return PIC_OK;
+}
+
+bool unfused_reserved(const pic_box* b) { return (b->d.flags & PIC_BOX_UNFUSED) != 0; }
+
+// The box's buffers.  Fields, currents and particle arrays come from the caller's pic_box_mem
+// when there is one, everything else from the workspace (library allocation or caller block).
+// Measuring pass (alloc_pass 1): only the workspace is counted.
+int32_t alloc_all(pic_box* b, const pic_box_mem* m)
+{
+    const pic_box_desc* d = &b->d;
+    const int tiles_ws = max_tiles(b->dim, b->n);  // any supported tiling fits the workspace
+    int32_t r = PIC_OK;
+    const bool measuring = b->alloc_pass == 1;
+    // a buffer the caller may own: taken from m (checked: non-null, 256-byte aligned) or carved
+    auto caller_buf = [&](auto*& p, auto* given, size_t count) -> int32_t {
+        if (m) {
+            if (measuring) return PIC_OK;
+            if (!given || (reinterpret_cast<uintptr_t>(given) & 255)) return PIC_EINVAL;
+            p = given;
+            return PIC_OK;
+        }
+        return dalloc(b, p, count);
+    };
+    auto field = [&](float*& p, float* given) -> int32_t {
+        float* q = nullptr;
+        int32_t rr = caller_buf(q, given, (size_t)b->comp_elems);
+        if (rr || measuring) return rr;
+        if (hipMemsetAsync(q, 0, sizeof(float) * b->comp_elems, b->st) != hipSuccess) return PIC_EDEVICE;
+        p = q + b->origin;
+        return PIC_OK;
+    };
+    for (int s = 0; s < b->nsets && !r; s++)
+        for (int c = 0; c < 6 && !r; c++) r = field(b->set[s][c], m ? m->field[s][c] : nullptr);
+    for (int c = 0; c < 3 && !r; c++) r = field(b->J[c], m ? m->current[0][c] : nullptr);
+    b->J0 = b->J[0];
+    if (d->frame == PIC_FRAME_SHEAR)
+        for (int c = 0; c < 3 && !r; c++) r = field(b->Jt[c], m ? m->current[1][c] : nullptr);
+    for (int s = 0; s < b->nsp && !r; s++) {
+        Species& S = b->sp[s];
+        S.cap = d->capacity[s];
+        S.qm = d->q_over_m[s];
+        S.q = d->q_macro[s];
+        const size_t cap = (size_t)S.cap + 1;
+        for (int k = 0; k < 2 && !r; k++) {
+            r = caller_buf(S.cell[k], m ? m->cell[s][k] : nullptr, cap);
+            for (int c = 0; c < 3 && !r; c++) {
+                if (c < b->dim)
+                    r = caller_buf(S.off[k][c], m ? m->off[s][k][c] : nullptr, cap);
+                else if (!m)
+                    r = dalloc(b, S.off[k][c], 1);
+            }
+            for (int c = 0; c < 3 && !r; c++) r = caller_buf(S.u[k][c], m ? m->u[s][k][c] : nullptr, cap);
+            if (!r && b->track_ids) r = caller_buf(S.id[k], m ? m->id[s][k] : nullptr, cap);
+            if (escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
+                for (int c = 0; c < 3 && !r; c++) r = caller_buf(S.dr[k][c], m ? m->dr[s][k][c] : nullptr, cap);
+        }
+        for (int k = 0; k < 2 && !r; k++) {
+            r = dalloc(b, S.sb.keys[k], cap);
+            if (!r) r = dalloc(b, S.sb.vals[k], cap);
+        }
+        if (!r) r = dalloc(b, S.sb.hist, sort_hist_words((int64_t)cap));
+        if (!r) r = dalloc(b, S.sb.scratch, scan_scratch_words((int64_t)sort_hist_words((int64_t)cap)));
+        for (int k = 0; k < 2 && !r; k++) r = dalloc(b, S.toff[k], (size_t)tiles_ws + 2);
+        const size_t nt = (size_t)tiles_ws;
+        if (!r) r = dalloc(b, S.sb.mcnt, nt * kMigDirs);
+        if (!r) r = dalloc(b, S.sb.mpre, nt * kMigDirs);
+        if (!r) r = dalloc(b, S.sb.tot, nt + 1);
+        if (!r) r = dalloc(b, S.sb.start, nt + 1);
+        if (!r) r = dalloc(b, S.sb.dcnt, nt + 1);
+        if (!r) r = dalloc(b, S.sb.dpre, nt + 1);
+        if (!r) r = dalloc(b, S.sb.mscratch, migrate_scratch_words(tiles_ws));
+        if (!r) r = dalloc(b, S.sb.fallback, 1);
+        if (!r) r = dalloc(b, S.n_live, 2);
+        // the record of unfused pushes: reserved at creation on request (a box on caller
+        // memory cannot take it later), else taken on first use
+        if (!r && unfused_reserved(b)) {
+            r = dalloc(b, S.ws_cell, cap);
+            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.ws_off[c], cap);
+            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.ws_disp[c], cap);
+        }
+        if (!r && !measuring && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess)
+            r = PIC_EDEVICE;
+    }
+    if (!r) r = dalloc(b, b->err, 4);
+    if (!r) r = dalloc(b, b->ctr, 4);
+    if (!r && d->frame == PIC_FRAME_SHEAR) r = dalloc(b, b->conv, kKsbConvWords);
+    if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
+    if (!r) r = dalloc(b, b->red_out, 16);
+    if (!r) r = dalloc(b, b->hist_edges, kHistMaxBins + 1);
+    if (!r) r = dalloc(b, b->hist_counts, kHistMaxBins + 2);
+    if (!r && escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
+        r = dalloc(b, b->mj, (size_t)kMjBins + kMjTail);
+    if (measuring || r) return r;
+    if (hipMemsetAsync(b->err, 0, 4 * sizeof(uint32_t), b->st) != hipSuccess) return PIC_EDEVICE;
+    if (hipMemsetAsync(b->ctr, 0, 4 * sizeof(unsigned long long), b->st) != hipSuccess) return PIC_EDEVICE;
+    if (b->conv && hipMemsetAsync(b->conv, 0, kKsbConvWords * sizeof(uint32_t), b->st) != hipSuccess)
+        return PIC_EDEVICE;
+    if (b->mj) {
+        std::vector<float> tab;
+        build_mj_table(d->leaky_theta_inj, tab);
+        // synchronous copy from the host vector (it is freed on return)
+        if (hipMemcpy(b->mj, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            return PIC_EDEVICE;
+    }
+    return PIC_OK;
+}
+
+// bytes of the arena: the workspace alone for a box on caller memory, everything otherwise
+int32_t measure(pic_box* b, const pic_box_mem* m, size_t* bytes)
+{
+    b->alloc_pass = 1;
+    b->arena_off = 0;
+    const int32_t r = alloc_all(b, m);
+    b->alloc_pass = 0;
+    *bytes = b->arena_off;
+    return r;
 }
 
 }  // namespace
@@ -1148,175 +1492,85 @@ int32_t pic_box_destroy(pic_box* b)
     }
     if (b->fork_ev) hipEventDestroy(b->fork_ev);
     if (b->side_ev) hipEventDestroy(b->side_ev);
-    for (auto& g : b->graphs) hipGraphExecDestroy(g.exec);
-    for (auto& sg : b->stage) {
-        if (sg.host) hipHostFree(sg.host);
-        if (sg.dev) hipFree(sg.dev);
-        if (sg.copied) hipEventDestroy(sg.copied);
-    }
-    for (void* p : b->allocs) hipFree(p);
+    stager_release(b->stager);
+    for (auto& a : b->allocs) lib_free(a.first, a.second);
     delete b;
     return PIC_OK;
 }
 
-int32_t pic_box_create(const pic_box_desc* d, pic_box** out)
+int32_t pic_box_layout(const pic_box_desc* d, pic_box_layout_info* out)
 {
     if (!d || !out) return PIC_EINVAL;
-    if (d->dim != 2 && d->dim != 3) return PIC_EINVAL;
-    int n[3] = {d->n[0], d->n[1], d->dim == 3 ? d->n[2] : 1};
-    if (d->dim == 2 && d->n[2] != 1 && d->n[2] != 0) return PIC_EINVAL;
-    for (int k = 0; k < d->dim; k++)
-        if (n[k] < 4) return PIC_EINVAL;
-    if (!(d->dt > 0) || d->dt * std::sqrt((double)d->dim) >= 1.0) return PIC_EINVAL;
-    if (d->frame < 0 || d->frame > 3) return PIC_EINVAL;
-    if (d->n_species < 1 || d->n_species > 2) return PIC_EINVAL;
-    if (d->maxwell_iters < 0 || d->maxwell_iters > kKsbMaxSweeps || !(d->maxwell_tol >= 0.0) ||
-        !(d->maxwell_tol < 1.0))
-        return PIC_EINVAL;
-    if (escapes(d)) {
-        if (d->leaky_mode == PIC_LEAKY_DISPLACEMENT && !(d->leaky_l_esc > 0 && d->leaky_theta_inj > 0))
-            return PIC_EINVAL;
-        if (d->leaky_mode == PIC_LEAKY_PROBABILISTIC && !(d->leaky_t_esc > 0)) return PIC_EINVAL;
-        if (d->leaky_mode != 0 && d->leaky_mode != 1) return PIC_EINVAL;
-    }
-    int tile[3];
-    for (int k = 0; k < 3; k++) tile[k] = d->tile[k];
-    if (tile[0] == 0) {
-        tile[0] = tile[1] = d->dim == 3 ? 8 : 16;
-        tile[2] = d->dim == 3 ? 8 : 1;
-    }
-    if (d->dim == 2) tile[2] = 1;
-    if (!tile_shape_supported(d->dim, tile)) return PIC_EINVAL;
-    int bits[3];
-    for (int k = 0; k < 3; k++) bits[k] = ceil_log2(n[k]);
-    if (bits[0] + bits[1] + bits[2] > 31) return PIC_EINVAL;
-    for (int s = 0; s < d->n_species; s++)
-        if (d->capacity[s] < 0 || d->capacity[s] >= (1ll << 30)) return PIC_EINVAL;  // 32-bit byte offsets
-
-    pic_box* b = new (std::nothrow) pic_box();
-    static std::atomic<uint64_t> next_uid{0};
-    if (b) b->uid = ++next_uid;
-    if (!b) return PIC_ENOMEM;
-    b->d = *d;
-    b->st = static_cast<hipStream_t>(d->stream);
-    b->dim = d->dim;
-    for (int k = 0; k < 3; k++) b->n[k] = n[k];
-    b->cc.b0 = bits[0];
-    b->cc.b1 = bits[1];
-    b->cc.m0 = (1u << bits[0]) - 1u;
-    b->cc.m1 = (1u << bits[1]) - 1u;
-    set_tiling(b, tile);
-    const int tiles_ws = max_tiles(b->dim, n);  // any supported tiling fits the workspace
-    GridDev& G = b->G;
-    G.dim = b->dim;
-    G.div0 = FastDiv::make((uint32_t)n[0]);
-    G.div1 = FastDiv::make((uint32_t)n[1]);
-    for (int k = 0; k < 3; k++) {
-        G.n[k] = n[k];
-        G.g[k] = (k < b->dim) ? kGuard : 0;
-    }
-    G.divyg = FastDiv::make((uint32_t)(n[1] + 2 * G.g[1]));
-    // rows of kRowAlign floats: interior x = 0 starts a 128-byte line in every row (the x
-    // guards sit in the padding before and after the interior)
-    const int NYg = n[1] + 2 * G.g[1], NZg = n[2] + 2 * G.g[2];
-    G.sy = (kRowAlign + n[0] + G.g[0] + kRowAlign - 1) / kRowAlign * kRowAlign;
-    G.sz = G.sy * NYg;
-    b->comp_elems = (int64_t)G.sy * NYg * NZg;
-    b->origin = (int64_t)kRowAlign + (int64_t)G.sy * G.g[1] + (int64_t)G.sz * G.g[2];
-    b->nsp = d->n_species;
-    b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || escapes(d);
-
-    int32_t r = PIC_OK;
-    auto grid_alloc = [&](float*& p) -> int32_t {
-        float* q = nullptr;
-        int32_t rr = dalloc(b, q, (size_t)b->comp_elems);
-        if (rr) return rr;
-        if (b->alloc_pass == 1) return PIC_OK;
-        if (hipMemsetAsync(q, 0, sizeof(float) * b->comp_elems, b->st) != hipSuccess) return PIC_EDEVICE;
-        p = q + b->origin;
-        return PIC_OK;
-    };
-    auto alloc_all = [&]() -> int32_t {
-    int32_t r = PIC_OK;
-    b->nsets = d->frame == PIC_FRAME_SHEAR ? 3 : 1;
-    for (int s = 0; s < b->nsets && !r; s++)
-        for (int c = 0; c < 6 && !r; c++) r = grid_alloc(b->set[s][c]);
-    for (int c = 0; c < 3 && !r; c++) r = grid_alloc(b->J[c]);
-    if (d->frame == PIC_FRAME_SHEAR)
-        for (int c = 0; c < 3 && !r; c++) r = grid_alloc(b->Jt[c]);
-    for (int s = 0; s < b->nsp && !r; s++) {
-        Species& S = b->sp[s];
-        S.cap = d->capacity[s];
-        S.qm = d->q_over_m[s];
-        S.q = d->q_macro[s];
-        const size_t cap = (size_t)S.cap + 1;
-        for (int k = 0; k < 2 && !r; k++) {
-            r = dalloc(b, S.cell[k], cap);
-            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.off[k][c], c < b->dim ? cap : 1);
-            for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.u[k][c], cap);
-            if (!r && b->track_ids) r = dalloc(b, S.id[k], cap);
-            if (escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
-                for (int c = 0; c < 3 && !r; c++) r = dalloc(b, S.dr[k][c], cap);
-        }
-        for (int k = 0; k < 2 && !r; k++) {
-            r = dalloc(b, S.sb.keys[k], cap);
-            if (!r) r = dalloc(b, S.sb.vals[k], cap);
-        }
-        if (!r) r = dalloc(b, S.sb.hist, sort_hist_words((int64_t)cap));
-        if (!r) r = dalloc(b, S.sb.scratch, scan_scratch_words((int64_t)sort_hist_words((int64_t)cap)));
-        for (int k = 0; k < 2 && !r; k++) r = dalloc(b, S.toff[k], (size_t)tiles_ws + 2);
-        const size_t nt = (size_t)tiles_ws;
-        if (!r) r = dalloc(b, S.sb.mcnt, nt * kMigDirs);
-        if (!r) r = dalloc(b, S.sb.mpre, nt * kMigDirs);
-        if (!r) r = dalloc(b, S.sb.tot, nt + 1);
-        if (!r) r = dalloc(b, S.sb.start, nt + 1);
-        if (!r) r = dalloc(b, S.sb.dcnt, nt + 1);
-        if (!r) r = dalloc(b, S.sb.dpre, nt + 1);
-        if (!r) r = dalloc(b, S.sb.mscratch, migrate_scratch_words(tiles_ws));
-        if (!r) r = dalloc(b, S.sb.fallback, 1);
-        if (!r) r = dalloc(b, S.n_live, 2);
-        if (!r && b->alloc_pass != 1 && hipMemsetAsync(S.n_live, 0, 2 * sizeof(int32_t), b->st) != hipSuccess)
-            r = PIC_EDEVICE;
-    }
-    if (!r) r = dalloc(b, b->err, 4);
-    if (!r) r = dalloc(b, b->ctr, 4);
-    if (!r && d->frame == PIC_FRAME_SHEAR) r = dalloc(b, b->conv, kKsbConvWords);
-    if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
-    if (!r) r = dalloc(b, b->red_out, 16);
-    if (!r) r = dalloc(b, b->hist_edges, kHistMaxBins + 1);
-    if (!r) r = dalloc(b, b->hist_counts, kHistMaxBins + 2);
-    if (!r && escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT)
-        r = dalloc(b, b->mj, (size_t)kMjBins + kMjTail);
-    if (b->alloc_pass == 1) return r;
-    if (!r && hipMemsetAsync(b->err, 0, 4 * sizeof(uint32_t), b->st) != hipSuccess) r = PIC_EDEVICE;
-    if (!r && hipMemsetAsync(b->ctr, 0, 4 * sizeof(unsigned long long), b->st) != hipSuccess) r = PIC_EDEVICE;
-    if (!r && b->conv && hipMemsetAsync(b->conv, 0, kKsbConvWords * sizeof(uint32_t), b->st) != hipSuccess)
-        r = PIC_EDEVICE;
-    if (!r && b->mj) {
-        std::vector<float> tab;
-        build_mj_table(d->leaky_theta_inj, tab);
-        // synchronous copy from the host vector (it is freed on return)
-        if (hipMemcpy(b->mj, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
-            r = PIC_EDEVICE;
-    }
-    return r;
-    };
-    b->alloc_pass = 1;
-    b->arena_off = 0;
-    r = alloc_all();
+    pic_box* b = nullptr;
+    int32_t r = init_box(d, nullptr, b);
+    if (r) return r;
+    std::memset(out, 0, sizeof(*out));
+    pic_box_mem probe{};  // measuring with caller memory: the workspace alone
+    size_t ws = 0;
+    r = measure(b, &probe, &ws);
     if (!r) {
+        out->workspace_bytes = (int64_t)ws;
+        out->field_sets = b->nsets;
+        out->current_arrays = d->frame == PIC_FRAME_SHEAR ? 2 : 1;
+        out->field_pitch_min[0] = b->G.sy;
+        out->field_pitch_min[1] = b->G.sz;
+        out->field_rows = (b->n[1] + 2 * b->G.g[1]) * (b->n[2] + 2 * b->G.g[2]);
+        out->field_planes = b->n[2] + 2 * b->G.g[2];
+        out->field_elems_min = b->comp_elems;
+        for (int s = 0; s < b->nsp; s++) out->particle_elems[s] = d->capacity[s] + 1;
+        out->has_id = b->track_ids ? 1 : 0;
+        out->has_dr = escapes(d) && d->leaky_mode == PIC_LEAKY_DISPLACEMENT ? 1 : 0;
+    }
+    delete b;
+    return r;
+}
+
+int32_t pic_workspace_bytes(const pic_box_desc* d, int64_t* bytes)
+{
+    if (!bytes) return PIC_EINVAL;
+    pic_box_layout_info L{};
+    const int32_t r = pic_box_layout(d, &L);
+    if (!r) *bytes = L.workspace_bytes;
+    return r;
+}
+
+int32_t pic_allocated_bytes(int64_t* device_bytes, int64_t* host_bytes)
+{
+    if (device_bytes) *device_bytes = g_dev_bytes.load();
+    if (host_bytes) *host_bytes = g_host_bytes.load();
+    return PIC_OK;
+}
+
+int32_t pic_box_create(const pic_box_desc* d, const pic_box_mem* m, pic_box** out)
+{
+    if (!d || !out) return PIC_EINVAL;
+    pic_box* b = nullptr;
+    int32_t r = init_box(d, m ? m->field_pitch : nullptr, b);
+    if (r) return r;
+    b->caller_mem = m != nullptr;
+    size_t bytes = 0;
+    r = measure(b, m, &bytes);
+    if (!r && m) {
+        // the caller's workspace: large enough and 256-byte aligned
+        if (!m->workspace || m->workspace_bytes < (int64_t)bytes || (reinterpret_cast<uintptr_t>(m->workspace) & 255))
+            r = m->workspace && m->workspace_bytes < (int64_t)bytes ? PIC_ENOMEM : PIC_EINVAL;
+        else
+            b->arena = static_cast<char*>(m->workspace);
+    } else if (!r) {
         void* q = nullptr;
-        if (hipMalloc(&q, b->arena_off) != hipSuccess) {
+        if (lib_malloc(&q, bytes) != hipSuccess) {
             r = PIC_ENOMEM;
         } else {
-            b->allocs.push_back(q);
+            b->allocs.push_back({q, bytes});
             b->arena = static_cast<char*>(q);
-            b->alloc_pass = 2;
-            b->arena_off = 0;
-            r = alloc_all();
         }
     }
-    b->alloc_pass = 0;
+    if (!r) {
+        b->alloc_pass = 2;
+        b->arena_off = 0;
+        r = alloc_all(b, m);
+        b->alloc_pass = 0;
+    }
     if (r) {
         pic_box_destroy(b);
         return r;
@@ -1649,8 +1903,12 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
 {
     int32_t r = check_boxes(boxes, nb);
     for (int i = 0; i < nb && !r; i++) r = side_join(boxes[i]);
-    if (!r && (flags & (PIC_STEP_BATCHED | PIC_STEP_GRAPH)))
-        return step_batched(boxes, nb, (flags & PIC_STEP_GRAPH) != 0);
+    if (!r && (flags & (PIC_STEP_BATCHED | PIC_STEP_GRAPH))) {
+        // the lead box stages the tables in its own (library) memory; a box on caller memory
+        // cannot, and leads batched steps only through pic_step_batch
+        if (boxes[0]->caller_mem) return PIC_EINVAL;
+        return step_batched(boxes, nb, (flags & PIC_STEP_GRAPH) != 0, boxes[0]->stager, false, nullptr);
+    }
     for (int i = 0; i < nb && !r; i++) {
         pic_box* b = boxes[i];
         r = sort_box(b);
@@ -1662,6 +1920,57 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
             if (b->d.frame != PIC_FRAME_SHEAR) r = fill_field_guards(b, time_of(b, b->step));
         }
     }
+    return r;
+}
+
+int32_t pic_batch_create(void* dev, void* host, int64_t bytes, void* stream, pic_batch** out)
+{
+    if (!out || !dev || !host || bytes < 2 * 4096 || (reinterpret_cast<uintptr_t>(dev) & 255) ||
+        (reinterpret_cast<uintptr_t>(host) & 255))
+        return PIC_EINVAL;
+    pic_batch* B = new (std::nothrow) pic_batch();
+    if (!B) return PIC_ENOMEM;
+    B->st = static_cast<hipStream_t>(stream);
+    B->sg.caller = true;
+    const size_t half = ((size_t)bytes / 2) & ~(size_t)255;
+    for (int k = 0; k < 2; k++) {
+        B->sg.buf[k].dev = static_cast<char*>(dev) + k * half;
+        B->sg.buf[k].host = static_cast<char*>(host) + k * half;
+        B->sg.buf[k].cap = half;
+    }
+    *out = B;
+    return PIC_OK;
+}
+
+int32_t pic_batch_destroy(pic_batch* B)
+{
+    if (!B) return PIC_OK;
+    hipStreamSynchronize(B->st);
+    stager_release(B->sg);
+    delete B;
+    return PIC_OK;
+}
+
+int32_t pic_step_batch(pic_batch* B, pic_box* const* boxes, int32_t nb, uint32_t flags)
+{
+    if (!B) return PIC_EINVAL;
+    int32_t r = check_boxes(boxes, nb);
+    for (int i = 0; i < nb && !r; i++)
+        if (boxes[i]->st != B->st) r = PIC_EINVAL;
+    for (int i = 0; i < nb && !r; i++) r = side_join(boxes[i]);
+    if (r) return r;
+    return step_batched(boxes, nb, (flags & PIC_STEP_GRAPH) != 0, B->sg, false, nullptr);
+}
+
+int32_t pic_step_table_bytes(pic_box* const* boxes, int32_t nb, int64_t* bytes)
+{
+    if (!bytes) return PIC_EINVAL;
+    int32_t r = check_boxes(boxes, nb);
+    if (r) return r;
+    Stager unused;
+    size_t tb = 0;
+    r = step_batched(boxes, nb, false, unused, true, &tb);
+    if (!r) *bytes = (int64_t)tb;
     return r;
 }
 
@@ -1774,6 +2083,9 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
     info->n_slow = (int64_t)ctr[0];
     info->n_escaped = (int64_t)ctr[1];
     info->n_superluminal = (int64_t)ctr[3];
+    info->field_set = b->cur_set;
+    info->current_array = b->J[0] == b->J0 ? 0 : 1;
+    for (int s = 0; s < b->nsp; s++) info->particle_copy[s] = b->sp[s].cur;
     info->step = b->step;
     info->t = time_of(b, b->step);
     info->dys = shear_offset(b, info->t);

@@ -27,7 +27,7 @@ import torch
 
 from . import _lib as L
 from . import synth
-from .box import Box, step_many
+from .box import Batch, Box, describe, footprint as box_footprint, step_many
 
 SIZES = (32, 64, 128, 256)
 KINDS = ("shear", "expand", "leaky")
@@ -118,31 +118,45 @@ def tile_for(n: int, ppc: int):
     return _TILES[(n, ppc_class(ppc))]
 
 
-def footprint(spec: RunSpec) -> int:
-    """Device bytes of one run: particle state double-buffered with ids and sort workspace
-    (~96 B per particle), 3 field sets + current + transport buffer with padded rows."""
-    cells = (spec.n + 64) * (spec.n + 4)
-    return spec.particles * 96 + cells * 4 * 30 + (1 << 20)
-
-
-def build_box(spec: RunSpec, tile=None) -> Box:
+def box_args(spec: RunSpec, tile=None):
+    """(descriptor arguments of the run's box, axis of B0)"""
     wp, q, B0 = synth.plasma_params(spec.ppc, 4.0, 0.1)
-    n = (spec.n, spec.n)
     count = spec.ppc * spec.n * spec.n
     species = [(-1.0, -q, count), (1.0, q, count)]
-    common = dict(dt=0.45, species=species, seed=spec.seed, box_id=max(spec.rid, 0),
-                  tile=tile if tile is not None else tile_for(spec.n, spec.ppc), maxwell_iters=4)
+    kw = dict(dt=0.45, species=species, seed=spec.seed, box_id=max(spec.rid, 0),
+              tile=tile if tile is not None else tile_for(spec.n, spec.ppc), maxwell_iters=4)
     axis = 2
     if spec.kind == "shear":
-        omega0 = 0.1 * B0 * min(1.0, 64.0 / spec.n)
-        box = Box(2, n, frame=L.FRAME_SHEAR, shear_s=spec.param, shear_omega0=omega0, **common)
+        kw.update(frame=L.FRAME_SHEAR, shear_s=spec.param,
+                  shear_omega0=0.1 * B0 * min(1.0, 64.0 / spec.n))
     elif spec.kind == "expand":
-        box = Box(2, n, frame=L.FRAME_EXPAND, expand_adot=spec.param, expand_axis_mask=0b110,
-                  **common)
+        kw.update(frame=L.FRAME_EXPAND, expand_adot=spec.param, expand_axis_mask=0b110)
         axis = 0
     else:
-        box = Box(2, n, frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_PROBABILISTIC,
-                  leaky_t_esc=spec.param * spec.n, leaky_gamma_thr=10.0, **common)
+        kw.update(frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_PROBABILISTIC,
+                  leaky_t_esc=spec.param * spec.n, leaky_gamma_thr=10.0)
+    return kw, axis
+
+
+_FOOTPRINTS: dict = {}
+
+
+def footprint(spec: RunSpec) -> int:
+    """Device bytes of one run, exactly: its box on torch memory as pic_box_layout sizes it
+    (fields and currents with guards, both particle copies, the workspace)."""
+    key = (spec.n, spec.ppc, spec.kind)
+    if key not in _FOOTPRINTS:
+        kw, _ = box_args(spec, tile=(0, 0, 0))
+        _FOOTPRINTS[key] = box_footprint(describe(2, (spec.n, spec.n), **kw))
+    return _FOOTPRINTS[key]
+
+
+def build_box(spec: RunSpec, tile=None, track_ids=False) -> Box:
+    """track_ids: carry particle ids (to match final states by id)."""
+    wp, q, B0 = synth.plasma_params(spec.ppc, 4.0, 0.1)
+    n = (spec.n, spec.n)
+    kw, axis = box_args(spec, tile)
+    box = Box(2, n, track_ids=track_ids, **kw)
     E, B = synth.uniform_field(n, axis, B0)
     box.set_fields(torch.from_numpy(E).float(), torch.from_numpy(B).float())
     for s, p in enumerate(synth.pair_plasma(n, spec.ppc, spec.theta, spec.seed, device="cuda")):
@@ -156,10 +170,23 @@ class RunResult:
     admitted: float
     done: float
     energies: tuple = field(default_factory=tuple)
+    state: dict = field(default_factory=dict)  # keep_state: final particles (by id) and fields
 
     @property
     def latency(self) -> float:
         return self.done - self.spec.arrival
+
+
+def _state(box: Box):
+    """Final particles of each species ordered by id, and the fields, on the host."""
+    out = {}
+    for sp in range(box.nsp):
+        g = {k: v.cpu().numpy() for k, v in box.get_particles(sp).items()}
+        order = np.argsort(g["id"], kind="stable")
+        out[sp] = {k: (v[..., order] if k != "dr" else v[:, order]) for k, v in g.items()}
+    E, B = box.get_fields()
+    out["E"], out["B"] = E.cpu().numpy(), B.cpu().numpy()
+    return out
 
 
 def _energies(box: Box):
@@ -173,35 +200,55 @@ ADMIT_PER_STEP = 8  # runs built per loop turn: building overlaps the GPU's step
 
 
 def serve(specs, budget_bytes, batched=True, keep_energies=False, graph=False,
-          clock=time.perf_counter):
+          clock=time.perf_counter, keep_state=False):
     """Run every spec (arrival times relative to the call) and return the results in
     completion order.  batched=False steps the active boxes one at a time (per-box launches);
     with admission of one run at a time that is the one-box-at-a-time baseline.  graph=True
     replays the batched step as a captured HIP graph while the set of active boxes is unchanged
-    (newly admitted runs take their first step, whose sort differs, before joining the set)."""
+    (newly admitted runs take their first step, whose sort differs, before joining the set).
+    keep_state: each result also holds the run's final particles (ids carried) and fields.
+    After the call,
+    serve.max_active is the most runs stepped together and serve.waited the runs that arrived
+    but waited for memory."""
     if graph:
         st = torch.cuda.Stream()  # graph capture needs a stream other than the null stream
         with torch.cuda.stream(st):
-            return _serve(specs, budget_bytes, batched, keep_energies, True, clock)
-    return _serve(specs, budget_bytes, batched, keep_energies, False, clock)
+            return _serve(specs, budget_bytes, batched, keep_energies, True, clock, keep_state)
+    return _serve(specs, budget_bytes, batched, keep_energies, False, clock, keep_state)
 
 
-def _serve(specs, budget_bytes, batched, keep_energies, graph, clock):
+def _serve(specs, budget_bytes, batched, keep_energies, graph, clock, keep_state):
+    # the batched step's argument tables are staged in torch memory (pic_batch)
+    batch = Batch(torch.cuda.current_stream()) if batched else None
+    try:
+        return _serve_loop(specs, budget_bytes, batched, keep_energies, graph, clock, batch,
+                           keep_state)
+    finally:
+        if batch is not None:
+            batch.close()
+
+
+def _serve_loop(specs, budget_bytes, batched, keep_energies, graph, clock, batch, keep_state):
     pending = sorted(specs, key=lambda s: s.arrival)
     active = []  # [spec, box, steps_done, admitted]
     used = 0
     out = []
     serve.build_s = serve.step_s = 0.0
+    serve.max_active = 0
+    waited = set()
     t0 = clock()
     i = 0
     while i < len(pending) or active:
         now = clock() - t0
         admitted = []
+        if i < len(pending) and pending[i].arrival <= now and active and \
+                used + footprint(pending[i]) > budget_bytes:
+            waited.add(pending[i].rid)  # arrived, but the memory is taken
         while i < len(pending) and pending[i].arrival <= now and len(admitted) < ADMIT_PER_STEP and (
                 not (active or admitted) or used + footprint(pending[i]) <= budget_bytes):
             sp = pending[i]
             tb = clock()
-            admitted.append([sp, build_box(sp), 0, now])
+            admitted.append([sp, build_box(sp, track_ids=keep_state), 0, now])
             serve.build_s += clock() - tb
             used += footprint(sp)
             i += 1
@@ -212,14 +259,14 @@ def _serve(specs, budget_bytes, batched, keep_energies, graph, clock):
         ts = clock()
         if batched:
             if graph and admitted:
-                step_many([a[1] for a in admitted], batched=True)
+                step_many([a[1] for a in admitted], batched=True, batch=batch)
                 for a in admitted:
                     a[2] += 1
             elif admitted:
                 active.extend(admitted)
                 admitted = []
             if active:
-                step_many([a[1] for a in active], batched=True, graph=graph)
+                step_many([a[1] for a in active], batched=True, graph=graph, batch=batch)
                 for a in active:
                     a[2] += 1
             active.extend(admitted)
@@ -229,16 +276,19 @@ def _serve(specs, budget_bytes, batched, keep_energies, graph, clock):
                 step_many([a[1]], batched=False)
                 a[2] += 1
         serve.step_s += clock() - ts
+        serve.max_active = max(serve.max_active, len(active))
         finished = [a for a in active if a[2] >= a[0].steps]
         if finished:
             torch.cuda.synchronize()
             t = clock() - t0
             for a in finished:
                 e = _energies(a[1]) if keep_energies else ()
-                out.append(RunResult(a[0], a[3], t, e))
+                stt = _state(a[1]) if keep_state else {}
+                out.append(RunResult(a[0], a[3], t, e, stt))
                 a[1].close()
                 used -= footprint(a[0])
             active = [a for a in active if a[2] < a[0].steps]
+    serve.waited = len(waited)
     return out, clock() - t0
 
 

@@ -53,7 +53,7 @@ class Case:
                  leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=3.0, t_esc=9.0, gamma_thr=10.0,
                  theta_inj=0.3, maxwell_iters=4, maxwell_tol=0.0, q=None, parts=None, track_ids=True,
                  use_3vec=0, box_seed=0x5EED1234ABCDEF01, box_id=7, stream=None,
-                 count_superluminal=False, escape=False):
+                 count_superluminal=False, escape=False, mem="caller"):
         self.dim = dim
         self.n = tuple(list(n) + [1] * (3 - len(n)))
         self.frame = FRAMES[frame]
@@ -82,7 +82,8 @@ class Case:
                        seed=box_seed, box_id=box_id, tile=tile, maxwell_iters=maxwell_iters,
                        maxwell_tol=maxwell_tol,
                        track_ids=track_ids, stream=stream,
-                       count_superluminal=count_superluminal, escape=escape)
+                       count_superluminal=count_superluminal, escape=escape, mem=mem,
+                       unfused=True)
         self.gpu.set_fields(torch.from_numpy(self.E32), torch.from_numpy(self.B32))
         for s, p in enumerate(self.parts):
             ids = np.arange(len(p["cell"])) + s * 10_000_000

@@ -103,7 +103,7 @@ def _desc(**kw):
 ])
 def test_invalid_descriptors_rejected_on_the_host(lib, bad):
     out = C.c_void_p()
-    rc = lib.pic_box_create(C.byref(_desc(**bad)), C.byref(out))
+    rc = lib.pic_box_create(C.byref(_desc(**bad)), None, C.byref(out))
     assert rc == L.PIC_EINVAL and not out.value
 
 
@@ -114,8 +114,8 @@ def test_null_arguments(lib):
     assert lib.pic_energy_histogram(None, 0, edges, 2, counts) == L.PIC_EINVAL
     assert lib.pic_energy_histogram_static(None, 0, edges, 2, counts) == L.PIC_EINVAL
     assert lib.pic_set_step(None, 0) == L.PIC_EINVAL
-    assert lib.pic_box_create(None, C.byref(out)) == L.PIC_EINVAL
-    assert lib.pic_box_create(C.byref(_desc()), None) == L.PIC_EINVAL
+    assert lib.pic_box_create(None, None, C.byref(out)) == L.PIC_EINVAL
+    assert lib.pic_box_create(C.byref(_desc()), None, None) == L.PIC_EINVAL
     assert lib.pic_box_destroy(None) == L.PIC_OK
 
 
@@ -174,3 +174,58 @@ int main(void) {{
                                            text=True).stdout.split()]
     assert got[0] == C.sizeof(py)
     assert got[1:] == [getattr(py, f).offset for f in fields]
+
+
+def test_layout_and_workspace_on_the_host(lib):
+    """pic_box_layout sizes the caller-owned buffers without a device: field pitches with the
+    interior x = 0 of every row on a 128-byte line, the particle arrays, the workspace; the
+    unfused record adds 28 B per slot per species; a bad descriptor is rejected."""
+    d = _desc(dim=3, n=(20, 12, 16), capacity=1000)
+    lay = L.pic_box_layout(d)
+    assert lay.field_sets == 1 and lay.current_arrays == 1
+    assert lay.field_pitch_min[0] % 32 == 0 and lay.field_pitch_min[0] >= 32 + 20 + 2
+    assert lay.field_pitch_min[1] == lay.field_pitch_min[0] * (12 + 4)
+    assert lay.field_planes == 16 + 4 and lay.field_elems_min == lay.field_pitch_min[1] * 20
+    assert list(lay.particle_elems) == [1001, 1001]
+    assert lay.has_id == 0 and lay.has_dr == 0
+    assert L.pic_workspace_bytes(d) == lay.workspace_bytes > 0
+    d.flags = L.BOX_UNFUSED
+    assert L.pic_workspace_bytes(d) >= lay.workspace_bytes + 2 * 28 * 1001
+    shear = _desc(dim=2, n=(64, 64, 1), frame=L.FRAME_SHEAR)
+    ls = L.pic_box_layout(shear)
+    assert ls.field_sets == 3 and ls.current_arrays == 2 and ls.field_planes == 1
+    leaky = _desc(dim=2, n=(32, 32, 1), frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_DISPLACEMENT,
+                  l_esc=4.0, theta_inj=0.3)
+    ll = L.pic_box_layout(leaky)
+    assert ll.has_id == 1 and ll.has_dr == 1
+    out = L.pic_box_layout_info()
+    assert lib.pic_box_layout(C.byref(_desc(dt=0.6)), C.byref(out)) == L.PIC_EINVAL
+
+
+def test_caller_memory_argument_checks_on_the_host(lib):
+    """Creating on caller memory with a missing, misaligned or too small buffer, or a bad pitch,
+    fails on the host before any device call."""
+    d = _desc(dim=2, n=(16, 16, 1), capacity=10)
+    out = C.c_void_p()
+    m = L.pic_box_mem()  # every pointer NULL
+    assert lib.pic_box_create(C.byref(d), C.byref(m), C.byref(out)) in (L.PIC_EINVAL, L.PIC_ENOMEM)
+    assert not out.value
+    m.field_pitch[0], m.field_pitch[1] = 40, 40 * 20  # not a multiple of 32
+    assert lib.pic_box_create(C.byref(d), C.byref(m), C.byref(out)) == L.PIC_EINVAL
+    m.field_pitch[0], m.field_pitch[1] = 32, 32 * 20  # below the row the 16 cells need
+    assert lib.pic_box_create(C.byref(d), C.byref(m), C.byref(out)) == L.PIC_EINVAL
+    dev, host = L.pic_allocated_bytes()
+    assert dev >= 0 and host >= 0
+
+
+def test_batch_argument_checks_on_the_host(lib):
+    buf = (C.c_ubyte * 20000)()
+    p = (C.addressof(buf) + 255) & ~255
+    out = C.c_void_p()
+    assert lib.pic_batch_create(None, p, 8192, None, C.byref(out)) == L.PIC_EINVAL
+    assert lib.pic_batch_create(p, p + 4, 8192, None, C.byref(out)) == L.PIC_EINVAL
+    assert lib.pic_batch_create(p, p, 4096, None, C.byref(out)) == L.PIC_EINVAL
+    assert lib.pic_batch_destroy(None) == L.PIC_OK
+    assert lib.pic_step_batch(None, None, 0, 0) == L.PIC_EINVAL
+    v = C.c_int64()
+    assert lib.pic_step_table_bytes(None, 1, C.byref(v)) == L.PIC_EINVAL

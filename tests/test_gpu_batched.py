@@ -24,9 +24,9 @@ MIX = [
 ]
 
 
-def make(spec, seed, stream=None):
+def make(spec, seed, stream=None, mem="caller"):
     return Case(spec["dim"], spec["n"], spec["frame"], ppc=spec["ppc"], seed=seed, theta=0.4,
-                tile=spec["tile"], maxwell_iters=4, stream=stream, **spec["kw"])
+                tile=spec["tile"], maxwell_iters=4, stream=stream, mem=mem, **spec["kw"])
 
 
 def assert_same_state(a, b, tag, by_id=False):
@@ -60,9 +60,12 @@ def assert_same_state(a, b, tag, by_id=False):
         assert np.abs(fa - fb).max() <= 1e-5 * np.abs(fb).max(), tag
 
 
-def test_batched_equals_alone():
-    mix = [make(sp, 300 + i) for i, sp in enumerate(MIX)]
-    alone = [make(sp, 300 + i) for i, sp in enumerate(MIX)]
+@pytest.mark.parametrize("mem", ["caller", "library"])
+def test_batched_equals_alone(mem):
+    """Boxes on torch memory step in batches through a pic_batch on torch staging; library-owned
+    boxes through the first box's own staging."""
+    mix = [make(sp, 300 + i, mem=mem) for i, sp in enumerate(MIX)]
+    alone = [make(sp, 300 + i, mem=mem) for i, sp in enumerate(MIX)]
     try:
         for step in range(6):
             step_many([c.gpu for c in mix], batched=True)

@@ -45,9 +45,12 @@ def test_tile_sort_bit_exact(dim):
 FRAME_CASES = [(d, f) for f in ("plain", "shear", "expand", "leaky") for d in (2, 3)]
 
 
+@pytest.mark.parametrize("mem", ["caller", "library"])
 @pytest.mark.parametrize("dim,frame", FRAME_CASES)
-def test_one_step_parity(dim, frame):
-    c = Case(dim, SIZE[dim], frame, ppc=4, seed=20 + dim)
+def test_one_step_parity(dim, frame, mem):
+    """One whole step against the oracle, for a box on torch memory (pic_box_mem) and for a box
+    on memory the library allocates."""
+    c = Case(dim, SIZE[dim], frame, ppc=4, seed=20 + dim, mem=mem)
     try:
         c.gpu.step()
         c.oracle_step()

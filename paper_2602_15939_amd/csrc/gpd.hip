@@ -30,6 +30,8 @@ __device__ inline f3 cross(f3 a, f3 b)
 // the correctly rounded division and square-root sequences.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// v_rsq_f32 for arguments >= 1 (Lorentz factors): no denormal rescaling needed
+__device__ inline float rsq1(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Particle arrays are indexed with 32-bit byte offsets (capacity below 2^30 per species), so
 // the loads and stores take a scalar base and one shared vector offset.
@@ -105,7 +107,7 @@ __device__ inline f3 push_boris(f3 u, f3 E, f3 B, float qm_hdt)
 {
     const f3 eps = qm_hdt * E;
     const f3 um = u + eps;
-    const float ig = rsqrtf(1.f + dot(um, um));
+    const float ig = rsq1(1.f + dot(um, um));
     const f3 t = (qm_hdt * ig) * B;
     const float d = 2.f * rcp(1.f + dot(t, t));
     const f3 c1 = cross(um, t);
@@ -116,7 +118,8 @@ __device__ inline f3 push_boris(f3 u, f3 E, f3 B, float qm_hdt)
 // Shearing-box push (Sec. 2.2, eq. OAu_disc): closed form
 //   u+ = B(u-) + R(S u-) + R(S w)/(1-g),  w = B(u-) + R(S u-),  g = S_2 . R(e_y),
 // with S u = e_y (s2 . u); R(e_y) written out.  gamma-bar from the printed first-order
-// approximation refined by two fixed-point steps of g^2 = 1 + A + K/g.
+// approximation refined by one fixed-point step of g^2 = 1 + A + K/g (the step contracts by
+// about |K|/(2 g^3), so the approximation's error, at most ~4e-7, drops below FP32 rounding).
 __device__ inline f3 push_shear(f3 u, f3 E, f3 B, float qm_hdt, float alpha1, float alpha2,
                                 float om_dt)
 {
@@ -128,7 +131,6 @@ __device__ inline f3 push_shear(f3 u, f3 E, f3 B, float qm_hdt, float alpha1, fl
     const float K = 2.f * alpha2 * ue * um.y;
     const float g0 = fsqrt(1.f + uu);
     float g = g0 + (alpha1 * um.x * um.y * g0 + alpha2 * ue * um.y) * rcp(1.f + uu);
-    g = fsqrt(1.f + A + K * rcp(g));
     g = fsqrt(1.f + A + K * rcp(g));
     const float ig = rcp(g);
     f3 t = (qm_hdt * ig) * B;
@@ -155,7 +157,7 @@ __device__ inline f3 push_expand(f3 u, f3 E, f3 B, float qm_hdt, const float lam
     const f3 eps = qm_hdt * E;
     const f3 um = u + eps;
     const f3 lu = mk(lam1p[0] * um.x, lam1p[1] * um.y, lam1p[2] * um.z);
-    const float ig = rsqrtf(1.f + dot(lu, lu));
+    const float ig = rsq1(1.f + dot(lu, lu));
     const float s = qm_hdt * ig;
     const f3 t = mk(s * tfac[0] * B.x, s * tfac[1] * B.y, s * tfac[2] * B.z);
     const f3 w = mk((1.f + ltil[0]) * um.x, (1.f + ltil[1]) * um.y, (1.f + ltil[2]) * um.z);
@@ -509,7 +511,6 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     for (int s = 0; s < P.nsp; s++) {
         const SpeciesDev& S = P.sp[s];
-        uint32_t stay = 0;  // particles that stay in this tile (the common direction)
         bool far = false;   // a particle beyond the neighbouring tiles
         uint32_t nesc = 0;  // probabilistic escapes (one counter add per wave, at the end)
         uint32_t nsl = 0;   // shearing box: superluminal effective velocities (likewise)
@@ -552,7 +553,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
 
             // ---- displacement of the deposit (comoving for the shearing box, primed for the
             // expanding box)
-            const float ig = rsqrtf(1.f + dot(u, u));
+            const float ig = rsq1(1.f + dot(u, u));
             const float hs = P.dt * ig;
             f3 D = hs * u;
             if (FRAME == kExpand) D = mk(D.x * P.linv[0], D.y * P.linv[1], D.z * P.linv[2]);
@@ -708,12 +709,14 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 }
                 int d = dy == 2 ? -1 : (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
                 if (ncell < 0) d = kMigDead;
-                if (d == 13)
-                    stay++;
-                else if (d >= 0)
-                    atomicAdd(&mc[s * kMigDirs + d], 1u);
-                else
-                    far = true;
+                // the particles that stay in the tile (the common direction, 13) are not counted
+                // here: they are the tile's particles less all the others (below)
+                if (d != 13) {
+                    if (d >= 0)
+                        atomicAdd(&mc[s * kMigDirs + d], 1u);
+                    else
+                        far = true;
+                }
             }
             st_at(S.cell_out, so, ncell);
             st_at(S.off_out[0], so, nox);
@@ -735,9 +738,6 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             if ((tid & 63) == 0 && nsl) atomicAdd(&P.ctr[3], (unsigned long long)nsl);
         }
         if (P.count_mig) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) stay += __shfl_xor(stay, o, 64);
-            if ((tid & 63) == 0 && stay) atomicAdd(&mc[s * kMigDirs + 13], stay);
             if (far) {
                 *P.mfb[s] = 1;
                 if (P.mig_latch) latch(P.err, kErrSort);
@@ -748,8 +748,14 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
     if (!fuse && !P.count_mig) return;
     __syncthreads();
     if (P.count_mig && tid < P.nsp * kMigDirs) {
-        const int s = tid / kMigDirs;
-        P.mcnt[s][(size_t)tile * kMigDirs + (tid - s * kMigDirs)] = mc[tid];
+        const int s = tid / kMigDirs, d = tid - s * kMigDirs;
+        uint32_t v = mc[tid];
+        if (d == 13) {  // the stayers: every particle of the tile goes to exactly one direction
+            v = (uint32_t)(P.sp[s].toff[tile + 1] - P.sp[s].toff[tile]);
+            for (int e = 0; e < kMigDirs; e++)
+                if (e != 13) v -= mc[s * kMigDirs + e];
+        }
+        P.mcnt[s][(size_t)tile * kMigDirs + d] = v;
     }
     if (fuse) flush_current<G, DIM, NT>(Jl, P, t0, ext, tid);
 }

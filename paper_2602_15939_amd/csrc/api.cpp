@@ -611,7 +611,11 @@ int32_t maxwell_box(pic_box* b)
         if (tol && zero_floats(reinterpret_cast<float*>(b->conv), 2 * K, st) != hipSuccess)
             return PIC_EDEVICE;
         int sk = sn, so = sb2;
+        // fixed count on the staged 3D grids: two sweeps per pass over memory (the same
+        // iterates bit for bit), a last single sweep when the count is odd
+        const bool paired = !tol && ksb_pass_fits(b->G) && K >= 2;
         for (int k = 0; k < K; k++) {
+            const bool pass = paired && k + 1 < K;
             KsbDev Kd{};
             Kd.G = b->G;
             for (int c = 0; c < 6; c++) {
@@ -633,7 +637,15 @@ int32_t maxwell_box(pic_box* b)
                 Kd.tol = (float)b->d.maxwell_tol;
                 Kd.k = k;
             }
-            if (ksb_sweep(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
+            if (pass) {
+                const double fl = std::floor(dys1);
+                Kd.y1_int = (int)fl;
+                Kd.y1_w = (float)(dys1 - fl);
+                if (ksb_pass(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
+                k++;
+            } else if (ksb_sweep(Kd, k == 0, st) != hipSuccess) {
+                return PIC_EDEVICE;
+            }
             if (tol && k == K - 1 && ksb_finalize(ksb_fin(b, K, so), st) != hipSuccess)
                 return PIC_EDEVICE;
             // the staged 3D sweep reads its whole halo at the (shearing-)periodic images: then

@@ -333,6 +333,11 @@ __device__ __attribute__((always_inline)) inline void yee_e_body(const MaxwellDe
 }
 PIC_BATCHED_KERNEL(yee_e, MaxwellDev, kBlock)
 
+// FP contraction inside one expression only in the shearing-box sweeps: every kernel that
+// computes an iterate (one sweep per launch, two per pass, the face columns of a pass) then
+// rounds it the same way, so the paths agree bit for bit.
+#pragma clang fp contract(on)
+
 // Shearing box, fixed-point sweeps of the implicit midpoint rule (Sec. 2.2):
 //   F^{k+1} = F^n + dt RHS((F^n + F^k)/2, J'),
 // RHS of eq. OAB / eq. OAE with v = -s Omega0 x:
@@ -628,6 +633,359 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
     if (K.conv) ksb_reduce<NT>(dm, fm, K.conv + 2 * K.k);
 }
 
+// ---- two sweeps per pass (3D, fixed sweep count)
+// A pass takes F^k to F^{k+2} = C + dt/2 L(F^{k+1}) with F^{k+1} = C + dt/2 L(F^k) kept in LDS:
+// the workgroup computes F^{k+1} on its PX x PY tile plus a one-cell halo, from F^k on the tile
+// plus a two-cell halo, then F^{k+2} on the tile, marching over z with three planes of each
+// iterate in LDS.  Memory sees one read of F^k and C and one write of F^{k+2} for two sweeps
+// (the first pass reads F^n and J and writes C and F^2).
+// The x halo of F^{k+1} beyond a shearing-periodic face is an image of the opposite face's
+// F^{k+1} at another y, which another workgroup owns: a face tile recomputes those values
+// itself, from F^k on the opposite face's three columns (one of them an image again) over the
+// rows the image interpolates between, one plane ahead of its own F^{k+1}.
+// Every value is the same expression as in the one-sweep kernels (contraction inside one
+// expression only), so a pass gives the two sweeps' iterate bit for bit.
+// Pipeline per plane: the stores of the previous plane's results, then the loads for the
+// next plane (F^k and C in two alternating register sets), which nothing reads before the
+// next plane, so the loads of a whole plane overlap the computation.
+// Roles of the 16 waves: every thread stages one F^k column position; threads 0..767 compute
+// F^{k+1} on the window rows, 128..639 F^{k+2} on the tile (two waves per SIMD); wave 0 stages
+// the x-halo columns of F^k, wave 12 computes the x-halo columns of F^{k+1}, waves 13 and 15
+// stage the opposite-face columns of F^k (one side each), wave 14 computes the opposite-face
+// values of F^{k+1}.
+constexpr int PX = 128, PY = 4, PZ = 64, PN = 1024;
+constexpr int W0X = PX + 4, W0Y = PY + 4;  // F^k window: tile + 2 (x from x0 - 2, y from y0 - 2)
+constexpr int W1X = PX + 2, W1Y = PY + 2;  // F^{k+1} window: tile + 1
+constexpr int XR1 = W1Y + 1, XR0 = XR1 + 2;  // opposite-face rows of F^{k+1} and of F^k
+// At 256^3 a pass takes 0.44 ms (the first 0.63) against 0.47 ms for two single sweeps: it
+// halves the memory traffic but is bound by its 2.5 operator evaluations per cell (F^{k+1} on
+// the halo adds half the tile) at one 1024-thread workgroup per CU (137 KB of LDS).
+
+// element of an array at a 32-bit byte offset from its base (the array pointer itself, in
+// scalar registers): plane and in-plane offsets are summed in 32 bits, so the compiler keeps
+// one offset register per position instead of a 64-bit address per array (the arrays of a
+// box that takes the pass span less than 4 GiB)
+__device__ inline float ld_off(const float* base, uint32_t ob)
+{
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + ob);
+}
+__device__ inline float* st_off(float* base, uint32_t ob)
+{
+    return reinterpret_cast<float*>(reinterpret_cast<char*>(base) + ob);
+}
+
+template <bool FIRST>
+__global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
+{
+    static_assert(W0Y * PX == PN && W1Y * PX <= 12 * 64 && 2 * W1Y <= 64, "thread roles");
+    static_assert(PX + PY * PX <= 10 * 64, "F^{k+2} on waves 2..9");
+    static_assert(3 * XR0 <= 32 && XR1 <= 32, "opposite-face roles fit half a wave per side");
+    __shared__ float A[3][6][W0Y * W0X];  // planes of F^k
+    __shared__ float Bs[3][6][W1Y * W1X];  // planes of F^{k+1}
+    __shared__ float XA[3][2][6][3 * XR0];  // opposite-face F^k: [plane][side][c][row * 3 + col]
+    __shared__ float XB[2][2][6][XR1];      // opposite-face F^{k+1}: [plane][side][c][row]
+    const GridDev& G = K.G;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int ntx = nx / PX, nty = (ny + PY - 1) / PY;
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * PX, y0 = ((tile / ntx) % nty) * PY, z0 = (tile / (ntx * nty)) * PZ;
+    const int z1 = min(z0 + PZ, nz);
+    const float* const* F = K.Fk;
+    const float h = 0.5f * K.dt;
+    const float fpdt = 4.f * 3.14159265358979f * K.dt;
+    // side 0: the face at x = 0 (x halo x = -1, an image of column nx - 1); side 1: x = nx - 1
+    const bool face[2] = {x0 == 0, x0 + PX == nx};
+    int js1[2];
+    float w1[2];
+    shear_image(false, K.y1_int, K.y1_w, js1[0], w1[0]);
+    shear_image(true, K.y1_int, K.y1_w, js1[1], w1[1]);
+
+    // ---- staged F^k position of every thread: window row tid / PX, tile column tid % PX
+    const uint32_t aoff = 4u * (uint32_t)(x0 + tid % PX + G.sy * wrapn(y0 - 2 + tid / PX, ny));
+    const int aslot = tid + (W0X - PX) * (tid / PX) + 2;
+    // extra F^k position, lanes 0..31 of wave 0 (x-halo columns lx = 0, 1, W0X-2, W0X-1 of
+    // F^k) and of waves 13 and 15 (column col, row r of the XR0 opposite-face rows of side 0 and
+    // side 1).  An image position interpolates two values (shift ydys of F^k): lane l + 32
+    // loads the second one for lane l.
+    uint32_t xoff = 0;
+    int xslot = 0;
+    bool xa = false, ximg = false;
+    float xw = 0.f;
+    const int xs = wv == 15 ? 1 : 0;
+    const bool xwave = wv == 0 || wv == 13 || wv == 15;
+    {
+        const int l = lane & 31;
+        int gx = 0, gy = 0;
+        bool pos = false;
+        if (wv == 0 && l < 4 * W0Y) {
+            const int ly = l >> 2, e = l & 3;
+            const int lx = e < 2 ? e : W0X - 4 + e;
+            gx = x0 - 2 + lx;
+            gy = y0 - 2 + ly;
+            pos = gx >= -1 && gx <= nx;  // x = -2, nx + 1 beyond a face are never read
+            xslot = ly * W0X + lx;
+        } else if ((wv == 13 || wv == 15) && l < 3 * XR0) {
+            const int col = l % 3, r = l / 3;
+            gx = (xs == 0 ? nx - 2 : -1) + col;
+            gy = y0 - 2 + js1[xs] + r;
+            pos = face[xs];
+            xslot = r * 3 + col;
+        }
+        int js = 0;
+        ximg = pos && (gx < 0 || gx >= nx);
+        if (ximg) shear_image(gx >= nx, K.ydys_int, K.ydys_w, js, xw);
+        const int sx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+        const int ya = wrapn(gy + js, ny);
+        const bool second = lane >= 32;
+        xa = pos && (!second || ximg);  // this lane loads a value
+        xoff = xa ? 4u * (uint32_t)(sx + G.sy * (second ? wrapn(ya + 1, ny) : ya)) : 0u;
+        if (second) xa = xa && ximg;
+        if (second) ximg = false;
+        if (second) pos = false;
+        xslot = pos ? xslot : -1;  // the lanes that store (lanes < 32 with a position)
+    }
+
+    // ---- F^{k+1} position: threads < W1Y * PX on the window rows over the tile columns
+    const bool bmain = tid < W1Y * PX;
+    const int blx = 1 + tid % PX, bly = bmain ? tid / PX : 0;
+    const int bslot = bly * W1X + blx;
+    const int bgx = x0 + tid % PX;
+    const uint32_t boff = 4u * (uint32_t)(bgx + G.sy * wrapn(y0 - 1 + bly, ny));
+    // extra F^{k+1} position (wave 12: the x-halo columns lx = 0, W1X - 1, rows r >> 1 --
+    // interior, or beyond a face an image of the opposite face's values; wave 14: row r of the
+    // opposite face of side cs, one plane ahead)
+    int cslot = 0, cs = 0, crow = 0, cgx = 0;
+    bool cop = false, cimg = false, caux = false;
+    uint32_t coff = 0;
+    if (wv == 12 && lane < 2 * W1Y) {
+        const int ly = lane >> 1, lx = (lane & 1) ? W1X - 1 : 0;
+        cgx = x0 - 1 + lx;
+        const int gy = y0 - 1 + ly;
+        cslot = ly * W1X + lx;
+        crow = ly;
+        cimg = cgx < 0 || cgx >= nx;
+        cop = !cimg;
+        cs = cgx < 0 ? 0 : 1;
+        coff = cop ? 4u * (uint32_t)(cgx + G.sy * wrapn(gy, ny)) : 0u;
+    } else if (wv == 14 && (lane & 31) < XR1) {
+        cs = lane >> 5;
+        crow = lane & 31;
+        caux = face[cs];
+        cgx = cs == 0 ? nx - 1 : 0;
+        coff = caux ? 4u * (uint32_t)(cgx + G.sy * wrapn(y0 - 1 + js1[cs] + crow, ny)) : 0u;
+    }
+    const bool cload = cop || caux;
+
+    // ---- F^{k+2}: the tile cell of threads PX .. PX + PY * PX - 1 (their F^{k+1} position)
+    const bool tmain = tid >= PX && tid < PX + PY * PX;
+    const int ty = (tid >> 7) - 1;
+    const bool inside = tmain && y0 + ty < ny;
+    const uint32_t i0 = 4u * (uint32_t)(bgx + G.sy * min(y0 + max(ty, 0), ny - 1));
+
+    // C of the F^{k+1} positions in two register sets used on alternate planes: the loads
+    // for plane q + 1 are issued at the top of plane q, beside the F^k loads
+    float R[6], X[6], Ca[6], Cb[6], Cn[6], Ct[6], Ores[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) X[c] = Ca[c] = Cb[c] = Cn[c] = Ct[c] = Ores[c] = 0.f;
+    auto plane_of = [&](int z) { return 4u * (uint32_t)G.sz * (uint32_t)wrapn(z, nz); };
+    auto fetch_main = [&](int z) {
+        const uint32_t pz = plane_of(z);
+#pragma unroll
+        for (int c = 0; c < 6; c++) R[c] = ld_off(F[c], pz + aoff);
+        if (wv == 0 && xa)
+#pragma unroll
+            for (int c = 0; c < 6; c++) X[c] = ld_off(F[c], pz + xoff);
+    };
+    auto fetch_aux = [&](int z) {
+        const uint32_t pz = plane_of(z);
+        if ((wv == 13 || wv == 15) && xa)
+#pragma unroll
+            for (int c = 0; c < 6; c++) X[c] = ld_off(F[c], pz + xoff);
+    };
+    // the extra value of a lane, interpolated with lane + 32's for an image (whole wave)
+    auto extra = [&](int c) {
+        const float v2 = __shfl(X[c], (lane & 31) + 32, 64);
+        return ximg ? shear_lerp(X[c], v2, xw) : X[c];
+    };
+    auto stash_main = [&](int s) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) A[s][c][aslot] = R[c];
+        if (wv == 0)
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const float v = extra(c);
+                if (xslot >= 0) A[s][c][xslot] = v;
+            }
+    };
+    auto stash_aux = [&](int s) {
+        if (wv == 13 || wv == 15)
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const float v = extra(c);
+                if (xslot >= 0) XA[s][xs][c][xslot] = v;
+            }
+    };
+    // C (first pass: J) of the F^{k+1} positions into Cd: main ones and wave 12's at plane zm,
+    // wave 14's at za
+    auto load_c = [&](float* Cd, int zm, int za) {
+        const uint32_t pm = plane_of(zm);
+        const uint32_t o = bmain ? boff : coff;
+        const uint32_t pc = caux ? plane_of(za) : pm;
+        if (bmain || cload)
+#pragma unroll
+            for (int c = 0; c < 6; c++)
+                if (!FIRST || c >= EX)
+                    Cd[c] = FIRST ? ld_off(K.J[c - EX], pc + o) : ld_off(K.C[c], pc + o);
+    };
+    // F^{k+1} = C + dt/2 L(F^k) at one position, the operator read through V; the first pass
+    // also gives C there (cout)
+    auto next_iterate = [&](auto&& V, int gx, const float* cw, float* out, float* cout) {
+        const float v0 = -K.sO * ((float)gx - K.half_nx);
+        const float vh = -K.sO * ((float)gx + 0.5f - K.half_nx);
+        float L[6];
+        ksb_operator<true>(V, v0, vh, K.sO, L);
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            if (FIRST) {
+                float cv = V(c, 0, 0, 0) + h * L[c];
+                if (c >= EX) cv -= fpdt * cw[c];
+                cout[c] = cv;
+                out[c] = cv + h * L[c];
+            } else {
+                out[c] = cw[c] + h * L[c];
+            }
+        }
+    };
+    // opposite-face F^{k+1} at plane z from the opposite-face F^k planes (m, c, p)
+    auto aux_iterate = [&](const float* cw, int m, int c0, int p, int xb) {
+        if (!caux) return;
+        auto V = [&](int c, int dx, int dy, int dz) {
+            const int s = dz < 0 ? m : (dz > 0 ? p : c0);
+            return XA[s][cs][c][(crow + 1 + dy) * 3 + 1 + dx];
+        };
+        float out[6], cv[6];
+        next_iterate(V, cgx, cw, out, cv);
+#pragma unroll
+        for (int c = 0; c < 6; c++) XB[xb][cs][c][crow] = out[c];
+    };
+
+    // ---- prologue: F^k planes z0 - 2, z0 - 1 (opposite face: z0 - 2 .. z0), the opposite
+    // face's F^{k+1} at z0 - 1, then the loads for the first plane
+    fetch_main(z0 - 2);
+    fetch_aux(z0 - 2);
+    stash_main(0);
+    stash_aux(0);
+    fetch_main(z0 - 1);
+    fetch_aux(z0 - 1);
+    stash_main(1);
+    stash_aux(1);
+    fetch_aux(z0);
+    load_c(Cb, z0 - 1, z0 - 1);
+    stash_aux(2);
+    __syncthreads();
+    aux_iterate(Cb, 0, 1, 2, 0);
+    __syncthreads();  // slot 0 of the opposite-face F^k is staged again at the first plane
+    fetch_main(z0);
+    fetch_aux(z0 + 1);
+    load_c(Ca, z0 - 1, z0);
+    int am = 0, ac = 1, ap = 2;  // F^k planes q - 1, q, q + 1
+    int bm = 0, bc = 1, bp = 2;  // F^{k+1} planes q - 2, q - 1, q
+    int xm = 1, xc = 2, xp = 0;  // opposite-face F^k planes q, q + 1, q + 2
+    int xbq = 0;                 // opposite-face F^{k+1} plane q (the other slot: q + 1)
+    // one plane: F^{k+1} at q with the C set Cu (loaded a plane earlier), the loads of the
+    // next plane's C into Cl
+    auto plane = [&](int q, float* Cu, float* Cl) {
+        stash_main(ap);  // F^k plane q + 1
+        stash_aux(xp);   // opposite-face F^k plane q + 2
+        if (inside) {
+            if (q - 2 >= z0) {
+                const uint32_t pz = plane_of(q - 2);
+#pragma unroll
+                for (int c = 0; c < 6; c++) __builtin_nontemporal_store(Ores[c], st_off(K.Fo[c], pz + i0));
+            }
+            if (FIRST && q - 1 >= z0 && q - 1 < z1) {
+                const uint32_t pz = plane_of(q - 1);
+#pragma unroll
+                for (int c = 0; c < 6; c++) __builtin_nontemporal_store(Ct[c], st_off(K.C[c], pz + i0));
+            }
+        }
+        if (q + 2 <= z1 + 1) fetch_main(q + 2);
+        if (q + 3 <= z1 + 1) fetch_aux(q + 3);
+        if (q + 1 <= z1) load_c(Cl, q + 1, q + 2);
+        __syncthreads();
+        // F^{k+1} at plane q
+        if (bmain) {
+            const int base = bslot + 2 * bly + W0X + 1;  // the same cell in the F^k window
+            auto V = [&](int c, int dx, int dy, int dz) {
+                const int s = dz < 0 ? am : (dz > 0 ? ap : ac);
+                return A[s][c][base + dx + W0X * dy];
+            };
+            float out[6];
+            next_iterate(V, bgx, Cu, out, Cn);
+#pragma unroll
+            for (int c = 0; c < 6; c++) Bs[bp][c][bslot] = out[c];
+        }
+        if (cop) {
+            const int base = cslot + 2 * crow + W0X + 1;
+            auto V = [&](int c, int dx, int dy, int dz) {
+                const int s = dz < 0 ? am : (dz > 0 ? ap : ac);
+                return A[s][c][base + dx + W0X * dy];
+            };
+            float out[6], cv[6];
+            next_iterate(V, cgx, Cu, out, cv);
+#pragma unroll
+            for (int c = 0; c < 6; c++) Bs[bp][c][cslot] = out[c];
+        } else if (cimg && face[cs]) {
+#pragma unroll
+            for (int c = 0; c < 6; c++)
+                Bs[bp][c][cslot] = shear_lerp(XB[xbq][cs][c][crow], XB[xbq][cs][c][crow + 1], w1[cs]);
+        }
+        if (q + 1 <= z1) aux_iterate(Cu, xm, xc, xp, xbq ^ 1);  // opposite face, plane q + 1
+        __syncthreads();
+        // F^{k+2} at plane q - 1
+        if (tmain && q - 1 >= z0) {
+            const int base = bslot;
+            auto V = [&](int c, int dx, int dy, int dz) {
+                const int s = dz < 0 ? bm : (dz > 0 ? bp : bc);
+                return Bs[s][c][base + dx + W1X * dy];
+            };
+            const float v0 = -K.sO * ((float)bgx - K.half_nx);
+            const float vh = -K.sO * ((float)bgx + 0.5f - K.half_nx);
+            float L[6];
+            ksb_operator<true>(V, v0, vh, K.sO, L);
+#pragma unroll
+            for (int c = 0; c < 6; c++) Ores[c] = Ct[c] + h * L[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) Ct[c] = FIRST ? Cn[c] : Cu[c];  // C at the tile cell, plane q
+        int t = am;
+        am = ac;
+        ac = ap;
+        ap = t;
+        t = bm;
+        bm = bc;
+        bc = bp;
+        bp = t;
+        t = xm;
+        xm = xc;
+        xc = xp;
+        xp = t;
+        xbq ^= 1;
+    };
+    int q = z0 - 1;
+    for (; q + 1 <= z1; q += 2) {
+        plane(q, Ca, Cb);
+        plane(q + 1, Cb, Ca);
+    }
+    if (q <= z1) plane(q, Ca, Cb);
+    if (inside && z1 - 1 >= z0) {
+        const uint32_t pz = plane_of(z1 - 1);
+#pragma unroll
+        for (int c = 0; c < 6; c++) __builtin_nontemporal_store(Ores[c], st_off(K.Fo[c], pz + i0));
+    }
+}
+
 // End of a tolerance-mode step (one record per box): find the first sweep that met the
 // tolerance, report the sweep count, latch kErrNoConverge if none did, and move that sweep's
 // iterate into the set the step hands on when it sits in the other one.
@@ -661,6 +1019,7 @@ __device__ __attribute__((always_inline)) inline void ksb_final_body(const KsbFi
     }
 }
 PIC_BATCHED_KERNEL(ksb_final, KsbFin, kBlock)
+#pragma clang fp contract(fast)
 
 // ------------------------------------------------------------------ utilities
 // grid-stride, 16-byte stores where the array is 16-byte aligned (the batched launch gives
@@ -870,6 +1229,7 @@ hipError_t yee_e(const MaxwellDev& M, hipStream_t st)
     return hipGetLastError();
 }
 bool ksb_staged(const GridDev& G) { return G.dim == 3 && G.n[0] % KX == 0; }
+bool ksb_pass_fits(const GridDev& G) { return ksb_staged(G) && 4 * (int64_t)G.sz * G.n[2] < (int64_t(1) << 32); }
 
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
 {
@@ -887,6 +1247,17 @@ hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
         else
             ksb_next_kernel<<<nb, kBlock, 0, st>>>(K);
     }
+    return hipGetLastError();
+}
+hipError_t ksb_pass(const KsbDev& K, bool first, hipStream_t st)
+{
+    if (!ksb_pass_fits(K.G) || K.conv) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((K.G.n[0] / PX) * ((K.G.n[1] + PY - 1) / PY) *
+                                     ((K.G.n[2] + PZ - 1) / PZ));
+    if (first)
+        ksb_pass3_kernel<true><<<grid, PN, 0, st>>>(K);
+    else
+        ksb_pass3_kernel<false><<<grid, PN, 0, st>>>(K);
     return hipGetLastError();
 }
 hipError_t ksb_finalize(const KsbFin& F, hipStream_t st)

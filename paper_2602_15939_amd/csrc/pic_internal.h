@@ -345,6 +345,10 @@ struct KsbDev {
     uint32_t* conv;
     float tol;
     int k;
+    // two sweeps per pass (3D grids of the staged sweep, fixed sweep count): the shift of the
+    // intermediate iterate's x images, Delta y_s at t^{n+1} = y1_int + y1_w
+    int y1_int;
+    float y1_w;
 };
 constexpr int kKsbMaxSweeps = 64;
 // words of a box's convergence record: kKsbMaxSweeps pairs, then the sweep count of the last
@@ -480,7 +484,13 @@ hipError_t yee_e(const MaxwellDev& M, hipStream_t st);
 // the staged kernel, which reads its whole halo at the (shearing-)periodic images itself;
 // otherwise one thread per cell reads the guard cells, which must be filled between sweeps
 bool ksb_staged(const GridDev& G);
+// the two-sweep pass applies: a staged grid whose arrays span less than 4 GiB (32-bit offsets)
+bool ksb_pass_fits(const GridDev& G);
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st);
+// two sweeps F^k -> F^{k+2} in one pass over memory (staged 3D grids only); first: F^k = F^n,
+// the pass also writes C
+hipError_t ksb_pass(const KsbDev& K, bool first, hipStream_t st);
+
 hipError_t ksb_finalize(const KsbFin& F, hipStream_t st);
 constexpr int kKsbFinBlocks = 512;  // workgroups per box of the finalize copy (grid stride)
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st);

@@ -1,0 +1,91 @@
+"""Two fixed-point sweeps per pass in the shearing-box Maxwell step (Sec. 2.2, implicit midpoint
+by fixed-point sweeps), taken on 3D grids whose x size is a multiple of the 128-cell column tile
+when the sweep count is fixed: the intermediate iterate lives only in on-chip memory, and its
+x-face images come from a small record of the two face columns.
+* The pass gives the same iterate as the same number of single sweeps, bit for bit.  Tolerance
+  mode with an unreachable tolerance runs exactly its cap of single sweeps (and latches
+  PIC_DERR_NOCONVERGE), so a box in that mode is the reference.  Even counts (passes only) and
+  odd counts (a last single sweep), with a current, on two x tiles (one face image each), one x
+  tile (both halos are images), ragged y tiles, ragged and single z chunks, the smallest grid
+  (windows wider than the grid in y and z), and a shear offset
+  Delta y_s that has a fractional part and wraps past n_y.
+* One Maxwell step against the oracle's FP64 step.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _cases import random_fields
+from paper_2602_15939_amd import _lib as L
+from paper_2602_15939_amd.box import Box
+
+pytestmark = pytest.mark.gpu
+
+S = 1.5
+
+
+def _box(n, omega0, start, J, **kw):
+    b = Box(3, n, frame=L.FRAME_SHEAR, species=((-1.0, 0.0, 16),), shear_s=S,
+            shear_omega0=omega0, **kw)
+    E, B = random_fields(n, 900)
+    b.set_fields(torch.from_numpy(E), torch.from_numpy(B))
+    b.set_step(start)
+    torch.cuda.synchronize()
+    cur = b.mem["current"][b.info().current_array]
+    for c in range(3):
+        b.interior(cur[c]).copy_(torch.from_numpy(J[c]))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(b.get_current().cpu().numpy(), J)  # written in place
+    return b, E, B
+
+
+def _current(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-0.01, 0.01, (3, n[2], n[1], n[0])).astype(np.float32)
+
+
+# |s omega0 nx / 2| dt stays below half a cell per step (the sweeps contract).
+CASES = [
+    ((256, 14, 70), 0.004, 19, 8),   # two x tiles, ragged y tile, two z chunks (one ragged)
+    ((256, 14, 70), 0.004, 19, 5),   # odd count: two passes and a last single sweep
+    ((128, 9, 5), -0.006, 7, 2),     # one x tile, one short z chunk, one pass
+    ((128, 6, 66), 0.005, 0, 3),     # Delta y_s = 0 at t^n
+    ((128, 4, 4), 0.005, 3, 4),      # the smallest grid: the windows wrap in y and z
+]
+
+
+@pytest.mark.parametrize("n,omega0,start,K", CASES)
+def test_pass_equals_single_sweeps(n, omega0, start, K):
+    J = _current(n, 31 + K)
+    a, _, _ = _box(n, omega0, start, J, maxwell_iters=K)
+    b, _, _ = _box(n, omega0, start, J, maxwell_iters=K, maxwell_tol=1e-30)
+    try:
+        a.maxwell()
+        b.maxwell()
+        ia, ib = a.info(), b.info()
+        assert ia.maxwell_sweeps == K and ib.maxwell_sweeps == K
+        assert ia.errors & ~L.DERR_ORDER == 0
+        assert ib.errors & L.DERR_NOCONVERGE
+        for fa, fb in zip(a.get_fields(), b.get_fields()):
+            np.testing.assert_array_equal(fa.cpu().numpy(), fb.cpu().numpy())
+    finally:
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("n,omega0,start,K", [CASES[1], CASES[2]])
+def test_pass_step_against_oracle(n, omega0, start, K):
+    J = _current(n, 77)
+    a, E, B = _box(n, omega0, start, J, maxwell_iters=K)
+    try:
+        a.maxwell()
+        box = oracle.make_box(3, n, frame=oracle.SHEAR, shear_s=S, omega0=omega0,
+                              maxwell_iters=K, step=start)
+        Eo, Bo = E.astype(np.float64), B.astype(np.float64)
+        oracle.maxwell(box, Eo, Bo, J.astype(np.float64))
+        Eg, Bg = (t.cpu().numpy().astype(np.float64) for t in a.get_fields())
+        for g, o in ((Eg, Eo), (Bg, Bo)):
+            assert np.abs(g - o).max() <= 1e-5 * np.abs(o).max()
+    finally:
+        a.close()

@@ -20,7 +20,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pic_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libpic_oracle.so")
 
-PLAIN, SHEAR, EXPAND, LEAKY = 0, 1, 2, 3
+PLAIN, SHEAR, EXPAND, LEAKY, SHEAR_EXPAND = 0, 1, 2, 3, 4
+# axis masks of the combined shearing and expanding frame: x and y scale together
+SHEAR_EXPAND_MASKS = (0b000, 0b100, 0b011, 0b111)
 LEAKY_DISPLACEMENT, LEAKY_PROBABILISTIC = 0, 1
 JG = 3  # x guard columns of the extended current grid
 
@@ -101,6 +103,8 @@ def make_box(dim, n, dt=0.45, frame=PLAIN, shear_s=0.0, omega0=0.0, adot=0.0, ax
              gamma_thr=10.0, seed=0, box_id=0, mj_table=None, maxwell_iters=8, maxwell_tol=0.0,
              step=0, escape=False) -> Box:
     n = list(n) + [1] * (3 - len(n))
+    if frame == SHEAR_EXPAND and axis_mask not in SHEAR_EXPAND_MASKS:
+        raise ValueError("the combined frame scales x and y together: axis_mask 0, 4, 3 or 7")
     b = Box()
     b.dim = dim
     for d in range(3):
@@ -233,6 +237,18 @@ def push_expand(qm, dt, lam, E, B, u, exact=False):
     return u
 
 
+def push_shear_expand(qm, dt, s, omega0, lam, xr, E, B, u, exact=False, return_gbar=False):
+    u = np.ascontiguousarray(u, float).copy()
+    E, B = np.ascontiguousarray(E, float), np.ascontiguousarray(B, float)
+    xr = np.ascontiguousarray(xr, float)
+    lam = np.ascontiguousarray(lam, float)
+    gb = np.zeros(len(u))
+    lib().ora_push_shear_expand(C.c_int64(len(u)), C.c_double(qm), C.c_double(dt), C.c_double(s),
+                                C.c_double(omega0), _p(lam), C.c_int(1 if exact else 0), _p(xr),
+                                _p(E), _p(B), _p(u), _p(gb))
+    return (u, gb) if return_gbar else u
+
+
 def shear_gamma_bar(A, K):
     return lib().ora_shear_gamma_bar(float(A), float(K))
 
@@ -270,6 +286,19 @@ def ksb_rhs(box: Box, E, B, J, dys=0.0):
     Ja = (C.POINTER(C.c_double) * 3)(*[_p(J[c]) for c in range(3)])
     Oa = (C.POINTER(C.c_double) * 6)(*[_p(out[c]) for c in range(6)])
     lib().ora_ksb_rhs(C.byref(box), Ea, Ba, C.c_double(dys), Ja, Oa)
+    return out
+
+
+def ksb_rhs_f(box: Box, E, B, J, d, kz, dys=0.0):
+    """The shearing-box right-hand side with the combined frame's factors: the curls act on
+    d_c F_c, kz multiplies v dE'y/dz in dE'z/dt."""
+    out = np.zeros((6,) + field_shape(box)[1:])
+    Ea = (C.POINTER(C.c_double) * 3)(*[_p(E[c]) for c in range(3)])
+    Ba = (C.POINTER(C.c_double) * 3)(*[_p(B[c]) for c in range(3)])
+    Ja = (C.POINTER(C.c_double) * 3)(*[_p(J[c]) for c in range(3)])
+    Oa = (C.POINTER(C.c_double) * 6)(*[_p(out[c]) for c in range(6)])
+    dd = np.ascontiguousarray(d, float)
+    lib().ora_ksb_rhs_f(C.byref(box), Ea, Ba, C.c_double(dys), Ja, _p(dd), C.c_double(kz), Oa)
     return out
 
 

@@ -54,9 +54,23 @@ static const double STAG_B[3][3] = {{0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}}
 /* ------------------------------------------------------------------ */
 
 /* Sec. 2.1: Delta y_s = s Omega0 (x_o - x_i) t, reduced modulo the box length in y */
+/* frames with the shearing-box geometry (Sec. 2) and with the expanding-box scale factors
+   (Sec. 3); the combined frame has both */
+static inline int sheared(const ora_box* b)
+{
+    return b->frame == ORA_SHEAR || b->frame == ORA_SHEAR_EXPAND;
+}
+static inline int expanding(const ora_box* b)
+{
+    return b->frame == ORA_EXPAND || b->frame == ORA_SHEAR_EXPAND;
+}
+
+/* Sec. 2.1: Delta y_s = s Omega0 (x_o - x_i) t.  In the combined frame x and y scale together
+   (reading), so the shear flow in the expanding coordinates, -s Omega0 (l_x/l_y) x', and with
+   it Delta y_s, keep their form. */
 double ora_shear_offset(const ora_box* b, double t)
 {
-    if (b->frame != ORA_SHEAR) return 0.0;
+    if (!sheared(b)) return 0.0;
     double ny = (double)b->n[1];
     double d = b->shear_s * b->omega0 * (double)b->n[0] * t;
     d = fmod(d, ny);
@@ -68,14 +82,14 @@ double ora_shear_offset(const ora_box* b, double t)
 /* Sec. 3.1: L = diag(l_1, l_2, l_3); reading: l_d = a(t) = 1 + adot t on the expanding axes */
 double ora_scale(const ora_box* b, int axis, double t)
 {
-    if (b->frame != ORA_EXPAND) return 1.0;
+    if (!expanding(b)) return 1.0;
     if (!((b->axis_mask >> axis) & 1)) return 1.0;
     return 1.0 + b->adot * t;
 }
 
 static double scale_rate(const ora_box* b, int axis)
 {
-    if (b->frame != ORA_EXPAND) return 0.0;
+    if (!expanding(b)) return 0.0;
     if (!((b->axis_mask >> axis) & 1)) return 0.0;
     return b->adot;
 }
@@ -93,7 +107,7 @@ static double fget(const ora_box* b, const double* F, int i, int j, int k, doubl
     const int nx = b->n[0], ny = b->n[1], nz = b->n[2];
     k = wrapi(k, nz);
     if (i >= 0 && i < nx) return F[cidx(b, i, wrapi(j, ny), k)];
-    if (b->frame != ORA_SHEAR) return F[cidx(b, wrapi(i, nx), wrapi(j, ny), k)];
+    if (!sheared(b)) return F[cidx(b, wrapi(i, nx), wrapi(j, ny), k)];
     double sh;
     int ii;
     if (i >= nx) {
@@ -356,6 +370,112 @@ void ora_push_expand(int64_t n, double qm, double dt, const double lam[3], int e
     }
 }
 
+/* 3x3 linear solve by Gaussian elimination with partial pivoting (augmented rows) */
+static void solve3(double M[3][4], double x[3])
+{
+    for (int piv = 0; piv < 3; piv++) {
+        int best = piv;
+        for (int r = piv + 1; r < 3; r++)
+            if (fabs(M[r][piv]) > fabs(M[best][piv])) best = r;
+        for (int c = 0; c < 4; c++) {
+            double tmp = M[piv][c];
+            M[piv][c] = M[best][c];
+            M[best][c] = tmp;
+        }
+        for (int r = 0; r < 3; r++) {
+            if (r == piv) continue;
+            double f = M[r][piv] / M[piv][piv];
+            for (int c = 0; c < 4; c++) M[r][c] -= f * M[piv][c];
+        }
+    }
+    for (int c = 0; c < 3; c++) x[c] = M[c][3] / M[c][c];
+}
+
+/* Combined shearing and expanding frame (the extension the conclusion, Sec. 5, names).
+   reading: the discrete momentum equation adds the diagonal Lambda of eq. EBu_disc (Sec. 3.2)
+   to eq. OAu_disc (Sec. 2.2),
+       (1 - Lambda) u+ - u+ x tau~ - S u+ = (1 + Lambda) u- + u- x tau~ + S u-,
+   with eps, eps~, tau~ = tau/gbar + dt Omega0, alpha1, alpha2 and the rank-1 S (only row y:
+   s2 = (alpha1 + alpha2 eps~_x, alpha2 eps~_y, alpha2 eps~_z)) of Sec. 2.2 and
+   Lambda = -(dt/2) L^-1 dL/dt of Sec. 3.2.  gbar takes both Boris-like definitions: the
+   largest real root of gbar^2 = 1 + ((1+Lambda)u-)^2 + 2 alpha1 u-_x u-_y
+   + 2 alpha2 (u-.eps) u-_y / gbar.  Closed form: A u = (1 - Lambda) u - u x tau~ is inverted
+   as the expanding push does, A^-1 r = R_t((1 - Lambda)^-1 r) with t = (1 - Lambda)^-1 tau~
+   (R the half rotation of Sec. 2.2), so that A^-1((1 + Lambda) v + v x tau~) is the printed
+   modified Boris operator B^(Lambda)(v) of Sec. 3.2; the rank-1 S is added by the
+   Sherman-Morrison formula, as the shearing push adds it to R:
+       w = B^(Lambda)(u-) + (s2 . u-) A^-1 e_y,   g = s2 . A^-1 e_y,
+       u+ = w + (s2 . w) A^-1 e_y / (1 - g),   u'^{n+1/2} = u+ + eps.
+   Lambda = 0 gives the shearing push of Sec. 2.2, S = 0 with Omega0 = 0 the expanding push of
+   Sec. 3.2.  exact != 0 solves the 3x3 system directly. */
+void ora_push_shear_expand(int64_t n, double qm, double dt, double s, double omega0,
+                           const double lam[3], int exact, const double* xr, const double* E,
+                           const double* B, double* u, double* gbar_out)
+{
+    const double a1 = s * omega0 * dt / 2.0;
+    for (int64_t p = 0; p < n; p++) {
+        const double a2 = s * omega0 * xr[p];
+        double eps[3], um[3], lu[3];
+        for (int c = 0; c < 3; c++) {
+            eps[c] = qm * dt * E[3 * p + c] / 2.0;
+            um[c] = u[3 * p + c] + eps[c];
+            lu[c] = (1.0 + lam[c]) * um[c];
+        }
+        const double A = dot(lu, lu) + 2.0 * a1 * um[0] * um[1];
+        const double K = 2.0 * a2 * dot(um, eps) * um[1];
+        const double gbar = ora_shear_gamma_bar(A, K);
+        if (gbar_out) gbar_out[p] = gbar;
+        double tt[3], et[3];
+        for (int c = 0; c < 3; c++) {
+            tt[c] = qm * dt * B[3 * p + c] / 2.0 / gbar;
+            et[c] = eps[c] / gbar;
+        }
+        tt[2] += dt * omega0;
+        const double s2[3] = {a1 + a2 * et[0], a2 * et[1], a2 * et[2]};
+        double up[3];
+        if (!exact) {
+            double t[3], Lt[3], v[3], vt[3], vtt[3], Bu[3];
+            for (int c = 0; c < 3; c++) {
+                t[c] = tt[c] / (1.0 - lam[c]);
+                Lt[c] = (1.0 + lam[c]) / (1.0 - lam[c]);
+                v[c] = (1.0 + Lt[c]) * um[c];
+            }
+            cross(v, t, vt);
+            cross(vt, t, vtt);
+            const double den = 1.0 + dot(t, t);
+            for (int c = 0; c < 3; c++) Bu[c] = Lt[c] * um[c] + vt[c] / den + vtt[c] / den;
+            /* A^-1 e_y = R_t((1 - Lambda)^-1 e_y) */
+            double ey[3] = {0.0, 1.0 / (1.0 - lam[1]), 0.0}, Ae[3];
+            op_half(ey, t, Ae);
+            const double g = dot(s2, Ae);
+            const double su = dot(s2, um);
+            double w[3];
+            for (int c = 0; c < 3; c++) w[c] = Bu[c] + su * Ae[c];
+            const double sw = dot(s2, w);
+            for (int c = 0; c < 3; c++) up[c] = w[c] + sw * Ae[c] / (1.0 - g);
+        } else {
+            /* M u+ = r, M = diag(1 - lam) - [x tau~] - e_y s2^T, r = (1 + lam) u- + u- x tau~
+               + e_y (s2 . u-), with [x t] v = v x t */
+            double M[3][4], ut[3];
+            cross(um, tt, ut);
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) M[r][c] = 0.0;
+            for (int c = 0; c < 3; c++) M[c][c] = 1.0 - lam[c];
+            M[0][1] -= tt[2];
+            M[0][2] += tt[1];
+            M[1][0] += tt[2];
+            M[1][2] -= tt[0];
+            M[2][0] -= tt[1];
+            M[2][1] += tt[0];
+            for (int c = 0; c < 3; c++) M[1][c] -= s2[c];
+            for (int c = 0; c < 3; c++) M[c][3] = (1.0 + lam[c]) * um[c] + ut[c];
+            M[1][3] += dot(s2, um);
+            solve3(M, up);
+        }
+        for (int c = 0; c < 3; c++) u[3 * p + c] = up[c] + eps[c];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Esirkepov charge-conserving deposit (CIC shape)                     */
 /* ------------------------------------------------------------------ */
@@ -528,7 +648,7 @@ void ora_finalize_current(const ora_box* b, const double* Jext, double* J, doubl
     const int64_t ne = jext_cells(b);
     double* T = (double*)malloc(sizeof(double) * 3 * ne);
     memcpy(T, Jext, sizeof(double) * 3 * ne);
-    if (b->frame == ORA_SHEAR) {
+    if (sheared(b)) {
         double* tmp = (double*)malloc(sizeof(double) * ny);
         for (int c = 0; c < 3; c++) {
             for (int k = 0; k < nz; k++)
@@ -562,7 +682,7 @@ void ora_finalize_current(const ora_box* b, const double* Jext, double* J, doubl
                 for (int j = 0; j < ny; j++) {
                     double v = *jext_at(b, T, c, i, j, k);
                     if (v == 0.0) continue;
-                    if (b->frame != ORA_SHEAR) {
+                    if (!sheared(b)) {
                         Jc[cidx(b, ii, j, k)] += v;
                     } else {
                         double sh = i >= nx ? dys : -dys;
@@ -715,9 +835,11 @@ static inline double up_dy(const ora_box* b, const facc* a, int i, int j, int k,
      dE'y/dt = (curl B)_y - 4 pi J'y - v dE'y/dy - v (dE'x/dx + dE'z/dz)
      dE'z/dt = (curl B)_z - 4 pi J'z + v dE'z/dy - v dE'y/dz
    reading: the non-advective cross derivatives are central and averaged to the target
-   component's location; Bx in the tidal term is the 4-point average at By. */
-static void ksb_rhs_acc(const ora_box* b, const facc E[3], const facc B[3], double* const J[3],
-                        double* const out[6])
+   component's location; Bx in the tidal term is the 4-point average at By.
+   The curls read the fields through Ec, Bc (the combined frame scales them, see maxwell_ksb),
+   and kz multiplies v dE'y/dz in dE'z/dt (1 in the shearing box). */
+static void ksb_rhs_acc(const ora_box* b, const facc E[3], const facc B[3], const facc Ec[3],
+                        const facc Bc[3], double kz, double* const J[3], double* const out[6])
 {
     const int nx = b->n[0], ny = b->n[1], nz = b->n[2];
     const int d3 = b->dim == 3;
@@ -730,18 +852,18 @@ static void ksb_rhs_acc(const ora_box* b, const facc E[3], const facc B[3], doub
                 const double v_int = -sO * ((double)i - 0.5 * nx);        /* at x = i */
                 const double v_half = -sO * ((double)i + 0.5 - 0.5 * nx); /* at x = i+1/2 */
                 /* Bx at (i, j+1/2, k+1/2) */
-                out[0][q] = -curlE(b, E, 0, i, j, k) - v_int * up_dy(b, &B[0], i, j, k, v_int);
+                out[0][q] = -curlE(b, Ec, 0, i, j, k) - v_int * up_dy(b, &B[0], i, j, k, v_int);
                 /* By at (i+1/2, j, k+1/2) */
                 double bx_avg = 0.25 * (fv(b, &B[0], i, j, k) + fv(b, &B[0], i + 1, j, k) +
                                         fv(b, &B[0], i, j - 1, k) + fv(b, &B[0], i + 1, j - 1, k));
-                out[1][q] = -curlE(b, E, 1, i, j, k) - v_half * up_dy(b, &B[1], i, j, k, v_half) -
+                out[1][q] = -curlE(b, Ec, 1, i, j, k) - v_half * up_dy(b, &B[1], i, j, k, v_half) -
                             sO * bx_avg;
                 /* Bz at (i+1/2, j+1/2, k) */
-                out[2][q] = -curlE(b, E, 2, i, j, k) - v_half * up_dy(b, &B[2], i, j, k, v_half);
+                out[2][q] = -curlE(b, Ec, 2, i, j, k) - v_half * up_dy(b, &B[2], i, j, k, v_half);
                 /* E'x at (i+1/2, j, k) */
                 double dEy_dx = 0.5 * ((fv(b, &E[1], i + 1, j, k) - fv(b, &E[1], i, j, k)) +
                                        (fv(b, &E[1], i + 1, j - 1, k) - fv(b, &E[1], i, j - 1, k)));
-                out[3][q] = curlB(b, B, 0, i, j, k) - 4.0 * ORA_PI * J[0][q] +
+                out[3][q] = curlB(b, Bc, 0, i, j, k) - 4.0 * ORA_PI * J[0][q] +
                             v_half * up_dy(b, &E[0], i, j, k, -v_half) - v_half * dEy_dx;
                 /* E'y at (i, j+1/2, k) */
                 double dEx_dx = 0.5 * ((fv(b, &E[0], i, j, k) - fv(b, &E[0], i - 1, j, k)) +
@@ -750,15 +872,15 @@ static void ksb_rhs_acc(const ora_box* b, const facc E[3], const facc B[3], doub
                     d3 ? 0.5 * ((fv(b, &E[2], i, j, k) - fv(b, &E[2], i, j, k - 1)) +
                                 (fv(b, &E[2], i, j + 1, k) - fv(b, &E[2], i, j + 1, k - 1)))
                        : 0.0;
-                out[4][q] = curlB(b, B, 1, i, j, k) - 4.0 * ORA_PI * J[1][q] -
+                out[4][q] = curlB(b, Bc, 1, i, j, k) - 4.0 * ORA_PI * J[1][q] -
                             v_int * up_dy(b, &E[1], i, j, k, v_int) - v_int * (dEx_dx + dEz_dz);
                 /* E'z at (i, j, k+1/2) */
                 double dEy_dz =
                     d3 ? 0.5 * ((fv(b, &E[1], i, j, k + 1) - fv(b, &E[1], i, j, k)) +
                                 (fv(b, &E[1], i, j - 1, k + 1) - fv(b, &E[1], i, j - 1, k)))
                        : 0.0;
-                out[5][q] = curlB(b, B, 2, i, j, k) - 4.0 * ORA_PI * J[2][q] +
-                            v_int * up_dy(b, &E[2], i, j, k, -v_int) - v_int * dEy_dz;
+                out[5][q] = curlB(b, Bc, 2, i, j, k) - 4.0 * ORA_PI * J[2][q] +
+                            v_int * up_dy(b, &E[2], i, j, k, -v_int) - v_int * (kz * dEy_dz);
             }
 }
 
@@ -771,34 +893,73 @@ void ora_ksb_rhs(const ora_box* b, double* const E[3], double* const B[3], doubl
         set_acc(&Ba[c], B[c]);
         Ea[c].dys_a = Ba[c].dys_a = dys;
     }
-    ksb_rhs_acc(b, Ea, Ba, J, out);
+    ksb_rhs_acc(b, Ea, Ba, Ea, Ba, 1.0, J, out);
+}
+
+void ora_ksb_rhs_f(const ora_box* b, double* const E[3], double* const B[3], double dys,
+                   double* const J[3], const double d[3], double kz, double* const out[6])
+{
+    facc Ea[3], Ba[3], Ec[3], Bc[3];
+    for (int c = 0; c < 3; c++) {
+        set_acc(&Ea[c], E[c]);
+        set_acc(&Ba[c], B[c]);
+        Ea[c].dys_a = Ba[c].dys_a = dys;
+        Ec[c] = Ea[c];
+        Bc[c] = Ba[c];
+        Ec[c].wa = Bc[c].wa = d[c];
+    }
+    ksb_rhs_acc(b, Ea, Ba, Ec, Bc, kz, J, out);
 }
 
 /* Sec. 2.2: implicit midpoint in time, F^{n+1} = F^n + dt RHS((F^n + F^{n+1})/2, J'),
    solved by the fixed-point iteration F^{k+1} = F^n + dt RHS((F^n + F^k)/2) from F^0 = F^n.
    reading: a fixed number of iterations (maxwell_iters), or, with maxwell_tol > 0, until
    max|F^{k+1} - F^k| <= tol max|F^{k+1}| (at most maxwell_iters).  The x guards of F^n (and of
-   F^0 = F^n) use Delta y_s(t^n), those of every later iterate Delta y_s(t^{n+1}). */
+   F^0 = F^n) use Delta y_s(t^n), those of every later iterate Delta y_s(t^{n+1}).
+   Combined frame (reading): the same step on the expanding-frame fields of Sec. 3.1,
+   F'' = (l/l_c) F_c for the c components of E' and B, with the factors of eqs. EBB/EBE at
+   t^{n+1/2}: the curls act on (1/l) L^2 F'' (d_c = l_c^2/l), the source is the deposited l J';
+   the transport and tidal terms of eqs. OAB/OAE keep their form in the expanding coordinates
+   (x and y scale together) except v dE'y/dz in dE'z/dt, which takes kz = (l_y/l_z)^2.  The
+   step converts F^n at t^n and F^{n+1} back at t^{n+1}. */
 static void maxwell_ksb(ora_box* b, ora_fields* f)
 {
     const int64_t nc = ncells(b);
     const double dt = b->dt;
-    const double tn = (double)b->step * dt;
-    const double dys_n = ora_shear_offset(b, tn), dys_1 = ora_shear_offset(b, tn + dt);
+    const double tn = (double)b->step * dt, th = tn + 0.5 * dt, t1 = tn + dt;
+    const double dys_n = ora_shear_offset(b, tn), dys_1 = ora_shear_offset(b, t1);
+    double sn[3], s1[3], d[3], lh[3];
+    for (int c = 0; c < 3; c++) lh[c] = ora_scale(b, c, th);
+    {
+        double ln[3], l1[3];
+        for (int c = 0; c < 3; c++) {
+            ln[c] = ora_scale(b, c, tn);
+            l1[c] = ora_scale(b, c, t1);
+        }
+        const double elln = ln[0] * ln[1] * ln[2], ell1 = l1[0] * l1[1] * l1[2];
+        const double ellh = lh[0] * lh[1] * lh[2];
+        for (int c = 0; c < 3; c++) {
+            sn[c] = elln / ln[c];
+            s1[c] = ell1 / l1[c];
+            d[c] = lh[c] * lh[c] / ellh;
+        }
+    }
+    const double kz = (lh[1] / lh[2]) * (lh[1] / lh[2]);
     double* Fk = (double*)malloc(sizeof(double) * 6 * nc);
     double* Fn = (double*)malloc(sizeof(double) * 6 * nc);
     double* R = (double*)malloc(sizeof(double) * 6 * nc);
-    for (int c = 0; c < 3; c++) {
-        memcpy(Fn + c * nc, f->B[c], sizeof(double) * nc);
-        memcpy(Fn + (3 + c) * nc, f->E[c], sizeof(double) * nc);
-    }
+    for (int c = 0; c < 3; c++)
+        for (int64_t q = 0; q < nc; q++) {
+            Fn[c * nc + q] = sn[c] * f->B[c][q];
+            Fn[(3 + c) * nc + q] = sn[c] * f->E[c][q];
+        }
     memcpy(Fk, Fn, sizeof(double) * 6 * nc);
     double* outp[6];
     for (int c = 0; c < 6; c++) outp[c] = R + c * nc;
     const int maxit = b->maxwell_iters > 0 ? b->maxwell_iters : 8;
     int it;
     for (it = 0; it < maxit; it++) {
-        facc Ea[3], Ba[3];
+        facc Ea[3], Ba[3], Ec[3], Bc[3];
         for (int c = 0; c < 3; c++) {
             Ba[c].a = Fn + c * nc;
             Ba[c].c = Fk + c * nc;
@@ -808,8 +969,11 @@ static void maxwell_ksb(ora_box* b, ora_fields* f)
             /* F^0 = F^n keeps its own boundary values; later iterates sit at t^{n+1} */
             Ba[c].dys_c = Ea[c].dys_c = it == 0 ? dys_n : dys_1;
             Ba[c].wa = Ba[c].wc = Ea[c].wa = Ea[c].wc = 0.5;
+            Ec[c] = Ea[c];
+            Bc[c] = Ba[c];
+            if (b->frame == ORA_SHEAR_EXPAND) Ec[c].wa = Ec[c].wc = Bc[c].wa = Bc[c].wc = 0.5 * d[c];
         }
-        ksb_rhs_acc(b, Ea, Ba, f->J, outp);
+        ksb_rhs_acc(b, Ea, Ba, Ec, Bc, b->frame == ORA_SHEAR_EXPAND ? kz : 1.0, f->J, outp);
         double dmax = 0.0, fmax = 0.0;
         for (int64_t q = 0; q < 6 * nc; q++) {
             double nv = Fn[q] + dt * R[q];
@@ -824,10 +988,11 @@ static void maxwell_ksb(ora_box* b, ora_fields* f)
         }
     }
     b->last_iters = it;
-    for (int c = 0; c < 3; c++) {
-        memcpy(f->B[c], Fk + c * nc, sizeof(double) * nc);
-        memcpy(f->E[c], Fk + (3 + c) * nc, sizeof(double) * nc);
-    }
+    for (int c = 0; c < 3; c++)
+        for (int64_t q = 0; q < nc; q++) {
+            f->B[c][q] = Fk[c * nc + q] / s1[c];
+            f->E[c][q] = Fk[(3 + c) * nc + q] / s1[c];
+        }
     free(Fk);
     free(Fn);
     free(R);
@@ -835,7 +1000,7 @@ static void maxwell_ksb(ora_box* b, ora_fields* f)
 
 void ora_maxwell(ora_box* b, ora_fields* f)
 {
-    if (b->frame == ORA_SHEAR)
+    if (sheared(b))
         maxwell_ksb(b, f);
     else
         maxwell_leapfrog(b, f);
@@ -1083,7 +1248,7 @@ void ora_f32_move(const ora_box* b, int64_t n, const int32_t* cell, const float*
         float o[3] = {off[p], off[n + p], nd == 3 ? off[2 * n + p] : 0.0f};
         float D[3] = {disp[p], disp[n + p], disp[2 * n + p]};
         float dy = D[1];
-        if (b->frame == ORA_SHEAR) {
+        if (sheared(b)) {
             volatile float xr = ((float)i - half_nx) + o[0];
             volatile float mid = fmaf(0.5f, D[0], xr);
             volatile float vs = -sO * mid;
@@ -1101,7 +1266,7 @@ void ora_f32_move(const ora_box* b, int64_t n, const int32_t* cell, const float*
         if (i >= nx || i < 0) {
             const int out = i >= nx;
             i += out ? -nx : nx;
-            if (b->frame == ORA_SHEAR) {
+            if (sheared(b)) {
                 int d2;
                 o[1] = f32_renorm(o[1], out ? dys_frac : -dys_frac, &d2);
                 j += (out ? dys_int : -dys_int) + d2;
@@ -1164,8 +1329,10 @@ static void make_scalars(const ora_box* b, step_scalars* S)
 
 /* One particle of the step orders of Sec. 2.2 (shearing box), Sec. 3.2 (expanding box),
    Sec. 4.1 (leaky box) and standard PIC: gather at x^n -> push -> deposit displacement
-   (x' - x^n for the shearing box, the primed displacement for the expanding box; deposited
-   when Jt is not NULL) -> shear move and boundaries -> leaky-box displacement and escape. */
+   (x' - x^n for the shearing box, the primed displacement for the expanding box, both for the
+   combined frame: dt L^-1 u'/gamma'; deposited when Jt is not NULL) -> shear move and
+   boundaries -> leaky-box displacement and escape.  In the combined frame the shear move of
+   Sec. 2.2 keeps its form in the expanding coordinates (x and y scale together). */
 /* One particle's step; returns 1 when the shearing-box effective velocity of the move,
    u'/gamma' + v_s (eq. OAx) with v_s = -s Omega0 x at the midpoint x of the move (the velocity
    the shear move uses), exceeds c = 1: the nonrelativistic velocity transformation allows it
@@ -1187,6 +1354,10 @@ static int particle_update(const ora_box* b, const ora_fields* f, const step_sca
     if (b->frame == ORA_SHEAR) {
         double xr = X0[0] - 0.5 * nx;
         ora_push_shear(1, S->q_over_m, dt, b->shear_s, b->omega0, &xr, E, B, u, NULL);
+    } else if (b->frame == ORA_SHEAR_EXPAND) {
+        double xr = X0[0] - 0.5 * nx;
+        ora_push_shear_expand(1, S->q_over_m, dt, b->shear_s, b->omega0, C->lam, b->expand_push,
+                              &xr, E, B, u, NULL);
     } else if (b->frame == ORA_EXPAND) {
         ora_push_expand(1, S->q_over_m, dt, C->lam, b->expand_push, E, B, u);
     } else {
@@ -1196,11 +1367,11 @@ static int particle_update(const ora_box* b, const ora_fields* f, const step_sca
     double D[3];
     for (int c = 0; c < 3; c++) {
         D[c] = dt * u[c] / gam;
-        if (b->frame == ORA_EXPAND) D[c] *= C->linv_h[c];
+        if (expanding(b)) D[c] *= C->linv_h[c];
     }
     double X1[3] = {X0[0] + D[0], X0[1] + D[1], nd == 3 ? X0[2] + D[2] : 0.0};
     if (Jt) deposit_one(b, S->q, X0, X1, D[2], Jt);
-    if (b->frame == ORA_SHEAR) {
+    if (sheared(b)) {
         /* x^{n+1} = x' - s Omega0 (x' + x^n)/2 dt e_y (Sec. 2.2) */
         double xp = X1[0] - 0.5 * nx, xn = X0[0] - 0.5 * nx;
         X1[1] -= C->sO * (xp + xn) / 2.0 * dt;
@@ -1210,10 +1381,10 @@ static int particle_update(const ora_box* b, const ora_fields* f, const step_sca
     }
     if (X1[0] >= nx) {
         X1[0] -= nx;
-        if (b->frame == ORA_SHEAR) X1[1] += C->dys_1;
+        if (sheared(b)) X1[1] += C->dys_1;
     } else if (X1[0] < 0.0) {
         X1[0] += nx;
-        if (b->frame == ORA_SHEAR) X1[1] -= C->dys_1;
+        if (sheared(b)) X1[1] -= C->dys_1;
     }
     X1[0] = wrapd(X1[0], nx);
     X1[1] = wrapd(X1[1], b->n[1]);

@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-enum { ORA_PLAIN = 0, ORA_SHEAR = 1, ORA_EXPAND = 2, ORA_LEAKY = 3 };
+enum { ORA_PLAIN = 0, ORA_SHEAR = 1, ORA_EXPAND = 2, ORA_LEAKY = 3, ORA_SHEAR_EXPAND = 4 };
 enum { ORA_LEAKY_DISPLACEMENT = 0, ORA_LEAKY_PROBABILISTIC = 1 };
 enum { ORA_EXPAND_PRINTED = 0, ORA_EXPAND_EXACT = 1 };
 
@@ -37,10 +37,11 @@ typedef struct ora_box {
     int dim;            /* 2 or 3 */
     int n[3];           /* cells per axis, n[2] = 1 in 2D */
     double dt;          /* time step */
-    int frame;          /* ORA_PLAIN / ORA_SHEAR / ORA_EXPAND / ORA_LEAKY */
+    int frame;          /* ORA_PLAIN / ORA_SHEAR / ORA_EXPAND / ORA_LEAKY / ORA_SHEAR_EXPAND */
     /* shearing box (section 2): v_s = -s*Omega0*x e_y */
     double shear_s, omega0;
-    /* expanding box (section 3): l_d(t) = 1 + adot*t on the axes set in axis_mask */
+    /* expanding box (section 3): l_d(t) = 1 + adot*t on the axes set in axis_mask; the
+       combined frame takes masks that scale x and y together (0, z, xy, xyz) */
     double adot;
     int axis_mask;
     int expand_push;    /* ORA_EXPAND_PRINTED (the method) or ORA_EXPAND_EXACT (3x3 solve) */
@@ -110,6 +111,12 @@ void ora_push_shear(int64_t n, double qm, double dt, double s, double omega0,
 void ora_push_expand(int64_t n, double qm, double dt, const double lam[3], int exact,
                      const double* E, const double* B, double* u);
 double ora_shear_gamma_bar(double A, double K);
+/* shearing and expanding frame combined (reading of the extension named in Sec. 5): the
+   rank-1 S and Coriolis tau~ of eq. OAu_disc with the diagonal Lambda of eq. EBu_disc;
+   exact != 0 solves the 3x3 system instead of the printed-style closed form */
+void ora_push_shear_expand(int64_t n, double qm, double dt, double s, double omega0,
+                           const double lam[3], int exact, const double* xr, const double* E,
+                           const double* B, double* u, double* gbar_out);
 
 /* Esirkepov deposit of n particles moving x0 -> x1 (global coordinates; x1 not wrapped),
    into the extended current grid Jext (3 components, (n0+2*ORA_JG)*n1*n2 each).
@@ -127,6 +134,10 @@ void ora_maxwell(ora_box* b, ora_fields* f);
    use shear offset dys; out = 6 arrays (dB/dt then dE'/dt) */
 void ora_ksb_rhs(const ora_box* b, double* const E[3], double* const B[3], double dys,
                  double* const J[3], double* const out[6]);
+/* the same with the expanding-frame factors of the combined frame: the curls act on d_c F_c,
+   the transport term v dE'y/dz of dE'z/dt carries kz */
+void ora_ksb_rhs_f(const ora_box* b, double* const E[3], double* const B[3], double dys,
+                   double* const J[3], const double d[3], double kz, double* const out[6]);
 
 /* charge density at nodes of n particles (CIC) into rho (n0*n1*n2), added */
 void ora_charge(const ora_box* b, int64_t n, double q, const double* x, const double* y,

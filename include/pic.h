@@ -47,7 +47,16 @@ typedef enum pic_status {
     PIC_ECAP = -5     /* particle count above the species capacity */
 } pic_status;
 
-enum pic_frame { PIC_FRAME_PLAIN = 0, PIC_FRAME_SHEAR = 1, PIC_FRAME_EXPAND = 2, PIC_FRAME_LEAKY = 3 };
+enum pic_frame { PIC_FRAME_PLAIN = 0, PIC_FRAME_SHEAR = 1, PIC_FRAME_EXPAND = 2, PIC_FRAME_LEAKY = 3,
+                 PIC_FRAME_SHEAR_EXPAND = 4 };
+/* PIC_FRAME_SHEAR_EXPAND: the shearing box of Sec. 2 in the expanding coordinates of Sec. 3 (the
+   combination the conclusion, Sec. 5, names).  The push solves eq. OAu_disc with the Lambda of
+   eq. EBu_disc added (Sherman-Morrison of the rank-1 S around the printed B^(Lambda) inverse),
+   positions move by dt L^-1 u'/gamma' plus the shear move, and the field step is the implicit
+   midpoint of Sec. 2.2 on the expanding-frame fields (l/l_c) F_c with the (1/l) L^2 curl factors
+   of eqs. EBB/EBE.  x and y scale together: expand_axis_mask 0, 4 (z), 3 (xy) or 7; other masks
+   are PIC_EINVAL.  Boxes of this frame step alone (a batched step containing one is PIC_EINVAL)
+   and take the one-thread-per-cell field sweeps. */
 enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 
 /* pic_gather_push flags */

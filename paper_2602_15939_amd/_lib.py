@@ -12,7 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ECAP = 0, -1, -2, -3, -4, -5
-FRAME_PLAIN, FRAME_SHEAR, FRAME_EXPAND, FRAME_LEAKY = 0, 1, 2, 3
+FRAME_PLAIN, FRAME_SHEAR, FRAME_EXPAND, FRAME_LEAKY, FRAME_SHEAR_EXPAND = 0, 1, 2, 3, 4
 LEAKY_DISPLACEMENT, LEAKY_PROBABILISTIC = 0, 1
 FUSE_DEPOSIT = 1
 REMAP_FIELDS, REMAP_CURRENT = 1, 2

@@ -196,6 +196,16 @@ bool escapes(const pic_box_desc* d)
 {
     return d->frame == PIC_FRAME_LEAKY || (d->flags & PIC_BOX_ESCAPE) != 0;
 }
+// frames with the shearing-box geometry (Sec. 2), and with the expanding-box factors (Sec. 3);
+// the combined frame has both
+bool sheared(const pic_box_desc* d)
+{
+    return d->frame == PIC_FRAME_SHEAR || d->frame == PIC_FRAME_SHEAR_EXPAND;
+}
+bool expanding(const pic_box_desc* d)
+{
+    return d->frame == PIC_FRAME_EXPAND || d->frame == PIC_FRAME_SHEAR_EXPAND;
+}
 
 template <class T>
 int32_t dalloc(pic_box* b, T*& p, size_t count)
@@ -229,10 +239,11 @@ int ceil_log2(int v)
 
 double time_of(const pic_box* b, int64_t step) { return (double)step * b->d.dt; }
 
-// Sec. 2.1: Delta y_s(t) = s Omega0 (x_o - x_i) t, reduced modulo n[1]
+// Sec. 2.1: Delta y_s(t) = s Omega0 (x_o - x_i) t, reduced modulo n[1] (the combined frame
+// scales x and y together, so the offset keeps its form in the expanding coordinates)
 double shear_offset(const pic_box* b, double t)
 {
-    if (b->d.frame != PIC_FRAME_SHEAR) return 0.0;
+    if (!sheared(&b->d)) return 0.0;
     const double ny = b->n[1];
     double v = std::fmod(b->d.shear_s * b->d.shear_omega0 * (double)b->n[0] * t, ny);
     if (v < 0) v += ny;
@@ -243,7 +254,7 @@ double shear_offset(const pic_box* b, double t)
 // Sec. 3.1: l_d(t) = 1 + adot t on the expanding axes
 double scale_of(const pic_box* b, int axis, double t)
 {
-    if (b->d.frame != PIC_FRAME_EXPAND || !((b->d.expand_axis_mask >> axis) & 1)) return 1.0;
+    if (!expanding(&b->d) || !((b->d.expand_axis_mask >> axis) & 1)) return 1.0;
     return 1.0 + b->d.expand_adot * t;
 }
 
@@ -352,7 +363,7 @@ StepDev make_step(pic_box* b)
     }
     for (int k = 0; k < 3; k++) {
         const double rate =
-            (b->d.frame == PIC_FRAME_EXPAND && ((b->d.expand_axis_mask >> k) & 1)) ? b->d.expand_adot : 0.0;
+            (expanding(&b->d) && ((b->d.expand_axis_mask >> k) & 1)) ? b->d.expand_adot : 0.0;
         const double lam = -0.5 * dt * rate / scale_of(b, k, tn);  // Lambda at t^n
         P.lam1p[k] = (float)(1.0 + lam);
         P.ltil[k] = (float)((1.0 + lam) / (1.0 - lam));
@@ -441,7 +452,7 @@ void set_tiling(pic_box* b, const int tile[3])
         b->mg.lt[k] = b->tl.lt[k];
         if (b->n[k] % tile[k] != 0 || b->tl.nt[k] == 2) b->mig_ok = false;
     }
-    if (b->d.frame == PIC_FRAME_SHEAR && b->tl.nt[0] < 3) b->mig_ok = false;
+    if (sheared(&b->d) && b->tl.nt[0] < 3) b->mig_ok = false;
     b->mg.n_tiles = b->tl.n_tiles;
 }
 
@@ -490,7 +501,7 @@ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 // dys_int = floor(Delta y_s(t^{n+1})): the new y tile is within one of (old tile + shift).
 void set_migration_shift(pic_box* b, int dys_int)
 {
-    if (b->d.frame != PIC_FRAME_SHEAR) {
+    if (!sheared(&b->d)) {
         b->mg.cy_out = b->mg.cy_in = 0;
         return;
     }
@@ -558,14 +569,14 @@ float* const* field_ptrs(pic_box* b) { return b->set[b->cur_set]; }
 
 int32_t fill_field_guards(pic_box* b, double t)
 {
-    return hip_fail(fill_guards(b->G, field_ptrs(b), 6, b->d.frame == PIC_FRAME_SHEAR ? 1 : 0,
+    return hip_fail(fill_guards(b->G, field_ptrs(b), 6, sheared(&b->d) ? 1 : 0,
                                 shear_offset(b, t), b->st));
 }
 
 int32_t fold_box(pic_box* b)
 {
     const double th = time_of(b, b->step) + 0.5 * b->d.dt;
-    const int shear = b->d.frame == PIC_FRAME_SHEAR;
+    const int shear = sheared(&b->d) ? 1 : 0;
     if (fold_current(b->G, b->J, b->Jt, shear, b->d.shear_s * b->d.shear_omega0, b->d.dt,
                      shear_offset(b, th), b->st) != hipSuccess)
         return PIC_EDEVICE;
@@ -599,7 +610,7 @@ int32_t maxwell_box(pic_box* b)
     const double dt = b->d.dt;
     const double tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
     hipStream_t st = b->st;
-    if (b->d.frame == PIC_FRAME_SHEAR) {
+    if (sheared(&b->d)) {
         // implicit midpoint by fixed-point sweeps from F^0 = F^n (with its own guards, at
         // t^n); every later iterate has its x images at t^{n+1}.  Three field sets: F^n (free
         // once the first sweep has read it), C, and the iterates alternating with F^n's set.
@@ -608,12 +619,38 @@ int32_t maxwell_box(pic_box* b)
         const double dys1 = shear_offset(b, t1);
         const double dys0 = shear_offset(b, tn);
         const bool tol = b->d.maxwell_tol > 0.0;
+        // combined frame: the sweeps run on the expanding-frame fields (l/l_c) F_c, converted
+        // from F^n at t^n here and back at t^{n+1} after the last sweep, with the curl factors
+        // l_c^2/l and kz = (l_y/l_z)^2 at t^{n+1/2}; one-thread-per-cell sweeps only
+        const bool comb = b->d.frame == PIC_FRAME_SHEAR_EXPAND;
+        float back[3] = {1.f, 1.f, 1.f}, dfac[3] = {1.f, 1.f, 1.f}, kz = 1.f;
+        if (comb) {
+            double ln[3], lh[3], l1[3];
+            for (int c = 0; c < 3; c++) {
+                ln[c] = scale_of(b, c, tn);
+                lh[c] = scale_of(b, c, th);
+                l1[c] = scale_of(b, c, t1);
+            }
+            const double elln = ln[0] * ln[1] * ln[2], ellh = lh[0] * lh[1] * lh[2];
+            const double ell1 = l1[0] * l1[1] * l1[2];
+            float fwd[3];
+            for (int c = 0; c < 3; c++) {
+                fwd[c] = (float)(elln / ln[c]);
+                back[c] = (float)(l1[c] / ell1);
+                dfac[c] = (float)(lh[c] * lh[c] / ellh);
+            }
+            kz = (float)((lh[1] / lh[2]) * (lh[1] / lh[2]));
+            if (scale_fields(b->G, b->set[sn], fwd, st) != hipSuccess ||
+                fill_guards(b->G, b->set[sn], 6, 1, dys0, st) != hipSuccess)
+                return PIC_EDEVICE;
+        }
+        const bool staged = ksb_staged(b->G) && !comb;
         if (tol && zero_floats(reinterpret_cast<float*>(b->conv), 2 * K, st) != hipSuccess)
             return PIC_EDEVICE;
         int sk = sn, so = sb2;
         // fixed count on the staged 3D grids: two sweeps per pass over memory (the same
         // iterates bit for bit), a last single sweep when the count is odd
-        const bool paired = !tol && ksb_pass_fits(b->G) && K >= 2;
+        const bool paired = !tol && !comb && ksb_pass_fits(b->G) && K >= 2;
         for (int k = 0; k < K; k++) {
             const bool pass = paired && k + 1 < K;
             KsbDev Kd{};
@@ -637,24 +674,30 @@ int32_t maxwell_box(pic_box* b)
                 Kd.tol = (float)b->d.maxwell_tol;
                 Kd.k = k;
             }
+            Kd.expand = comb ? 1 : 0;
+            for (int c = 0; c < 3; c++) Kd.dfac[c] = dfac[c];
+            Kd.kz = kz;
             if (pass) {
                 const double fl = std::floor(dys1);
                 Kd.y1_int = (int)fl;
                 Kd.y1_w = (float)(dys1 - fl);
                 if (ksb_pass(Kd, k == 0, st) != hipSuccess) return PIC_EDEVICE;
                 k++;
-            } else if (ksb_sweep(Kd, k == 0, st) != hipSuccess) {
+            } else if ((staged ? ksb_sweep(Kd, k == 0, st) : ksb_sweep_unstaged(Kd, k == 0, st)) != hipSuccess) {
                 return PIC_EDEVICE;
             }
             if (tol && k == K - 1 && ksb_finalize(ksb_fin(b, K, so), st) != hipSuccess)
                 return PIC_EDEVICE;
             // the staged 3D sweep reads its whole halo at the (shearing-)periodic images: then
             // only the last iterate's guards are filled (for the push)
-            if ((!ksb_staged(b->G) || k == K - 1) && fill_guards(b->G, b->set[so], 6, 1, dys1, st) != hipSuccess)
+            if ((!staged || k == K - 1) && fill_guards(b->G, b->set[so], 6, 1, dys1, st) != hipSuccess)
                 return PIC_EDEVICE;
             sk = so;
             so = so == sb2 ? sn : sb2;
         }
+        if (comb && (scale_fields(b->G, b->set[sk], back, st) != hipSuccess ||
+                     fill_guards(b->G, b->set[sk], 6, 1, dys1, st) != hipSuccess))
+            return PIC_EDEVICE;
         b->cur_set = sk;
         b->last_sweeps = tol ? -1 : K;
         return PIC_OK;
@@ -878,6 +921,8 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
         pic_box* b = boxes[i];
         if (b->st != st || b->deposit_pending) return b->st != st ? PIC_EINVAL : PIC_ESTATE;
         if (!batch_tile_supported(b->dim, b->tile)) return PIC_EINVAL;
+        // the combined shearing and expanding frame steps one box at a time
+        if (b->d.frame == PIC_FRAME_SHEAR_EXPAND) return PIC_EINVAL;
         for (int j = 0; j < i; j++)
             if (boxes[j] == b) return PIC_EINVAL;
     }
@@ -1281,7 +1326,10 @@ int32_t init_box(const pic_box_desc* d, const int32_t pitch[2], pic_box*& out)
     for (int k = 0; k < d->dim; k++)
         if (n[k] < 4) return PIC_EINVAL;
     if (!(d->dt > 0) || d->dt * std::sqrt((double)d->dim) >= 1.0) return PIC_EINVAL;
-    if (d->frame < 0 || d->frame > 3) return PIC_EINVAL;
+    if (d->frame < 0 || d->frame > 4) return PIC_EINVAL;
+    // the combined frame scales x and y together (axis masks 0, z, xy, xyz)
+    if (d->frame == PIC_FRAME_SHEAR_EXPAND && ((d->expand_axis_mask & 3) == 1 || (d->expand_axis_mask & 3) == 2))
+        return PIC_EINVAL;
     if (d->n_species < 1 || d->n_species > 2) return PIC_EINVAL;
     if (d->maxwell_iters < 0 || d->maxwell_iters > kKsbMaxSweeps || !(d->maxwell_tol >= 0.0) ||
         !(d->maxwell_tol < 1.0))
@@ -1346,7 +1394,7 @@ int32_t init_box(const pic_box_desc* d, const int32_t pitch[2], pic_box*& out)
     b->origin = (int64_t)kRowAlign + sy * G.g[1] + sz * G.g[2];
     b->nsp = d->n_species;
     b->track_ids = (d->flags & PIC_BOX_TRACK_IDS) || escapes(d);
-    b->nsets = d->frame == PIC_FRAME_SHEAR ? 3 : 1;
+    b->nsets = sheared(d) ? 3 : 1;
     out = b;
     return PIC_OK;
 }
@@ -1384,7 +1432,7 @@ int32_t alloc_all(pic_box* b, const pic_box_mem* m)
         for (int c = 0; c < 6 && !r; c++) r = field(b->set[s][c], m ? m->field[s][c] : nullptr);
     for (int c = 0; c < 3 && !r; c++) r = field(b->J[c], m ? m->current[0][c] : nullptr);
     b->J0 = b->J[0];
-    if (d->frame == PIC_FRAME_SHEAR)
+    if (sheared(d))
         for (int c = 0; c < 3 && !r; c++) r = field(b->Jt[c], m ? m->current[1][c] : nullptr);
     for (int s = 0; s < b->nsp && !r; s++) {
         Species& S = b->sp[s];
@@ -1434,7 +1482,7 @@ int32_t alloc_all(pic_box* b, const pic_box_mem* m)
     }
     if (!r) r = dalloc(b, b->err, 4);
     if (!r) r = dalloc(b, b->ctr, 4);
-    if (!r && d->frame == PIC_FRAME_SHEAR) r = dalloc(b, b->conv, kKsbConvWords);
+    if (!r && sheared(d)) r = dalloc(b, b->conv, kKsbConvWords);
     if (!r) r = dalloc(b, b->red_part, (size_t)10 * kRedBlocks);
     if (!r) r = dalloc(b, b->red_out, 16);
     if (!r) r = dalloc(b, b->hist_edges, kHistMaxBins + 1);
@@ -1523,7 +1571,7 @@ int32_t pic_box_layout(const pic_box_desc* d, pic_box_layout_info* out)
     if (!r) {
         out->workspace_bytes = (int64_t)ws;
         out->field_sets = b->nsets;
-        out->current_arrays = d->frame == PIC_FRAME_SHEAR ? 2 : 1;
+        out->current_arrays = sheared(d) ? 2 : 1;
         out->field_pitch_min[0] = b->G.sy;
         out->field_pitch_min[1] = b->G.sz;
         out->field_rows = (b->n[1] + 2 * b->G.g[1]) * (b->n[2] + 2 * b->G.g[2]);
@@ -1809,7 +1857,7 @@ int32_t pic_maxwell_step(pic_box* const* boxes, int32_t nb, uint32_t)
         r = maxwell_box(b);
         if (!r) {
             b->step += 1;
-            if (b->d.frame != PIC_FRAME_SHEAR) r = fill_field_guards(b, time_of(b, b->step));
+            if (!sheared(&b->d)) r = fill_field_guards(b, time_of(b, b->step));
         }
     }
     return r;
@@ -1929,7 +1977,7 @@ int32_t pic_step(pic_box* const* boxes, int32_t nb, uint32_t flags)
         if (!r) r = maxwell_box(b);
         if (!r) {
             b->step += 1;
-            if (b->d.frame != PIC_FRAME_SHEAR) r = fill_field_guards(b, time_of(b, b->step));
+            if (!sheared(&b->d)) r = fill_field_guards(b, time_of(b, b->step));
         }
     }
     return r;
@@ -2103,7 +2151,7 @@ int32_t pic_box_get(pic_box* b, pic_box_info* info)
     info->dys = shear_offset(b, info->t);
     info->a = 1.0;
     for (int k = 0; k < 3; k++)
-        if (b->d.frame == PIC_FRAME_EXPAND && ((b->d.expand_axis_mask >> k) & 1)) info->a = scale_of(b, k, info->t);
+        if (expanding(&b->d) && ((b->d.expand_axis_mask >> k) & 1)) info->a = scale_of(b, k, info->t);
     return PIC_OK;
 }
 

@@ -168,6 +168,49 @@ __device__ inline f3 push_expand(f3 u, f3 E, f3 B, float qm_hdt, const float lam
     return up + eps;
 }
 
+// Combined shearing and expanding frame (the extension named in the conclusion, Sec. 5;
+// reading): (1 - Lambda) u+ - u+ x tau~ - S u+ = (1 + Lambda) u- + u- x tau~ + S u-, i.e.
+// eq. OAu_disc with the diagonal Lambda of eq. EBu_disc.  A u = (1 - Lambda) u - u x tau~ is
+// inverted as the expanding push does, A^-1 r = R_t((1 - Lambda)^-1 r), t = (1 - Lambda)^-1
+// tau~, so A^-1((1 + Lambda) v + v x tau~) is the printed B^(Lambda)(v); the rank-1 S is added
+// by the Sherman-Morrison formula, as the shearing push adds it to R:
+//   w = B^(Lambda)(u-) + (s2.u-) A^-1 e_y,  u+ = w + (s2.w) A^-1 e_y / (1 - s2.A^-1 e_y).
+// gamma-bar solves g^2 = 1 + ((1+Lambda)u-)^2 + 2 alpha1 u-_x u-_y + 2 alpha2 (u-.eps) u-_y / g:
+// the shearing push's first-order approximation (with (1+Lambda) u- in place of u-) and one
+// fixed-point refinement.  Lambda = 0 is the shearing push, alpha = Omega0 = 0 the expanding.
+__device__ inline f3 push_shear_expand(f3 u, f3 E, f3 B, float qm_hdt, float alpha1, float alpha2,
+                                       float om_dt, const float lam1p[3], const float ltil[3],
+                                       const float tfac[3])
+{
+    const f3 eps = qm_hdt * E;
+    const f3 um = u + eps;
+    const f3 lu = mk(lam1p[0] * um.x, lam1p[1] * um.y, lam1p[2] * um.z);
+    const float ll = dot(lu, lu);
+    const float ue = dot(um, eps);
+    const float A = ll + 2.f * alpha1 * um.x * um.y;
+    const float K = 2.f * alpha2 * ue * um.y;
+    const float g0 = fsqrt(1.f + ll);
+    float g = g0 + (alpha1 * um.x * um.y * g0 + alpha2 * ue * um.y) * rcp(1.f + ll);
+    g = fsqrt(1.f + A + K * rcp(g));
+    const float ig = rcp(g);
+    f3 tt = (qm_hdt * ig) * B;
+    tt.z += om_dt;
+    const f3 t = mk(tfac[0] * tt.x, tfac[1] * tt.y, tfac[2] * tt.z);
+    const f3 et = ig * eps;
+    const f3 s2 = mk(alpha1 + alpha2 * et.x, alpha2 * et.y, alpha2 * et.z);
+    const float d = rcp(1.f + dot(t, t));
+    const f3 v = mk((1.f + ltil[0]) * um.x, (1.f + ltil[1]) * um.y, (1.f + ltil[2]) * um.z);
+    const f3 c1 = cross(v, t);
+    const f3 c2 = cross(c1, t);
+    const f3 Bu = mk(ltil[0] * um.x, ltil[1] * um.y, ltil[2] * um.z) + d * (c1 + c2);
+    // A^-1 e_y = R_t(e_y) / (1 - Lambda_y), R_t(e_y) written out
+    const f3 Ae = tfac[1] * mk(d * (t.z + t.x * t.y), 1.f - d * (t.x * t.x + t.z * t.z), d * (t.y * t.z - t.x));
+    const float gg = dot(s2, Ae);
+    const f3 w = Bu + dot(s2, um) * Ae;
+    const f3 up = w + (dot(s2, w) * rcp(1.f - gg)) * Ae;
+    return up + eps;
+}
+
 // ------------------------------------------------------------------ positions
 // In-cell offset renormalisation after s = off + delta (|delta| < 1), in FP32:
 // s >= 1 -> (+1, s-1) exact; s < 0 -> t = s+1, (-1, t) if t < 1 else (0, 0).  Written with
@@ -546,22 +589,25 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             const float xr = __fadd_rn(__fsub_rn((float)cx, P.half_nx), ox);  // radial x (shearing box)
             if (FRAME == kShear)
                 u = push_shear(u, E, B, S.qm_hdt, P.alpha1, P.sO * xr, P.om_dt);
+            else if (FRAME == kShearExpand)
+                u = push_shear_expand(u, E, B, S.qm_hdt, P.alpha1, P.sO * xr, P.om_dt, P.lam1p,
+                                      P.ltil, P.tfac);
             else if (FRAME == kExpand)
                 u = push_expand(u, E, B, S.qm_hdt, P.lam1p, P.ltil, P.tfac);
             else
                 u = push_boris(u, E, B, S.qm_hdt);
 
             // ---- displacement of the deposit (comoving for the shearing box, primed for the
-            // expanding box)
+            // expanding box, both for the combined frame)
             const float ig = rsq1(1.f + dot(u, u));
             const float hs = P.dt * ig;
             f3 D = hs * u;
-            if (FRAME == kExpand) D = mk(D.x * P.linv[0], D.y * P.linv[1], D.z * P.linv[2]);
+            if (frame_expanding(FRAME)) D = mk(D.x * P.linv[0], D.y * P.linv[1], D.z * P.linv[2]);
             // y increment of the position: the shearing box adds the shear move
             // y -= s Omega0 (x' + x^n)/2 dt (Sec. 2.2), x' + x^n = 2 x^n + D.x, each operation
             // rounded as written (the FP32 integer layer of the oracle repeats it bit for bit)
             float dyt = D.y, vs = 0.f;
-            if (FRAME == kShear) {
+            if (frame_sheared(FRAME)) {  // the combined frame: x and y scale together
                 vs = __fmul_rn(-P.sO, __fmaf_rn(0.5f, D.x, xr));  // v_s at the midpoint x
                 dyt = __fmaf_rn(P.dt, vs, D.y);
             }
@@ -600,7 +646,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
 
             // ---- new position: x' = x^n + D, then (shearing box) the shear move
             // y -= s Omega0 (x' + x^n)/2 dt (Sec. 2.2)
-            if (FRAME == kShear) {
+            if (frame_sheared(FRAME)) {
                 // the effective velocity u'/gamma' + v_s e_y (eq. OAx) can exceed c for
                 // relativistic particles (Sec. 2.1): counted, not corrected.  With
                 // |u'|^2/gamma'^2 = 1 - 1/gamma'^2, |v|^2 > 1 reads vs (2 u'_y/gamma' + vs) > 1/gamma'^2.
@@ -617,7 +663,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 // y + Delta y_s(t^{n+1}); leaving through x_i re-enters at x_o with y - Delta y_s
                 const bool out = ncx >= nx;
                 ncx += out ? -nx : nx;
-                if (FRAME == kShear) {
+                if (frame_sheared(FRAME)) {
                     int d2;
                     noy = renorm(__fadd_rn(noy, out ? P.dys_frac : -P.dys_frac), d2);
                     // ncy in [-1, ny], dys_int in [0, ny): the sum lies in (-ny-2, 2ny+1)
@@ -699,7 +745,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
                 const int dx = P.mg.nt[0] == 1 ? 0 : (rx + dcx) >> P.tl.lt[0];
                 int dy = P.mg.nt[1] == 1 ? 0 : (ry + dcy) >> P.tl.lt[1];
                 const int dz = (DIM == 2 || P.mg.nt[2] == 1) ? 0 : (rz + dcz) >> P.tl.lt[2];
-                if (FRAME == kShear && xwrap && P.mg.nt[1] > 1) {
+                if (frame_sheared(FRAME) && xwrap && P.mg.nt[1] > 1) {
                     int r = (ncy >> P.tl.lt[1]) - tsy - (dx > 0 ? P.mg.cy_out : P.mg.cy_in);
                     const int n1 = P.mg.nt[1];  // r lies in (-2 n1, 2 n1)
                     if (r < 0) r += n1;
@@ -732,7 +778,7 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
             for (int o = 32; o > 0; o >>= 1) nesc += __shfl_xor(nesc, o, 64);
             if ((tid & 63) == 0 && nesc) atomicAdd(&P.ctr[1], (unsigned long long)nesc);
         }
-        if (FRAME == kShear && P.count_sl) {
+        if (frame_sheared(FRAME) && P.count_sl) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) nsl += __shfl_xor(nsl, o, 64);
             if ((tid & 63) == 0 && nsl) atomicAdd(&P.ctr[3], (unsigned long long)nsl);
@@ -844,6 +890,9 @@ static hipError_t launch_shape(const StepDev& P, int fuse, hipStream_t st)
         break;
     case kLeaky:
         gpd_kernel<DIM, TX, TY, TZ, kLeaky, NT><<<grid, block, 0, st>>>(P, fuse);
+        break;
+    case kShearExpand:
+        gpd_kernel<DIM, TX, TY, TZ, kShearExpand, NT><<<grid, block, 0, st>>>(P, fuse);
         break;
     default:
         gpd_kernel<DIM, TX, TY, TZ, kPlain, NT><<<grid, block, 0, st>>>(P, fuse);

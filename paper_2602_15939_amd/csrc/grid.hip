@@ -381,6 +381,38 @@ __device__ inline void ksb_operator(const Acc& V, float v0, float vh, float sO, 
     L[EZ] = cBz + v0 * updy(EZ, -v0) - v0 * dEy_dz;
 }
 
+// The operator of the combined shearing and expanding frame (reading: the step of Sec. 2.2 on
+// the expanding-frame fields of Sec. 3.1): the curls act on (1/l) L^2 F, i.e. d[c] F_c, as in
+// eqs. EBB/EBE; the transport and tidal terms keep their form in the expanding coordinates (x
+// and y scale together) except v dE'y/dz in dE'z/dt, which takes kz = (l_y/l_z)^2.
+template <bool D3, class Acc>
+__device__ inline void ksb_operator_f(const Acc& V, float v0, float vh, float sO, const float d[3],
+                                      float kz, float L[6])
+{
+    const float cEx = d[2] * (V(EZ, 0, 1, 0) - V(EZ, 0, 0, 0)) - (D3 ? d[1] * (V(EY, 0, 0, 1) - V(EY, 0, 0, 0)) : 0.f);
+    const float cEy = (D3 ? d[0] * (V(EX, 0, 0, 1) - V(EX, 0, 0, 0)) : 0.f) - d[2] * (V(EZ, 1, 0, 0) - V(EZ, 0, 0, 0));
+    const float cEz = d[1] * (V(EY, 1, 0, 0) - V(EY, 0, 0, 0)) - d[0] * (V(EX, 0, 1, 0) - V(EX, 0, 0, 0));
+    const float cBx = d[2] * (V(BZ, 0, 0, 0) - V(BZ, 0, -1, 0)) - (D3 ? d[1] * (V(BY, 0, 0, 0) - V(BY, 0, 0, -1)) : 0.f);
+    const float cBy = (D3 ? d[0] * (V(BX, 0, 0, 0) - V(BX, 0, 0, -1)) : 0.f) - d[2] * (V(BZ, 0, 0, 0) - V(BZ, -1, 0, 0));
+    const float cBz = d[1] * (V(BY, 0, 0, 0) - V(BY, -1, 0, 0)) - d[0] * (V(BX, 0, 0, 0) - V(BX, 0, -1, 0));
+    const float bxa = 0.25f * (V(BX, 0, 0, 0) + V(BX, 1, 0, 0) + V(BX, 0, -1, 0) + V(BX, 1, -1, 0));
+    const float dEy_dx = 0.5f * ((V(EY, 1, 0, 0) - V(EY, 0, 0, 0)) + (V(EY, 1, -1, 0) - V(EY, 0, -1, 0)));
+    const float dEx_dx = 0.5f * ((V(EX, 0, 0, 0) - V(EX, -1, 0, 0)) + (V(EX, 0, 1, 0) - V(EX, -1, 1, 0)));
+    const float dEz_dz =
+        D3 ? 0.5f * ((V(EZ, 0, 0, 0) - V(EZ, 0, 0, -1)) + (V(EZ, 0, 1, 0) - V(EZ, 0, 1, -1))) : 0.f;
+    const float dEy_dz =
+        D3 ? 0.5f * ((V(EY, 0, 0, 1) - V(EY, 0, 0, 0)) + (V(EY, 0, -1, 1) - V(EY, 0, -1, 0))) : 0.f;
+    auto updy = [&](int c, float w) {
+        return w > 0.f ? V(c, 0, 0, 0) - V(c, 0, -1, 0) : V(c, 0, 1, 0) - V(c, 0, 0, 0);
+    };
+    L[BX] = -cEx - v0 * updy(BX, v0);
+    L[BY] = -cEy - vh * updy(BY, vh) - sO * bxa;
+    L[BZ] = -cEz - vh * updy(BZ, vh);
+    L[EX] = cBx + vh * updy(EX, -vh) - vh * dEy_dx;
+    L[EY] = cBy - v0 * updy(EY, v0) - v0 * (dEx_dx + dEz_dz);
+    L[EZ] = cBz + v0 * updy(EZ, -v0) - v0 * (kz * dEy_dz);
+}
+
 // ---- tolerance mode of the sweeps
 // a sweep's (largest change, largest value) pair meets the tolerance (a finite change only)
 __device__ inline bool ksb_met(const uint32_t* pair, float tol)
@@ -467,10 +499,16 @@ __device__ __attribute__((always_inline)) inline void ksb_sweep_body(const KsbDe
         const float v0 = -K.sO * ((float)x - K.half_nx);         // at x = i
         const float vh = -K.sO * ((float)x + 0.5f - K.half_nx);  // at x = i + 1/2
         float L[6], Fk[6];
-        if (G.dim == 3)
+        if (K.expand) {
+            if (G.dim == 3)
+                ksb_operator_f<true>(V, v0, vh, K.sO, K.dfac, K.kz, L);
+            else
+                ksb_operator_f<false>(V, v0, vh, K.sO, K.dfac, K.kz, L);
+        } else if (G.dim == 3) {
             ksb_operator<true>(V, v0, vh, K.sO, L);
-        else
+        } else {
             ksb_operator<false>(V, v0, vh, K.sO, L);
+        }
 #pragma unroll
         for (int c = 0; c < 6; c++) Fk[c] = F[c][i];
         ksb_store<FIRST>(K, i, L, Fk, dm, fm);
@@ -1022,6 +1060,26 @@ PIC_BATCHED_KERNEL(ksb_final, KsbFin, kBlock)
 #pragma clang fp contract(fast)
 
 // ------------------------------------------------------------------ utilities
+// interior of six components (B then E) times f[c % 3] (the expanding-frame conversion of the
+// combined frame's field step)
+struct ScaleArgs {
+    GridDev G;
+    float* F[6];
+    float f[3];
+};
+__global__ __launch_bounds__(kBlock) void scale_fields_kernel(ScaleArgs a)
+{
+    const GridDev& G = a.G;
+    const int64_t n = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+        int x, y, z;
+        cell_of(G, t, x, y, z);
+        const int64_t i = gidx(G, x, y, z);
+#pragma unroll
+        for (int c = 0; c < 6; c++) a.F[c][i] *= a.f[c % 3];
+    }
+}
+
 // grid-stride, 16-byte stores where the array is 16-byte aligned (the batched launch gives
 // every word its own thread, so most of its threads find nothing to do)
 __device__ __attribute__((always_inline)) inline void zero_body(const ZeroArgs& a, int blk, int nblk, int)
@@ -1249,6 +1307,15 @@ hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
     }
     return hipGetLastError();
 }
+hipError_t ksb_sweep_unstaged(const KsbDev& K, bool first, hipStream_t st)
+{
+    const unsigned nb = nblocks((int64_t)K.G.n[0] * K.G.n[1] * K.G.n[2]);
+    if (first)
+        ksb_first_kernel<<<nb, kBlock, 0, st>>>(K);
+    else
+        ksb_next_kernel<<<nb, kBlock, 0, st>>>(K);
+    return hipGetLastError();
+}
 hipError_t ksb_pass(const KsbDev& K, bool first, hipStream_t st)
 {
     if (!ksb_pass_fits(K.G) || K.conv) return hipErrorInvalidValue;
@@ -1258,6 +1325,15 @@ hipError_t ksb_pass(const KsbDev& K, bool first, hipStream_t st)
         ksb_pass3_kernel<true><<<grid, PN, 0, st>>>(K);
     else
         ksb_pass3_kernel<false><<<grid, PN, 0, st>>>(K);
+    return hipGetLastError();
+}
+hipError_t scale_fields(const GridDev& G, float* const* F, const float f[3], hipStream_t st)
+{
+    ScaleArgs a{};
+    a.G = G;
+    for (int c = 0; c < 6; c++) a.F[c] = F[c];
+    for (int c = 0; c < 3; c++) a.f[c] = f[c];
+    scale_fields_kernel<<<std::min(nblocks((int64_t)G.n[0] * G.n[1] * G.n[2]), kStrideBlocks), kBlock, 0, st>>>(a);
     return hipGetLastError();
 }
 hipError_t ksb_finalize(const KsbFin& F, hipStream_t st)

@@ -14,7 +14,10 @@ constexpr int kBlock = 256;    // threads per workgroup of the particle kernels 
 constexpr int kMjBins = 4096;  // reinjection sampler: bulk inverse-CDF bins
 constexpr int kMjTail = 64;    // reinjection sampler: tail bins in -log2(1-p)
 
-enum Frame { kPlain = 0, kShear = 1, kExpand = 2, kLeaky = 3 };
+enum Frame { kPlain = 0, kShear = 1, kExpand = 2, kLeaky = 3, kShearExpand = 4 };
+// frames with the shearing-box geometry, and with the expanding-box scale factors
+constexpr bool frame_sheared(int f) { return f == kShear || f == kShearExpand; }
+constexpr bool frame_expanding(int f) { return f == kExpand || f == kShearExpand; }
 
 // Particle cells are packed as i | j << b0 | k << (b0+b1) with b_d = ceil(log2 n_d),
 // so decoding is shifts and masks.  A dead particle has cell -1.
@@ -349,6 +352,12 @@ struct KsbDev {
     // intermediate iterate's x images, Delta y_s at t^{n+1} = y1_int + y1_w
     int y1_int;
     float y1_w;
+    // combined shearing and expanding frame (one-thread-per-cell sweeps only): the iterates are
+    // the expanding-frame fields, the curls act on dfac[c] F_c and kz multiplies the z
+    // transport of E'_y in dE'_z/dt
+    int expand;
+    float dfac[3];
+    float kz;
 };
 constexpr int kKsbMaxSweeps = 64;
 // words of a box's convergence record: kKsbMaxSweeps pairs, then the sweep count of the last
@@ -487,11 +496,15 @@ bool ksb_staged(const GridDev& G);
 // the two-sweep pass applies: a staged grid whose arrays span less than 4 GiB (32-bit offsets)
 bool ksb_pass_fits(const GridDev& G);
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st);
+// the one-thread-per-cell sweep on any grid (reads the iterate's guard cells)
+hipError_t ksb_sweep_unstaged(const KsbDev& K, bool first, hipStream_t st);
 // two sweeps F^k -> F^{k+2} in one pass over memory (staged 3D grids only); first: F^k = F^n,
 // the pass also writes C
 hipError_t ksb_pass(const KsbDev& K, bool first, hipStream_t st);
 
 hipError_t ksb_finalize(const KsbFin& F, hipStream_t st);
+// interior of six field components (B then E) times f[c % 3]
+hipError_t scale_fields(const GridDev& G, float* const* F, const float f[3], hipStream_t st);
 constexpr int kKsbFinBlocks = 512;  // workgroups per box of the finalize copy (grid stride)
 hipError_t zero_floats(float* p, int64_t n, hipStream_t st);
 hipError_t interior_copy(const GridDev& G, float* guarded, float* dense, int to_dense,

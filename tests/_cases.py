@@ -16,7 +16,7 @@ from paper_2602_15939_amd import _lib as L
 from paper_2602_15939_amd import synth
 
 FRAMES = {"plain": L.FRAME_PLAIN, "shear": L.FRAME_SHEAR, "expand": L.FRAME_EXPAND,
-          "leaky": L.FRAME_LEAKY}
+          "leaky": L.FRAME_LEAKY, "shear_expand": L.FRAME_SHEAR_EXPAND}
 
 
 def cell_coords(cell, n):

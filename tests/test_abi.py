@@ -76,6 +76,8 @@ def _desc(**kw):
     d.leaky_t_esc = kw.get("t_esc", 0.0)
     d.maxwell_iters = kw.get("maxwell_iters", 8)
     d.maxwell_tol = kw.get("maxwell_tol", 0.0)
+    d.expand_adot = kw.get("adot", 0.0)
+    d.expand_axis_mask = kw.get("axis_mask", 0)
     return d
 
 
@@ -85,6 +87,10 @@ def _desc(**kw):
     dict(dt=0.6),                      # c dt sqrt(3) >= dx
     dict(dt=-0.1),
     dict(frame=7),
+    dict(frame=5),
+    # the combined shearing and expanding frame scales x and y together
+    dict(frame=L.FRAME_SHEAR_EXPAND, axis_mask=0b001, adot=1e-3),
+    dict(frame=L.FRAME_SHEAR_EXPAND, axis_mask=0b110, adot=1e-3),
     dict(n_species=0),
     dict(n_species=3),
     dict(frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=0.0, theta_inj=0.3),
@@ -194,6 +200,9 @@ def test_layout_and_workspace_on_the_host(lib):
     shear = _desc(dim=2, n=(64, 64, 1), frame=L.FRAME_SHEAR)
     ls = L.pic_box_layout(shear)
     assert ls.field_sets == 3 and ls.current_arrays == 2 and ls.field_planes == 1
+    comb = _desc(dim=3, n=(20, 12, 16), frame=L.FRAME_SHEAR_EXPAND, axis_mask=0b011, adot=1e-3)
+    lc = L.pic_box_layout(comb)
+    assert lc.field_sets == 3 and lc.current_arrays == 2
     leaky = _desc(dim=2, n=(32, 32, 1), frame=L.FRAME_LEAKY, leaky_mode=L.LEAKY_DISPLACEMENT,
                   l_esc=4.0, theta_inj=0.3)
     ll = L.pic_box_layout(leaky)

@@ -1,0 +1,97 @@
+"""The combined shearing and expanding frame on the GPU (PIC_FRAME_SHEAR_EXPAND) against the
+oracle: the push of eq. OAu_disc with the Lambda of eq. EBu_disc, the position update in the
+expanding coordinates with the shear move and shearing-periodic faces, the comoving current
+with its transport and fold, and the implicit-midpoint field step on the expanding-frame
+fields with the (1/l) L^2 curl factors.
+Bars as the other frames: push 2e-6 relative, positions 2e-6 cells, J and fields 1e-5 of
+their maximum; several steps across a wrap of Delta y_s; x and y expanding together, z alone,
+and all three axes.  Without expansion the frame is the shearing box (within FP32 rounding),
+and a batched step that contains such a box is refused."""
+import numpy as np
+import pytest
+
+from _cases import Case, compare_particles
+from paper_2602_15939_amd import _lib as L
+from paper_2602_15939_amd.box import Batch
+
+pytestmark = pytest.mark.gpu
+
+SIZE = {2: (40, 36), 3: (20, 12, 16)}
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+def _check(c, tol_f=1e-5):
+    for s in range(2):
+        st = compare_particles(c, s, c.gpu_species(s))
+        assert st["n"] == len(c.parts[s]["cell"])
+        assert st["err_u"] < 2e-6 and st["err_x"] < 2e-6, (s, st)
+    assert rel(c.gpu.get_current().cpu().numpy(), c.J) < 1e-5
+    E, B = (t.cpu().numpy() for t in c.gpu.get_fields())
+    assert rel(E, c.E) < tol_f and rel(B, c.B) < tol_f
+    info = c.gpu.info()
+    assert info.errors & ~L.DERR_ORDER == 0 and info.n_slow == 0
+
+
+@pytest.mark.parametrize("dim,mask", [(2, 0b011), (3, 0b011), (3, 0b100), (3, 0b111), (2, 0b100)])
+def test_one_step_parity(dim, mask):
+    c = Case(dim, SIZE[dim], "shear_expand", ppc=4, seed=60 + dim + mask, adot=4e-3,
+             axis_mask=mask, omega0=0.015)
+    try:
+        c.gpu.step()
+        c.oracle_step()
+        _check(c)
+    finally:
+        c.close()
+
+
+def test_steps_across_a_shear_offset_wrap():
+    """Delta y_s = s Omega0 n_x t moves 0.45 cells per step from 11.3: it wraps past n_y = 12."""
+    c = Case(3, (20, 12, 16), "shear_expand", ppc=2, seed=71, adot=5e-3, axis_mask=0b111,
+             omega0=0.0333)
+    c.gpu.set_step(25)
+    c.box.step = 25
+    try:
+        for _ in range(4):
+            c.gpu.step()
+            c.oracle_step()
+        _check(c)
+        assert c.gpu.info().step == 29
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_without_expansion_is_the_shearing_box(dim):
+    a = Case(dim, SIZE[dim], "shear_expand", ppc=3, seed=80 + dim, adot=0.0, axis_mask=0b111)
+    b = Case(dim, SIZE[dim], "shear", ppc=3, seed=80 + dim)
+    try:
+        for _ in range(3):
+            a.gpu.step()
+            b.gpu.step()
+        for s in range(2):
+            ga, gb = a.gpu_species(s), b.gpu_species(s)
+            np.testing.assert_array_equal(ga["cell"], gb["cell"])
+            np.testing.assert_allclose(ga["off"], gb["off"], rtol=0, atol=2e-6)
+            np.testing.assert_allclose(ga["u"], gb["u"], rtol=1e-6, atol=1e-7)
+        for fa, fb in zip(a.gpu.get_fields(), b.gpu.get_fields()):
+            assert rel(fa.cpu().numpy(), fb.cpu().numpy()) < 1e-6
+    finally:
+        a.close()
+        b.close()
+
+
+def test_batched_step_is_refused():
+    c = Case(2, SIZE[2], "shear_expand", ppc=2, seed=90, adot=3e-3, axis_mask=0b011)
+    batch = Batch(None, nbytes=1 << 20)
+    try:
+        assert L.pic_step_batch(batch.h, [c.gpu.h], L.STEP_BATCHED) == L.PIC_EINVAL
+        assert c.gpu.info().step == 0
+        c.gpu.step()  # the box still steps alone
+        assert c.gpu.info().step == 1
+    finally:
+        c.close()
+        batch.close()

@@ -8,6 +8,9 @@
       FETCH_SIZE / WRITE_SIZE per dispatch of the fused push kernel (after the first `skip`
       dispatches), scaled by what the same counters read for the plain device copy of
       copy_bytes in the same run; optionally written as the JSON record bench.py reads
+  python -m paper_2602_15939_amd.profile_summary counters <results.db> <kernel substring>
+      every counter of a --pmc run for the last dispatch of each kernel whose name contains the
+      substring (the last timed step of a bench.py run)
 """
 from __future__ import annotations
 
@@ -84,6 +87,23 @@ def main(argv):
             with open(argv[5], "w") as fh:
                 json.dump(rec, fh, indent=1)
             print("wrote", argv[5])
+    elif argv[0] == "counters":
+        cur = sqlite3.connect(argv[1]).cursor()
+        rows = cur.execute("select dispatch_id, kernel_name, counter_name, value "
+                           "from counters_collection").fetchall()
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        names = {}
+        for d, k, c, v in rows:
+            per[d][c] += v
+            names[d] = k
+        last = {}
+        for d in sorted(per):
+            if argv[2] in names[d]:
+                last[names[d]] = d
+        for k, d in last.items():
+            print(k)
+            for c, v in sorted(per[d].items()):
+                print(f"   {c:28s} {v:.4e}")
     else:
         raise SystemExit(__doc__)
 

@@ -133,19 +133,22 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(seconds=12.0, n=64):
-    """The FP64 oracle, unchanged, on the host cores: an n^3 sample of the same workload (same
-    ppc, theta, sigma, shear), one untimed step, then timed steps until ~seconds have elapsed
-    (at least 3)."""
+def cpu_baseline(seconds=12.0, n=64, w=None, steps=None):
+    """The FP64 oracle, unchanged, on the host cores: an n^3 sample of the 3D shearing-box
+    workload (same ppc, theta, sigma, shear), or the workload w itself when given, one untimed
+    step, then timed steps until ~seconds have elapsed (at least 3), or exactly `steps`."""
     import numpy as np
 
     import oracle
     from paper_2602_15939_amd import synth
 
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    w = workload_shear3d(n=n)
+    sample = w is None
+    if sample:
+        w = workload_shear3d(n=n)
+    dim = w["dim"]
     parts = synth.pair_plasma(w["n"], w["ppc"], w["theta"], 99, device="cpu")
-    box = oracle.make_box(3, w["n"], dt=w["dt"], frame=oracle.SHEAR, shear_s=w["shear_s"],
+    box = oracle.make_box(dim, w["n"], dt=w["dt"], frame=oracle.SHEAR, shear_s=w["shear_s"],
                           omega0=w["omega0"], maxwell_iters=w["maxwell_iters"])
     E, B = synth.uniform_field(w["n"], 2, w["B0"])
     J = np.zeros_like(E)
@@ -156,23 +159,28 @@ def cpu_baseline(seconds=12.0, n=64):
         n = w["n"]
         x = c % n[0] + off[0]
         y = (c // n[0]) % n[1] + off[1]
-        z = c // (n[0] * n[1]) + off[2]
+        z = c // (n[0] * n[1]) + off[2] if dim == 3 else None
         u = p["u"].numpy().astype(np.float64)
         qm = (-1.0, 1.0)[s]
         sp.append(oracle.SpeciesState(x, y, z, u[0], u[1], u[2], qm, qm * w["q"]))
     npart = sum(len(s.x) for s in sp)
     oracle.step(box, E, B, J, sp, nthreads=cores)  # warm-up (page faults of the buffers)
-    steps, t0 = 0, time.perf_counter()
+    done, t0 = 0, time.perf_counter()
     while True:
         oracle.step(box, E, B, J, sp, nthreads=cores)
-        steps += 1
+        done += 1
         el = time.perf_counter() - t0
-        if (el > seconds and steps >= 3) or steps >= 200:
+        if steps is not None:
+            if done >= steps:
+                break
+        elif (el > seconds and done >= 3) or done >= 200:
             break
-    return dict(value=npart * steps / el, unit="particle-steps/s", cores=cores, kind="oracle",
+    what = (f"{w['n'][0]}^3 shearing box of the same recipe, {w['ppc']} ppc/species" if sample
+            else f"the same {w['name']} box, {w['ppc']} ppc/species")
+    return dict(value=npart * done / el, unit="particle-steps/s", cores=cores, kind="oracle",
                 cpu_model=cpu_model(), threads=cores,
-                sample=f"{n}^3 shearing box of the same recipe, 8 ppc/species ({npart} particles), "
-                       f"1 untimed + {steps} timed full steps in {el:.1f} s, OpenMP over particles")
+                sample=f"{what} ({npart} particles), 1 untimed + {done} timed full steps in "
+                       f"{el:.1f} s, OpenMP over particles")
 
 
 def serve_bench(args):
@@ -260,9 +268,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="shear3d",
-                    choices=["shear3d", "expand3d", "leaky2d", "leaky2d_stress", "leaky2d_paper",
-                             "leaky2d_paper_stress"],
-                    help="shear3d: 256^3 shearing box (the default line); expand3d: 128x128x512 "
+                    choices=["shear3d", "shear2d_parity", "expand3d", "leaky2d", "leaky2d_stress",
+                             "leaky2d_paper", "leaky2d_paper_stress"],
+                    help="shear3d: 256^3 shearing box (the default line); shear2d_parity: the "
+                         "64^2 parity configuration (time it over 200 steps: the oracle runs "
+                         "the same steps beside it); expand3d: 128x128x512 "
                          "expanding box; leaky2d: 2048^2 leaky box (probabilistic escape); "
                          "leaky2d_paper: the same box with the displacement escape of the paper; "
                          "*_stress: the escape path under load")
@@ -303,6 +313,9 @@ def main():
     else:
         w = workloads.WORKLOADS[args.workload]()
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
+    graph_steps = w["dim"] == 2 and w["kind"] == "shear"
+    if graph_steps:  # a captured graph needs a stream other than the legacy default one
+        torch.cuda.set_stream(torch.cuda.Stream())
     box, npart = make_box(w, args.seed)
     h = [box.h]
     st = torch.cuda.current_stream()
@@ -350,6 +363,20 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     gpd_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    graph_el = None
+    if graph_steps:
+        # the small parity box is bound by launches: the same steps replayed as one captured
+        # HIP graph per step (the batched step of one box), the way such a box is run
+        from paper_2602_15939_amd.box import step_many
+
+        for _ in range(3):
+            step_many([box], batched=True, graph=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step_many([box], batched=True, graph=True)
+        torch.cuda.synchronize()
+        graph_el = time.perf_counter() - t1
     if args.copy_calibration:
         src = torch.empty(COPY_CAL_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -367,6 +394,9 @@ def main():
         psteps = live0 * (1.0 - r ** args.steps) / (1.0 - r)
     else:
         psteps = float(live0 * args.steps)
+    eager_el = el
+    if graph_el is not None and graph_el < el:
+        el = graph_el
     value = psteps / el
     n_avg = psteps / args.steps  # live particles per timed step (npart without escapes)
     nbytes = algorithmic_bytes(w, n_avg)
@@ -396,6 +426,9 @@ def main():
                    "slow_path_particles": int(info.n_slow),
                    "kernel_source_hash": kernel_source_hash(), "settle_steps": args.settle,
                    "sort": "serial" if args.serial_sort else "overlapped",
+                   "step_mode": "graph replay" if el is not eager_el else "eager",
+                   "eager_ms_per_step": eager_el * 1e3 / args.steps,
+                   "graph_ms_per_step": None if graph_el is None else graph_el * 1e3 / args.steps,
                    "autotune": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
@@ -403,7 +436,10 @@ def main():
     box.close()
     if not args.no_cpu_baseline and w["kind"] == "shear":  # the oracle sample is a shearing box
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        if w["dim"] == 2:  # the small parity box: the oracle runs the timed steps in full
+            out["cpu_baseline"] = cpu_baseline(w=w, steps=args.steps)
+        else:
+            out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

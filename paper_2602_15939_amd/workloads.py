@@ -3,6 +3,9 @@ method's arithmetic).  Code units c = 1, dx = 1; skin depth 4 cells; |q|/m = 1 p
 
   shear3d   3D shearing box, 256^3 cells, 8 ppc per species, Maxwell-Juttner theta = 0.3,
             B0 along z with sigma = 0.05, Keplerian s = 1.5, Omega0 = 0.05 omega_c, dt = 0.45
+  shear2d_parity  the small parity configuration: 2D shearing box, 64^2 cells, 16 ppc per
+            species (131,072 particles), theta = 0.1, B0 along z with sigma = 0.1, s = 1.5,
+            Omega0 = 0.1 omega_c, dt = 0.45, timed over 200 steps with the oracle beside it
   expand3d  3D expanding box, 128 x 128 x 512 cells, 16 ppc per species, theta = 0.05,
             B0 along the long axis (z) with sigma = 0.05 plus random-phase transverse
             fluctuations B = curl(psi e_z), |dB_k| ~ |k|^(-11/6) on 1 <= |n| <= 8,
@@ -31,6 +34,12 @@ def shear3d(n=256, ppc=8):
     wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.05)
     return dict(name=f"shear3d_{n}^3_ppc{ppc}", kind="shear", dim=3, n=(n, n, n), ppc=ppc,
                 theta=0.3, q=q, B0=B0, shear_s=1.5, omega0=0.05 * B0, dt=0.45, maxwell_iters=8)
+
+
+def shear2d_parity(n=64, ppc=16):
+    wp, q, B0 = synth.plasma_params(ppc, 4.0, 0.1)
+    return dict(name=f"shear2d_{n}^2_ppc{ppc}", kind="shear", dim=2, n=(n, n), ppc=ppc,
+                theta=0.1, q=q, B0=B0, shear_s=1.5, omega0=0.1 * B0, dt=0.45, maxwell_iters=8)
 
 
 def expand3d(nxy=128, nz=512, ppc=16):
@@ -69,7 +78,8 @@ def leaky2d_paper_stress(n=2048, ppc=32):
     return w
 
 
-WORKLOADS = {"shear3d": shear3d, "expand3d": expand3d, "leaky2d": leaky2d,
+WORKLOADS = {"shear3d": shear3d, "shear2d_parity": shear2d_parity, "expand3d": expand3d,
+             "leaky2d": leaky2d,
              "leaky2d_stress": leaky2d_stress, "leaky2d_paper": leaky2d_paper,
              "leaky2d_paper_stress": leaky2d_paper_stress}
 

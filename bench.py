@@ -292,7 +292,7 @@ def main():
                     help="the served batch of independent 2D boxes instead of the 3D box")
     ap.add_argument("--runs", type=int, default=512)
     ap.add_argument("--run-steps", type=int, default=500)
-    ap.add_argument("--baseline-runs", type=int, default=64)
+    ap.add_argument("--baseline-runs", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=160.0)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -686,18 +686,30 @@ __global__ __launch_bounds__(KX * KY) void ksb_sweep3_kernel(KsbDev K)
 // Pipeline per plane: the stores of the previous plane's results, then the loads for the
 // next plane (F^k and C in two alternating register sets), which nothing reads before the
 // next plane, so the loads of a whole plane overlap the computation.
-// Roles of the 16 waves: every thread stages one F^k column position; threads 0..767 compute
-// F^{k+1} on the window rows, 128..639 F^{k+2} on the tile (two waves per SIMD); wave 0 stages
-// the x-halo columns of F^k, wave 12 computes the x-halo columns of F^{k+1}, waves 13 and 15
-// stage the opposite-face columns of F^k (one side each), wave 14 computes the opposite-face
-// values of F^{k+1}.
-constexpr int PX = 128, PY = 4, PZ = 64, PN = 1024;
-constexpr int W0X = PX + 4, W0Y = PY + 4;  // F^k window: tile + 2 (x from x0 - 2, y from y0 - 2)
-constexpr int W1X = PX + 2, W1Y = PY + 2;  // F^{k+1} window: tile + 1
-constexpr int XR1 = W1Y + 1, XR0 = XR1 + 2;  // opposite-face rows of F^{k+1} and of F^k
-// At 256^3 a pass takes 0.44 ms (the first 0.63) against 0.47 ms for two single sweeps: it
-// halves the memory traffic but is bound by its 2.5 operator evaluations per cell (F^{k+1} on
-// the halo adds half the tile) at one 1024-thread workgroup per CU (137 KB of LDS).
+// Roles: every thread stages one F^k column position (the PY + 4 window rows over the PX tile
+// columns); the threads of the first PY + 2 rows compute F^{k+1} on the window rows, those of
+// rows 1..PY also F^{k+2} on the tile; wave WXA stages the x-halo columns of F^k, WXB computes
+// the x-halo columns of F^{k+1}, WO0 and WO1 stage the opposite-face columns of F^k (one side
+// each), WAUX computes the opposite-face values of F^{k+1}.
+template <int X>
+struct PassTile {
+    static constexpr int PX = X, PY = 4, PZ = 64;
+    static constexpr int W0X = PX + 4, W0Y = PY + 4;  // F^k window: tile + 2 (x from x0 - 2, y from y0 - 2)
+    static constexpr int W1X = PX + 2, W1Y = PY + 2;  // F^{k+1} window: tile + 1
+    static constexpr int XR1 = W1Y + 1, XR0 = XR1 + 2;  // opposite-face rows of F^{k+1} and of F^k
+    static constexpr int PN = W0Y * PX;                 // one staged F^k position per thread
+    // the extra roles go to the waves past the window rows where there are some (a 1024-thread
+    // tile), else to the two last waves, which also compute (a 512-thread tile)
+    static constexpr int WXA = 0, WXB = W1Y * PX / 64;
+    static constexpr int WO0 = PN == 1024 ? 13 : WXB, WO1 = PN == 1024 ? 15 : WXB + 1;
+    static constexpr int WAUX = PN == 1024 ? 14 : WXB + 1;
+};
+// 64 x 4 tiles: 512 threads and 72 KB of LDS, two workgroups per CU.  At 256^3 a pass takes
+// 0.44 ms, the same as the 128 x 4 tile (1024 threads, 137 KB, one workgroup per CU), against
+// 0.49 ms for two single sweeps.  Neither the stencil (the pass without it takes as long) nor
+// HBM bandwidth bounds it: the loads of one plane, one plane ahead, are its memory parallelism,
+// and a second register set for two planes ahead spills (measured slower).
+constexpr int kPassX = 64;
 
 // element of an array at a 32-bit byte offset from its base (the array pointer itself, in
 // scalar registers): plane and in-plane offsets are summed in 32 bits, so the compiler keeps
@@ -712,11 +724,16 @@ __device__ inline float* st_off(float* base, uint32_t ob)
     return reinterpret_cast<float*>(reinterpret_cast<char*>(base) + ob);
 }
 
-template <bool FIRST>
-__global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
+template <int TX, bool FIRST>
+__global__ __launch_bounds__(PassTile<TX>::PN) __attribute__((amdgpu_waves_per_eu(4)))
+void ksb_pass3_kernel(KsbDev K)
 {
-    static_assert(W0Y * PX == PN && W1Y * PX <= 12 * 64 && 2 * W1Y <= 64, "thread roles");
-    static_assert(PX + PY * PX <= 10 * 64, "F^{k+2} on waves 2..9");
+    using T = PassTile<TX>;
+    constexpr int PX = T::PX, PY = T::PY, PZ = T::PZ, PN = T::PN;
+    constexpr int W0X = T::W0X, W0Y = T::W0Y, W1X = T::W1X, W1Y = T::W1Y, XR0 = T::XR0, XR1 = T::XR1;
+    static_assert(PX % 64 == 0 && W1Y * PX == 64 * T::WXB && T::WAUX < PN / 64 && T::WO1 < PN / 64,
+                  "thread roles");
+    static_assert(2 * W1Y <= 64 && PX + PY * PX <= 64 * T::WXB, "F^{k+2} on window-row waves");
     static_assert(3 * XR0 <= 32 && XR1 <= 32, "opposite-face roles fit half a wave per side");
     __shared__ float A[3][6][W0Y * W0X];  // planes of F^k
     __shared__ float Bs[3][6][W1Y * W1X];  // planes of F^{k+1}
@@ -750,20 +767,20 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
     int xslot = 0;
     bool xa = false, ximg = false;
     float xw = 0.f;
-    const int xs = wv == 15 ? 1 : 0;
-    const bool xwave = wv == 0 || wv == 13 || wv == 15;
+    const int xs = wv == T::WO1 ? 1 : 0;
+    const bool owave = wv == T::WO0 || wv == T::WO1;
     {
         const int l = lane & 31;
         int gx = 0, gy = 0;
         bool pos = false;
-        if (wv == 0 && l < 4 * W0Y) {
+        if (wv == T::WXA && l < 4 * W0Y) {
             const int ly = l >> 2, e = l & 3;
             const int lx = e < 2 ? e : W0X - 4 + e;
             gx = x0 - 2 + lx;
             gy = y0 - 2 + ly;
             pos = gx >= -1 && gx <= nx;  // x = -2, nx + 1 beyond a face are never read
             xslot = ly * W0X + lx;
-        } else if ((wv == 13 || wv == 15) && l < 3 * XR0) {
+        } else if (owave && l < 3 * XR0) {
             const int col = l % 3, r = l / 3;
             gx = (xs == 0 ? nx - 2 : -1) + col;
             gy = y0 - 2 + js1[xs] + r;
@@ -796,7 +813,7 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
     int cslot = 0, cs = 0, crow = 0, cgx = 0;
     bool cop = false, cimg = false, caux = false;
     uint32_t coff = 0;
-    if (wv == 12 && lane < 2 * W1Y) {
+    if (wv == T::WXB && lane < 2 * W1Y) {
         const int ly = lane >> 1, lx = (lane & 1) ? W1X - 1 : 0;
         cgx = x0 - 1 + lx;
         const int gy = y0 - 1 + ly;
@@ -806,7 +823,8 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
         cop = !cimg;
         cs = cgx < 0 ? 0 : 1;
         coff = cop ? 4u * (uint32_t)(cgx + G.sy * wrapn(gy, ny)) : 0u;
-    } else if (wv == 14 && (lane & 31) < XR1) {
+    }
+    if (wv == T::WAUX && (lane & 31) < XR1) {
         cs = lane >> 5;
         crow = lane & 31;
         caux = face[cs];
@@ -817,7 +835,7 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
 
     // ---- F^{k+2}: the tile cell of threads PX .. PX + PY * PX - 1 (their F^{k+1} position)
     const bool tmain = tid >= PX && tid < PX + PY * PX;
-    const int ty = (tid >> 7) - 1;
+    const int ty = tid / PX - 1;
     const bool inside = tmain && y0 + ty < ny;
     const uint32_t i0 = 4u * (uint32_t)(bgx + G.sy * min(y0 + max(ty, 0), ny - 1));
 
@@ -831,13 +849,13 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
         const uint32_t pz = plane_of(z);
 #pragma unroll
         for (int c = 0; c < 6; c++) R[c] = ld_off(F[c], pz + aoff);
-        if (wv == 0 && xa)
+        if (wv == T::WXA && xa)
 #pragma unroll
             for (int c = 0; c < 6; c++) X[c] = ld_off(F[c], pz + xoff);
     };
     auto fetch_aux = [&](int z) {
         const uint32_t pz = plane_of(z);
-        if ((wv == 13 || wv == 15) && xa)
+        if (owave && xa)
 #pragma unroll
             for (int c = 0; c < 6; c++) X[c] = ld_off(F[c], pz + xoff);
     };
@@ -849,7 +867,7 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
     auto stash_main = [&](int s) {
 #pragma unroll
         for (int c = 0; c < 6; c++) A[s][c][aslot] = R[c];
-        if (wv == 0)
+        if (wv == T::WXA)
 #pragma unroll
             for (int c = 0; c < 6; c++) {
                 const float v = extra(c);
@@ -857,7 +875,7 @@ __global__ __launch_bounds__(PN) void ksb_pass3_kernel(KsbDev K)
             }
     };
     auto stash_aux = [&](int s) {
-        if (wv == 13 || wv == 15)
+        if (owave)
 #pragma unroll
             for (int c = 0; c < 6; c++) {
                 const float v = extra(c);
@@ -1287,7 +1305,10 @@ hipError_t yee_e(const MaxwellDev& M, hipStream_t st)
     return hipGetLastError();
 }
 bool ksb_staged(const GridDev& G) { return G.dim == 3 && G.n[0] % KX == 0; }
-bool ksb_pass_fits(const GridDev& G) { return ksb_staged(G) && 4 * (int64_t)G.sz * G.n[2] < (int64_t(1) << 32); }
+bool ksb_pass_fits(const GridDev& G)
+{
+    return G.dim == 3 && G.n[0] % kPassX == 0 && 4 * (int64_t)G.sz * G.n[2] < (int64_t(1) << 32);
+}
 
 hipError_t ksb_sweep(const KsbDev& K, bool first, hipStream_t st)
 {
@@ -1319,12 +1340,13 @@ hipError_t ksb_sweep_unstaged(const KsbDev& K, bool first, hipStream_t st)
 hipError_t ksb_pass(const KsbDev& K, bool first, hipStream_t st)
 {
     if (!ksb_pass_fits(K.G) || K.conv) return hipErrorInvalidValue;
-    const unsigned grid = (unsigned)((K.G.n[0] / PX) * ((K.G.n[1] + PY - 1) / PY) *
-                                     ((K.G.n[2] + PZ - 1) / PZ));
+    using T = PassTile<kPassX>;
+    const unsigned grid = (unsigned)((K.G.n[0] / T::PX) * ((K.G.n[1] + T::PY - 1) / T::PY) *
+                                     ((K.G.n[2] + T::PZ - 1) / T::PZ));
     if (first)
-        ksb_pass3_kernel<true><<<grid, PN, 0, st>>>(K);
+        ksb_pass3_kernel<kPassX, true><<<grid, T::PN, 0, st>>>(K);
     else
-        ksb_pass3_kernel<false><<<grid, PN, 0, st>>>(K);
+        ksb_pass3_kernel<kPassX, false><<<grid, T::PN, 0, st>>>(K);
     return hipGetLastError();
 }
 hipError_t scale_fields(const GridDev& G, float* const* F, const float f[3], hipStream_t st)

@@ -1,12 +1,12 @@
 """Two fixed-point sweeps per pass in the shearing-box Maxwell step (Sec. 2.2, implicit midpoint
-by fixed-point sweeps), taken on 3D grids whose x size is a multiple of the 128-cell column tile
+by fixed-point sweeps), taken on 3D grids whose x size is a multiple of the 64-cell column tile
 when the sweep count is fixed: the intermediate iterate lives only in on-chip memory, and its
 x-face images come from a small record of the two face columns.
 * The pass gives the same iterate as the same number of single sweeps, bit for bit.  Tolerance
   mode with an unreachable tolerance runs exactly its cap of single sweeps (and latches
   PIC_DERR_NOCONVERGE), so a box in that mode is the reference.  Even counts (passes only) and
-  odd counts (a last single sweep), with a current, on two x tiles (one face image each), one x
-  tile (both halos are images), ragged y tiles, ragged and single z chunks, the smallest grid
+  odd counts (a last single sweep), with a current, on several x tiles (one face image each,
+  interior tiles between them), one x tile (both halos are images), ragged y tiles, ragged and single z chunks, the smallest grid
   (windows wider than the grid in y and z), and a shear offset
   Delta y_s that has a fractional part and wraps past n_y.
 * One Maxwell step against the oracle's FP64 step.
@@ -47,11 +47,13 @@ def _current(n, seed):
 
 # |s omega0 nx / 2| dt stays below half a cell per step (the sweeps contract).
 CASES = [
-    ((256, 14, 70), 0.004, 19, 8),   # two x tiles, ragged y tile, two z chunks (one ragged)
+    ((256, 14, 70), 0.004, 19, 8),   # four x tiles, ragged y tile, two z chunks (one ragged)
     ((256, 14, 70), 0.004, 19, 5),   # odd count: two passes and a last single sweep
-    ((128, 9, 5), -0.006, 7, 2),     # one x tile, one short z chunk, one pass
+    ((128, 9, 5), -0.006, 7, 2),     # two x tiles, one short z chunk, one pass
     ((128, 6, 66), 0.005, 0, 3),     # Delta y_s = 0 at t^n
     ((128, 4, 4), 0.005, 3, 4),      # the smallest grid: the windows wrap in y and z
+    ((64, 7, 6), 0.006, 11, 4),      # one x tile: both x halos are images
+    ((192, 5, 9), -0.005, 23, 3),    # an interior x tile between the two face tiles
 ]
 
 

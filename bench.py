@@ -6,7 +6,8 @@ per cell per species (e+ and e-, 268,435,456 particles), Maxwell-Juttner theta =
 4 cells, weak B0 along z with sigma = 0.05, Keplerian shear q = 1.5, Omega0/omega_c = 0.05,
 dt = 0.45, FP32 particles (int32 cell + FP32 offset) with FP64 shear offset.  Synthetic seeded
 inputs.  --workload expand3d / leaky2d: the 128x128x512 expanding box and the 2048^2 leaky box
-(recipes in paper_2602_15939_amd/workloads.py); --serve: the served batch of 2D boxes.
+(recipes in paper_2602_15939_amd/workloads.py); the full default run (no --workload, CPU baseline
+on) also times these two after the shearing box and reports them under "other_workloads"; --serve: the served batch of 2D boxes.
 
 One step = tile sort + fused gather/push/deposit + current fold with the J' transport +
 implicit-midpoint Maxwell (fixed-point sweeps) + guard fills, i.e. the whole hot path.
@@ -267,7 +268,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="shear3d",
+    ap.add_argument("--workload", default=None,
                     choices=["shear3d", "shear2d_parity", "expand3d", "leaky2d", "leaky2d_stress",
                              "leaky2d_paper", "leaky2d_paper_stress"],
                     help="shear3d: 256^3 shearing box (the default line); shear2d_parity: the "
@@ -275,9 +276,12 @@ def main():
                          "the same steps beside it); expand3d: 128x128x512 "
                          "expanding box; leaky2d: 2048^2 leaky box (probabilistic escape); "
                          "leaky2d_paper: the same box with the displacement escape of the paper; "
-                         "*_stress: the escape path under load")
+                         "*_stress: the escape path under load.  Without it: shear3d, and in "
+                         "the full default run (with the CPU baseline) also expand3d and leaky2d")
     ap.add_argument("--n", type=int, default=None, help="shear3d only: cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="default run only: skip timing the expanding and leaky boxes after it")
     ap.add_argument("--seed", type=int, default=20260216)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for profiles)")
@@ -302,16 +306,42 @@ def main():
     if args.serve:
         serve_bench(args)
         return
+    from paper_2602_15939_amd import workloads
+
+    full = args.workload is None and args.n is None and not args.no_cpu_baseline
+    if args.workload in (None, "shear3d"):
+        w = workload_shear3d(n=args.n or 256)
+    else:
+        w = workloads.WORKLOADS[args.workload]()
+    out = measure(args, w)
+    if full and not args.no_other_workloads:
+        # the full default run: the paper's other two frames at their benchmark sizes, timed in
+        # the same process after the line's workload (their lines alone: --workload expand3d /
+        # leaky2d); the profiling runs (--no-cpu-baseline) time the shearing box only
+        out["other_workloads"] = []
+        for name in ("expand3d", "leaky2d"):
+            o = measure(args, workloads.WORKLOADS[name]())
+            out["other_workloads"].append({
+                "workload": o["config"]["workload"], "value": o["value"], "unit": o["unit"],
+                "ms_per_step": o["ms_per_step"], "steps": o["steps"],
+                "particles": o["config"]["particles"], "gpd_ms": o["config"]["gpd_ms"],
+                "roofline_frac": o["roofline"]["frac"], "autotune_tile": (o["config"]["autotune"] or {}).get("tile")})
+    if not args.no_cpu_baseline and w["kind"] == "shear":  # the oracle sample is a shearing box
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        if w["dim"] == 2:  # the small parity box: the oracle runs the timed steps in full
+            out["cpu_baseline"] = cpu_baseline(w=w, steps=args.steps)
+        else:
+            out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def measure(args, w):
+    """Build the workload's box on the GPU, settle, optionally autotune, time args.steps steps;
+    the bench line of that workload (without the CPU baseline)."""
     import torch
 
     from paper_2602_15939_amd import _lib as L
 
-    from paper_2602_15939_amd import workloads
-
-    if args.workload == "shear3d":
-        w = workload_shear3d(n=args.n or 256)
-    else:
-        w = workloads.WORKLOADS[args.workload]()
     print(f"[bench] building {w['name']}", file=sys.stderr, flush=True)
     graph_steps = w["dim"] == 2 and w["kind"] == "shear"
     if graph_steps:  # a captured graph needs a stream other than the legacy default one
@@ -434,13 +464,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
     box.close()
-    if not args.no_cpu_baseline and w["kind"] == "shear":  # the oracle sample is a shearing box
-        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        if w["dim"] == 2:  # the small parity box: the oracle runs the timed steps in full
-            out["cpu_baseline"] = cpu_baseline(w=w, steps=args.steps)
-        else:
-            out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
+    del box
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -1,5 +1,5 @@
-"""The leaky box's escape rule in the shearing and expanding frames (PIC_BOX_ESCAPE), GPU
-against the oracle: displacement escape with the Maxwell-Juttner re-draw (2D, and 3D with the
+"""The leaky box's escape rule in the shearing, expanding and combined frames (PIC_BOX_ESCAPE),
+GPU against the oracle: displacement escape with the Maxwell-Juttner re-draw (2D, and 3D with the
 3-vector test) and probabilistic escape with compaction (masks and survivors bit-exact for a
 population far above gamma_thr; the escape counter equals the oracle's escapes)."""
 import numpy as np
@@ -25,13 +25,18 @@ def frozen(n, gammas, seed, dims):
     return out
 
 
+KW = {"shear": dict(shear_s=1.5, omega0=0.01), "expand": dict(adot=2e-3),
+      "shear_expand": dict(shear_s=1.5, omega0=0.01, adot=2e-3, axis_mask=0b011)}
+
+
 @pytest.mark.parametrize("frame,dim,use_3vec", [("shear", 2, 0), ("expand", 2, 0), ("shear", 3, 1),
-                                                ("expand", 3, 0)])
+                                                ("expand", 3, 0), ("shear_expand", 2, 0),
+                                                ("shear_expand", 3, 1)])
 def test_displacement_escape_in_frame(frame, dim, use_3vec):
     dims = (32, 32) if dim == 2 else (12, 12, 12)
     shape = (3, 1, 32, 32) if dim == 2 else (3, 12, 12, 12)
     zero = (np.zeros(shape, np.float32), np.zeros(shape, np.float32))
-    kw = dict(shear_s=1.5, omega0=0.01) if frame == "shear" else dict(adot=2e-3)
+    kw = KW[frame]
     c = Case(dim, dims, frame, parts=frozen(4000, (1.3, 1.05), 70 + dim, dims), fields=zero, q=0.0,
              leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=1.5, theta_inj=0.3, use_3vec=use_3vec,
              escape=True, **kw)
@@ -56,12 +61,12 @@ def test_displacement_escape_in_frame(frame, dim, use_3vec):
         c.close()
 
 
-@pytest.mark.parametrize("frame", ["shear", "expand"])
+@pytest.mark.parametrize("frame", ["shear", "expand", "shear_expand"])
 def test_probabilistic_escape_in_frame(frame):
     dims = (32, 32)
     dt = 0.45
     zero = (np.zeros((3, 1, 32, 32), np.float32),) * 2
-    kw = dict(shear_s=1.5, omega0=0.01) if frame == "shear" else dict(adot=2e-3)
+    kw = KW[frame]
     c = Case(2, dims, frame, parts=frozen(6000, (30.0, 25.0), 91, dims), fields=zero, q=0.0,
              leaky_mode=L.LEAKY_PROBABILISTIC, t_esc=dt / 0.1, gamma_thr=10.0, escape=True, **kw)
     try:

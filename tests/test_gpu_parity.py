@@ -268,7 +268,8 @@ def test_energy_history_config0_200_steps():
         c.close()
 
 
-@pytest.mark.parametrize("dim,frame", [(2, "shear"), (2, "expand"), (2, "leaky"), (3, "shear")])
+@pytest.mark.parametrize("dim,frame", [(2, "shear"), (2, "expand"), (2, "leaky"), (3, "shear"),
+                                       (2, "shear_expand")])
 def test_energy_history_1000_steps(dim, frame):
     """Field and kinetic energy histories within 1% of the FP64 oracle over 1000 steps, sampled
     every 50 steps, at the size of the parity configuration (64x64 cells, 16 ppc per species;
@@ -276,7 +277,8 @@ def test_energy_history_1000_steps(dim, frame):
     the shearing box (q = 1.5, Omega0 = 0.1 omega_c), the expanding box (x and y, perpendicular
     to B0, grow as a = 1 + adot t with adot = 1e-3 omega_p) and the leaky box in the paper's
     displacement mode (escape at |dr| = L/2, Maxwell-Juttner reinjection at the plasma
-    temperature: every particle crosses that distance many times in 1000 steps).  The magnetic
+    temperature: every particle crosses that distance many times in 1000 steps), and the
+    combined frame (the shearing box's parameters with x and y expanding as above).  The magnetic
     energy per component (the observable of the shearing-box application, Sec. 2.3) within 1%
     of the total magnetic energy.  Live particle counts equal."""
     import os
@@ -289,7 +291,9 @@ def test_energy_history_1000_steps(dim, frame):
     fields = (E.astype(np.float32), B.astype(np.float32))
     kw = dict(shear=dict(shear_s=1.5, omega0=0.1 * B0, maxwell_iters=8),
               expand=dict(adot=1e-3 * wp, axis_mask=0b011),
-              leaky=dict(leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=32.0, theta_inj=0.1))[frame]
+              leaky=dict(leaky_mode=L.LEAKY_DISPLACEMENT, l_esc=32.0, theta_inj=0.1),
+              shear_expand=dict(shear_s=1.5, omega0=0.1 * B0, maxwell_iters=8, adot=1e-3 * wp,
+                                axis_mask=0b011))[frame]
     c = Case(dim, dims, frame, ppc=ppc, theta=0.1, seed=4051, fields=fields, q=q, **kw)
     nthreads = min(16, len(os.sched_getaffinity(0)))
     try:

@@ -55,8 +55,8 @@ enum pic_frame { PIC_FRAME_PLAIN = 0, PIC_FRAME_SHEAR = 1, PIC_FRAME_EXPAND = 2,
    positions move by dt L^-1 u'/gamma' plus the shear move, and the field step is the implicit
    midpoint of Sec. 2.2 on the expanding-frame fields (l/l_c) F_c with the (1/l) L^2 curl factors
    of eqs. EBB/EBE.  x and y scale together: expand_axis_mask 0, 4 (z), 3 (xy) or 7; other masks
-   are PIC_EINVAL.  Boxes of this frame step alone (a batched step containing one is PIC_EINVAL)
-   and take the one-thread-per-cell field sweeps. */
+   are PIC_EINVAL.  The field step takes the one-thread-per-cell sweeps (also in a batched
+   step, where the conversions to and from the expanding-frame fields are batched launches). */
 enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 
 /* pic_gather_push flags */

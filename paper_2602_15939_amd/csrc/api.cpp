@@ -605,6 +605,33 @@ KsbFin ksb_fin(const pic_box* b, int K, int last)
     return F;
 }
 
+// The combined frame's Maxwell step runs on the expanding-frame fields (l/l_c) F_c: the factors
+// that convert F^n at t^n (fwd) and back at t^{n+1} (back), the curl factors l_c^2/l (dfac) and
+// kz = (l_y/l_z)^2, all at the step's times
+struct CombFactors {
+    float fwd[3], back[3], dfac[3], kz;
+};
+CombFactors comb_factors(const pic_box* b)
+{
+    const double dt = b->d.dt, tn = time_of(b, b->step), th = tn + 0.5 * dt, t1 = tn + dt;
+    double ln[3], lh[3], l1[3];
+    for (int c = 0; c < 3; c++) {
+        ln[c] = scale_of(b, c, tn);
+        lh[c] = scale_of(b, c, th);
+        l1[c] = scale_of(b, c, t1);
+    }
+    const double elln = ln[0] * ln[1] * ln[2], ellh = lh[0] * lh[1] * lh[2];
+    const double ell1 = l1[0] * l1[1] * l1[2];
+    CombFactors f{};
+    for (int c = 0; c < 3; c++) {
+        f.fwd[c] = (float)(elln / ln[c]);
+        f.back[c] = (float)(l1[c] / ell1);
+        f.dfac[c] = (float)(lh[c] * lh[c] / ellh);
+    }
+    f.kz = (float)((lh[1] / lh[2]) * (lh[1] / lh[2]));
+    return f;
+}
+
 int32_t maxwell_box(pic_box* b)
 {
     const double dt = b->d.dt;
@@ -625,22 +652,13 @@ int32_t maxwell_box(pic_box* b)
         const bool comb = b->d.frame == PIC_FRAME_SHEAR_EXPAND;
         float back[3] = {1.f, 1.f, 1.f}, dfac[3] = {1.f, 1.f, 1.f}, kz = 1.f;
         if (comb) {
-            double ln[3], lh[3], l1[3];
+            const CombFactors f = comb_factors(b);
             for (int c = 0; c < 3; c++) {
-                ln[c] = scale_of(b, c, tn);
-                lh[c] = scale_of(b, c, th);
-                l1[c] = scale_of(b, c, t1);
+                back[c] = f.back[c];
+                dfac[c] = f.dfac[c];
             }
-            const double elln = ln[0] * ln[1] * ln[2], ellh = lh[0] * lh[1] * lh[2];
-            const double ell1 = l1[0] * l1[1] * l1[2];
-            float fwd[3];
-            for (int c = 0; c < 3; c++) {
-                fwd[c] = (float)(elln / ln[c]);
-                back[c] = (float)(l1[c] / ell1);
-                dfac[c] = (float)(lh[c] * lh[c] / ellh);
-            }
-            kz = (float)((lh[1] / lh[2]) * (lh[1] / lh[2]));
-            if (scale_fields(b->G, b->set[sn], fwd, st) != hipSuccess ||
+            kz = f.kz;
+            if (scale_fields(b->G, b->set[sn], f.fwd, st) != hipSuccess ||
                 fill_guards(b->G, b->set[sn], 6, 1, dys0, st) != hipSuccess)
                 return PIC_EDEVICE;
         }
@@ -921,8 +939,6 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
         pic_box* b = boxes[i];
         if (b->st != st || b->deposit_pending) return b->st != st ? PIC_EINVAL : PIC_ESTATE;
         if (!batch_tile_supported(b->dim, b->tile)) return PIC_EINVAL;
-        // the combined shearing and expanding frame steps one box at a time
-        if (b->d.frame == PIC_FRAME_SHEAR_EXPAND) return PIC_EINVAL;
         for (int j = 0; j < i; j++)
             if (boxes[j] == b) return PIC_EINVAL;
     }
@@ -1056,7 +1072,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
             fy.push_back(FoldPArgs{G, Jc, 1});
             fyb.push_back(grid_blocks((int64_t)NXg * nly * G.n[2]));
             const double th = time_of(b, b->step) + 0.5 * b->d.dt;
-            if (b->d.frame == PIC_FRAME_SHEAR) {
+            if (sheared(&b->d)) {
                 // transport + x fold from J into the second array, which then becomes the
                 // current (the later stages of this step are planned with the swapped arrays)
                 const double dh = shear_offset(b, th), fl = std::floor(dh);
@@ -1086,7 +1102,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
         int kmax = 0;
         for (int i = 0; i < nb; i++) {
             pic_box* b = boxes[i];
-            if (b->d.frame == PIC_FRAME_SHEAR) {
+            if (sheared(&b->d)) {
                 kmax = std::max(kmax, b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8);
                 continue;
             }
@@ -1151,13 +1167,35 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
             const int sn = b->cur_set;
             rot[i] = Rot{sn, (sn + 1) % 3, (sn + 2) % 3, sn, (sn + 2) % 3};
         }
+        // combined-frame boxes: F^n to the expanding-frame fields at t^n, guards at t^n
+        std::vector<CombFactors> cf(nb);
+        {
+            std::vector<ScaleArgs> sa;
+            std::vector<uint32_t> sab;
+            std::vector<FillArgs> sf;
+            std::vector<uint32_t> sfb;
+            for (int i = 0; i < nb; i++) {
+                pic_box* b = boxes[i];
+                if (b->d.frame != PIC_FRAME_SHEAR_EXPAND) continue;
+                cf[i] = comb_factors(b);
+                ScaleArgs a{};
+                a.G = b->G;
+                for (int c = 0; c < 6; c++) a.F[c] = b->set[rot[i].sn][c];
+                for (int c = 0; c < 3; c++) a.f[c] = cf[i].fwd[c];
+                sa.push_back(a);
+                sab.push_back(grid_blocks((int64_t)b->n[0] * b->n[1] * b->n[2]));
+                plan_fill(sf, sfb, b->G, b->set[rot[i].sn], 6, 1, shear_offset(b, time_of(b, b->step)));
+            }
+            plan.grid(kBatchScale, sa, sab, 1);
+            plan.grid(kBatchFill, sf, sfb, 6);
+        }
         // tolerance-mode boxes: clear their convergence records first
         {
             std::vector<ZeroArgs> cz;
             std::vector<uint32_t> czb;
             for (int i = 0; i < nb; i++) {
                 pic_box* b = boxes[i];
-                if (b->d.frame != PIC_FRAME_SHEAR || !(b->d.maxwell_tol > 0.0)) continue;
+                if (!sheared(&b->d) || !(b->d.maxwell_tol > 0.0)) continue;
                 const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
                 cz.push_back(ZeroArgs{b->conv, (int64_t)2 * K});
                 czb.push_back(grid_blocks(2 * K));
@@ -1173,7 +1211,7 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
             std::vector<uint32_t> kzb;
             for (int i = 0; i < nb; i++) {
                 pic_box* b = boxes[i];
-                if (b->d.frame != PIC_FRAME_SHEAR) continue;
+                if (!sheared(&b->d)) continue;
                 const int K = b->d.maxwell_iters > 0 ? b->d.maxwell_iters : 8;
                 if (k >= K) continue;
                 const bool tol = b->d.maxwell_tol > 0.0;
@@ -1194,6 +1232,14 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
                     Kd.tol = (float)b->d.maxwell_tol;
                     Kd.k = k;
                 }
+                if (b->d.frame == PIC_FRAME_SHEAR_EXPAND) {
+                    Kd.expand = 1;
+                    for (int c = 0; c < 3; c++) Kd.dfac[c] = cf[i].dfac[c];
+                    Kd.kz = cf[i].kz;
+                } else {
+                    for (int c = 0; c < 3; c++) Kd.dfac[c] = 1.f;
+                    Kd.kz = 1.f;
+                }
                 ks.push_back(Kd);
                 ksb.push_back(grid_blocks((int64_t)b->n[0] * b->n[1] * b->n[2]));
                 if (tol && k == K - 1) {
@@ -1213,11 +1259,29 @@ int32_t step_batched(pic_box* const* boxes, int nb, bool graph, Stager& sg_all, 
             plan.grid(kBatchKsbFinal, kz, kzb, 1);
             plan.grid(kBatchFill, kf, kfb, 6);
         }
+        // combined-frame boxes: the last iterate back to the frame's fields at t^{n+1}
+        {
+            std::vector<ScaleArgs> sa;
+            std::vector<uint32_t> sab;
+            for (int i = 0; i < nb; i++) {
+                pic_box* b = boxes[i];
+                if (b->d.frame != PIC_FRAME_SHEAR_EXPAND) continue;
+                ScaleArgs a{};
+                a.G = b->G;
+                for (int c = 0; c < 6; c++) a.F[c] = b->set[b->cur_set][c];
+                for (int c = 0; c < 3; c++) a.f[c] = cf[i].back[c];
+                sa.push_back(a);
+                sab.push_back(grid_blocks((int64_t)b->n[0] * b->n[1] * b->n[2]));
+                plan_fill(fend, fendb, b->G, b->set[b->cur_set], 6, 1,
+                          shear_offset(b, time_of(b, b->step) + b->d.dt));
+            }
+            plan.grid(kBatchScale, sa, sab, 1);
+        }
         // time advance; guard cells of the non-shear fields at t^{n+1}
         for (int i = 0; i < nb; i++) {
             pic_box* b = boxes[i];
             b->step += 1;
-            if (b->d.frame != PIC_FRAME_SHEAR) plan_fill(fend, fendb, b->G, field_ptrs(b), 6, 0, 0.0);
+            if (!sheared(&b->d)) plan_fill(fend, fendb, b->G, field_ptrs(b), 6, 0, 0.0);
         }
         plan.grid(kBatchFill, fend, fendb, 6);
     }

@@ -942,6 +942,7 @@ static hipError_t launch_batch_shape(const StepDev* table, UnitMap m, int blocks
     switch (frame) {
     case kShear: gpd_batch<DIM, TX, TY, TZ, kShear, NT><<<blocks, NT, 0, st>>>(table, m); break;
     case kExpand: gpd_batch<DIM, TX, TY, TZ, kExpand, NT><<<blocks, NT, 0, st>>>(table, m); break;
+    case kShearExpand: gpd_batch<DIM, TX, TY, TZ, kShearExpand, NT><<<blocks, NT, 0, st>>>(table, m); break;
     case kLeaky: gpd_batch<DIM, TX, TY, TZ, kLeaky, NT><<<blocks, NT, 0, st>>>(table, m); break;
     default: gpd_batch<DIM, TX, TY, TZ, kPlain, NT><<<blocks, NT, 0, st>>>(table, m); break;
     }

@@ -1080,16 +1080,12 @@ PIC_BATCHED_KERNEL(ksb_final, KsbFin, kBlock)
 // ------------------------------------------------------------------ utilities
 // interior of six components (B then E) times f[c % 3] (the expanding-frame conversion of the
 // combined frame's field step)
-struct ScaleArgs {
-    GridDev G;
-    float* F[6];
-    float f[3];
-};
-__global__ __launch_bounds__(kBlock) void scale_fields_kernel(ScaleArgs a)
+// grid-stride over the cells (the batched launch gives every cell its own thread)
+__device__ __attribute__((always_inline)) inline void scale_fields_body(const ScaleArgs& a, int blk, int nblk, int)
 {
     const GridDev& G = a.G;
     const int64_t n = (int64_t)G.n[0] * G.n[1] * G.n[2];
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+    for (int64_t t = (int64_t)blk * kBlock + threadIdx.x; t < n; t += (int64_t)nblk * kBlock) {
         int x, y, z;
         cell_of(G, t, x, y, z);
         const int64_t i = gidx(G, x, y, z);
@@ -1097,6 +1093,7 @@ __global__ __launch_bounds__(kBlock) void scale_fields_kernel(ScaleArgs a)
         for (int c = 0; c < 6; c++) a.F[c][i] *= a.f[c % 3];
     }
 }
+PIC_BATCHED_KERNEL(scale_fields, ScaleArgs, kBlock)
 
 // grid-stride, 16-byte stores where the array is 16-byte aligned (the batched launch gives
 // every word its own thread, so most of its threads find nothing to do)
@@ -1387,6 +1384,7 @@ hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks,
         break;
     case kBatchKsbNext: ksb_next_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbDev*>(table), m); break;
     case kBatchKsbFinal: ksb_final_batch<<<grid, kBlock, 0, st>>>(static_cast<const KsbFin*>(table), m); break;
+    case kBatchScale: scale_fields_batch<<<grid, kBlock, 0, st>>>(static_cast<const ScaleArgs*>(table), m); break;
     }
     return hipGetLastError();
 }

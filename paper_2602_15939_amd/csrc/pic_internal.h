@@ -469,9 +469,16 @@ hipError_t migrate_sort(const int32_t* cell, const int32_t* toff_prev, int n_upp
                         bool counts_ready, hipStream_t st);
 
 // batched launches of the grid and sort kernels (tables of per-unit arguments on the device)
+// per-component factors of a field set (the combined frame's conversion to and from the
+// expanding-frame fields): F_c *= f[c % 3] on the interior
+struct ScaleArgs {
+    GridDev G;
+    float* F[6];
+    float f[3];
+};
 enum GridBatchKind {
     kBatchZero, kBatchFill, kBatchFoldP, kBatchShearFold, kBatchFoldX, kBatchYeeB, kBatchYeeE,
-    kBatchKsbFirst, kBatchKsbNext, kBatchKsbFinal
+    kBatchKsbFirst, kBatchKsbNext, kBatchKsbFinal, kBatchScale
 };
 hipError_t grid_batch(GridBatchKind k, const void* table, UnitMap m, int blocks, int ydim,
                       hipStream_t st);

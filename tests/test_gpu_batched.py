@@ -21,6 +21,10 @@ MIX = [
          kw=dict(leaky_mode=L.LEAKY_PROBABILISTIC, t_esc=4.0, gamma_thr=1.5)),
     dict(dim=2, n=(48, 64), frame="plain", tile=(16, 16, 1), ppc=3, kw={}),
     dict(dim=3, n=(24, 24, 24), frame="shear", tile=(8, 8, 8), ppc=2, kw=dict(omega0=0.04)),
+    dict(dim=2, n=(32, 48), frame="shear_expand", tile=(8, 8, 1), ppc=4,
+         kw=dict(omega0=0.02, adot=3e-3, axis_mask=0b011)),
+    dict(dim=3, n=(24, 24, 24), frame="shear_expand", tile=(8, 8, 8), ppc=2,
+         kw=dict(omega0=0.03, adot=3e-3, axis_mask=0b100)),
 ]
 
 

@@ -5,14 +5,14 @@ with its transport and fold, and the implicit-midpoint field step on the expandi
 fields with the (1/l) L^2 curl factors.
 Bars as the other frames: push 2e-6 relative, positions 2e-6 cells, J and fields 1e-5 of
 their maximum; several steps across a wrap of Delta y_s; x and y expanding together, z alone,
-and all three axes.  Without expansion the frame is the shearing box (within FP32 rounding),
-and a batched step that contains such a box is refused."""
+and all three axes.  Without expansion the frame is the shearing box (within FP32 rounding).
+A batched step of such boxes beside boxes of the other frames equals their steps alone."""
 import numpy as np
+import torch
 import pytest
 
 from _cases import Case, compare_particles
 from paper_2602_15939_amd import _lib as L
-from paper_2602_15939_amd.box import Batch
 
 pytestmark = pytest.mark.gpu
 
@@ -84,14 +84,49 @@ def test_without_expansion_is_the_shearing_box(dim):
         b.close()
 
 
-def test_batched_step_is_refused():
-    c = Case(2, SIZE[2], "shear_expand", ppc=2, seed=90, adot=3e-3, axis_mask=0b011)
-    batch = Batch(None, nbytes=1 << 20)
+def test_batched_step_in_tolerance_mode_equals_alone():
+    """Combined-frame boxes in tolerance mode (3D, x and y expanding; 2D, z expanding) with a
+    shearing box in one batched step, four steps, against the same boxes stepped alone: ids and
+    cells equal, momenta within 2e-6 relative, positions within 2e-6 cells, fields within 1e-5 of
+    their maximum (the batched step differs only by the order of the FP32 additions of the
+    tile-halo current), the same sweep counts.  Fixed-count combined boxes are in the batched
+    mix of the batched-step tests."""
+    from _cases import positions_f64, wrap_diff
+    from paper_2602_15939_amd.box import step_many
+
+    specs = [(3, (16, 16, 16), (8, 8, 8), "shear_expand",
+              dict(adot=3e-3, axis_mask=0b011, omega0=0.01, maxwell_tol=1e-5, maxwell_iters=40)),
+             (2, (32, 32), (8, 8, 1), "shear_expand",
+              dict(adot=3e-3, axis_mask=0b100, omega0=0.02, maxwell_tol=1e-5, maxwell_iters=40)),
+             (2, (32, 32), (16, 16, 1), "shear", dict(omega0=0.02))]
+    stream = torch.cuda.Stream()
+    alone, batch = [], []
     try:
-        assert L.pic_step_batch(batch.h, [c.gpu.h], L.STEP_BATCHED) == L.PIC_EINVAL
-        assert c.gpu.info().step == 0
-        c.gpu.step()  # the box still steps alone
-        assert c.gpu.info().step == 1
+        for i, (dim, n, tile, frame, kw) in enumerate(specs):
+            for group in (alone, batch):
+                group.append(Case(dim, n, frame, ppc=2, seed=120 + i, tile=tile, stream=stream, **kw))
+        for _ in range(4):
+            for c in alone:
+                step_many([c.gpu], batched=False)
+            step_many([c.gpu for c in batch], batched=True)
+        for a, b in zip(alone, batch):
+            ia, ib = a.gpu.info(), b.gpu.info()
+            assert ia.step == ib.step == 4
+            assert ia.errors & ~L.DERR_ORDER == 0 and ib.errors & ~L.DERR_ORDER == 0
+            assert ia.maxwell_sweeps == ib.maxwell_sweeps
+            for s in range(2):
+                ga, gb = a.gpu_species(s), b.gpu_species(s)
+                np.testing.assert_array_equal(ga["id"], gb["id"])
+                np.testing.assert_array_equal(ga["cell"], gb["cell"])
+                ua, ub = ga["u"].astype(np.float64), gb["u"].astype(np.float64)
+                du = np.linalg.norm(ua - ub, axis=0) / np.maximum(np.linalg.norm(ub, axis=0), 1e-2)
+                assert du.max() < 2e-6, (s, du.max())
+                xa = positions_f64(ga["cell"], ga["off"], a.n, a.dim)
+                xb = positions_f64(gb["cell"], gb["off"], b.n, b.dim)
+                for d in range(a.dim):
+                    assert np.abs(wrap_diff(xa[d], xb[d], a.n[d])).max() < 2e-6, (s, d)
+            for fa, fb in zip(a.gpu.get_fields(), b.gpu.get_fields()):
+                assert rel(fb.cpu().numpy(), fa.cpu().numpy()) < 1e-5
     finally:
-        c.close()
-        batch.close()
+        for c in alone + batch:
+            c.close()

@@ -7,7 +7,8 @@ per cell per species (e+ and e-, 268,435,456 particles), Maxwell-Juttner theta =
 dt = 0.45, FP32 particles (int32 cell + FP32 offset) with FP64 shear offset.  Synthetic seeded
 inputs.  --workload expand3d / leaky2d: the 128x128x512 expanding box and the 2048^2 leaky box
 (recipes in paper_2602_15939_amd/workloads.py); the full default run (no --workload, CPU baseline
-on) also times these two after the shearing box and reports them under "other_workloads"; --serve: the served batch of 2D boxes.
+on) also times these two after the shearing box, and a 128-run sample of the served batch, and
+reports them under "other_workloads"; --serve: the served batch of 2D boxes.
 
 One step = tile sort + fused gather/push/deposit + current fold with the J' transport +
 implicit-midpoint Maxwell (fixed-point sweeps) + guard fills, i.e. the whole hot path.
@@ -184,9 +185,9 @@ def cpu_baseline(seconds=12.0, n=64, w=None, steps=None):
                        f"{el:.1f} s, OpenMP over particles")
 
 
-def serve_bench(args):
+def serve_bench(args, runs=None, run_steps=None, baseline_runs=None):
     """The served batch: 512 independent 2D box runs of 500 steps (see serve.py for the
-    recipe).  (1) capacity: all runs queued at t = 0, admitted by HBM footprint, stepped together
+    recipe; runs / run_steps / baseline_runs override the command line for a smaller sample).  (1) capacity: all runs queued at t = 0, admitted by HBM footprint, stepped together
     by the batched step, eagerly and replayed as HIP graphs (the faster mode serves the rest);
     (2) Poisson arrivals at 0.8 x capacity: p50/p99 run latency and aggregate particle-steps/s;
     (3) one box at a time (per-box launches) on the first runs of the same list; (4) runs sampled
@@ -196,6 +197,9 @@ def serve_bench(args):
 
     from paper_2602_15939_amd import serve
 
+    runs = runs if runs is None else runs
+    run_steps = run_steps if run_steps is None else run_steps
+    baseline_runs = baseline_runs if baseline_runs is None else baseline_runs
     budget = int(args.budget_gb * 2**30)
     tiles = serve.tune_tiles(log=lambda m: print(m, file=sys.stderr, flush=True))
     # warm-up (module loads, allocator pools): a few runs each way, not timed
@@ -203,21 +207,21 @@ def serve_bench(args):
     serve.serve(warm, budget, batched=True)
     serve.serve(warm, budget, batched=True, graph=True)
     serve.serve(warm[:2], 0, batched=False)
-    specs = serve.make_specs(args.runs, args.run_steps)
+    specs = serve.make_specs(runs, run_steps)
     print(f"[serve] capacity run: {len(specs)} runs queued at t=0", file=sys.stderr, flush=True)
     res, wall = serve.serve(specs, budget, batched=True)
     cap_eager = serve.summarize(res, wall)
     print("[serve] capacity run, batched step replayed as HIP graphs", file=sys.stderr, flush=True)
-    res, wall = serve.serve(serve.make_specs(args.runs, args.run_steps), budget, batched=True, graph=True)
+    res, wall = serve.serve(serve.make_specs(runs, run_steps), budget, batched=True, graph=True)
     cap_graph = serve.summarize(res, wall)
     graph = cap_graph["particle_steps_per_s"] > cap_eager["particle_steps_per_s"]
     cap = cap_graph if graph else cap_eager
     rate = 0.8 * cap["runs_per_s"]
-    specs = serve.poisson_arrivals(serve.make_specs(args.runs, args.run_steps), rate)
+    specs = serve.poisson_arrivals(serve.make_specs(runs, run_steps), rate)
     print(f"[serve] Poisson run at {rate:.2f} runs/s (graph={graph})", file=sys.stderr, flush=True)
     res, wall = serve.serve(specs, budget, batched=True, keep_energies=True, graph=graph)
     mix = serve.summarize(res, wall)
-    base_specs = serve.make_specs(args.runs, args.run_steps)[: args.baseline_runs]
+    base_specs = serve.make_specs(runs, run_steps)[: baseline_runs]
     print(f"[serve] one box at a time: {len(base_specs)} runs", file=sys.stderr, flush=True)
     bres, bwall = serve.serve(base_specs, 0, batched=False)
     base = serve.summarize(bres, bwall)
@@ -240,7 +244,7 @@ def serve_bench(args):
         "value": mix["particle_steps_per_s"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.run_steps,
+        "steps": run_steps,
         "warmup": 0,
         "ms_per_step": None,
         "higher_is_better": True,
@@ -248,8 +252,8 @@ def serve_bench(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"served_2d_{args.runs}runs_{args.run_steps}steps",
-                   "runs": args.runs, "steps_per_run": args.run_steps,
+        "config": {"workload": f"served_2d_{runs}runs_{run_steps}steps",
+                   "runs": runs, "steps_per_run": run_steps,
                    "budget_gb": args.budget_gb, "arrival_rate_runs_per_s": rate,
                    "tiles": {f"{n}^2 ppc{serve.PPC_CLASSES[k][0]}-{serve.PPC_CLASSES[k][1]}":
                              "x".join(map(str, t[:2])) for (n, k), t in sorted(tiles.items())},
@@ -260,7 +264,7 @@ def serve_bench(args):
                    "capacity_over_one_at_a_time": cap["particle_steps_per_s"] / base["particle_steps_per_s"],
                    "alone_vs_mix_max_rel_energy_diff": worst, "alone_vs_mix_runs": len(sample)},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -304,7 +308,7 @@ def main():
               "--gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
     if args.serve:
-        serve_bench(args)
+        print(json.dumps(serve_bench(args)), flush=True)
         return
     from paper_2602_15939_amd import workloads
 
@@ -326,6 +330,18 @@ def main():
                 "ms_per_step": o["ms_per_step"], "steps": o["steps"],
                 "particles": o["config"]["particles"], "gpd_ms": o["config"]["gpd_ms"],
                 "roofline_frac": o["roofline"]["frac"], "autotune_tile": (o["config"]["autotune"] or {}).get("tile")})
+        # a sample of the served batch (its full line: --serve): 128 runs of 250 steps, the
+        # one-box-at-a-time baseline over all of them
+        o = serve_bench(args, runs=128, run_steps=250, baseline_runs=128)
+        c = o["config"]
+        out["other_workloads"].append({
+            "workload": c["workload"], "value": o["value"], "unit": o["unit"],
+            "metric": o["metric"], "p50_latency_s": c["poisson"]["p50_latency_s"],
+            "p99_latency_s": c["poisson"]["p99_latency_s"], "capacity": c["capacity"]["particle_steps_per_s"],
+            "graph": c["graph"], "one_at_a_time": c["one_at_a_time"]["particle_steps_per_s"],
+            "batched_over_one_at_a_time": c["batched_over_one_at_a_time"],
+            "capacity_over_one_at_a_time": c["capacity_over_one_at_a_time"],
+            "alone_vs_mix_max_rel_energy_diff": c["alone_vs_mix_max_rel_energy_diff"]})
     if not args.no_cpu_baseline and w["kind"] == "shear":  # the oracle sample is a shearing box
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         if w["dim"] == 2:  # the small parity box: the oracle runs the timed steps in full

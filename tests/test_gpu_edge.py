@@ -1,7 +1,7 @@
 """Edge cases of the HIP path against the FP64 oracle or against the plain frame:
 empty boxes (no particles: the fields follow the oracle's vacuum Maxwell steps), boxes smaller
 than one tile (a single partial tile), the degenerate frames (shearing box with s = Omega0 = 0,
-expanding box with adot = 0, which reduce to the plain push), and positions on cell edges (the
+expanding box with adot = 0, the combined frame with both, which reduce to the plain push), and positions on cell edges (the
 FP32 offset renormalisation never stores 1.0 and stays within 2e-6 cells of the oracle)."""
 import numpy as np
 import pytest
@@ -18,7 +18,8 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
 
-@pytest.mark.parametrize("dim,frame", [(2, "plain"), (2, "shear"), (3, "shear"), (3, "expand")])
+@pytest.mark.parametrize("dim,frame", [(2, "plain"), (2, "shear"), (3, "shear"), (3, "expand"),
+                                       (2, "shear_expand"), (3, "shear_expand")])
 def test_empty_box_fields_follow_oracle(dim, frame):
     n = (24, 20) if dim == 2 else (16, 12, 8)
     c = Case(dim, n, frame, ppc=0, seed=90 + dim)
@@ -36,7 +37,8 @@ def test_empty_box_fields_follow_oracle(dim, frame):
 
 
 @pytest.mark.parametrize("dim,n,frame", [(2, (10, 6), "shear"), (2, (12, 9), "leaky"),
-                                         (3, (5, 6, 7), "plain"), (3, (7, 5, 6), "shear")])
+                                         (3, (5, 6, 7), "plain"), (3, (7, 5, 6), "shear"),
+                                         (2, (10, 6), "shear_expand"), (3, (7, 5, 6), "shear_expand")])
 def test_box_smaller_than_one_tile(dim, n, frame):
     """Default tiles (16x16, 8^3) larger than the box: one partial tile holds everything."""
     c = Case(dim, n, frame, ppc=4, seed=70 + dim)
@@ -56,9 +58,11 @@ def test_box_smaller_than_one_tile(dim, n, frame):
 
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("frame,kw", [("shear", dict(shear_s=0.0, omega0=0.0)),
-                                      ("expand", dict(adot=0.0))])
+                                      ("expand", dict(adot=0.0)),
+                                      ("shear_expand", dict(shear_s=0.0, omega0=0.0, adot=0.0))])
 def test_degenerate_frame_equals_plain(dim, frame, kw):
-    """With no shear and no rotation, or no expansion, the frame's pusher is the Boris push:
+    """With no shear and no rotation, or no expansion (the combined frame: neither), the
+    frame's pusher is the Boris push:
     momenta, positions and the deposited current equal the plain box's after one step (FP32
     rounding of different formulas), and the expanding box's Maxwell step equals Yee's."""
     n = (40, 36) if dim == 2 else (20, 12, 16)

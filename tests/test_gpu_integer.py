@@ -3,7 +3,7 @@
   * cell indices and FP32 offsets after a push equal, bit for bit, the oracle's FP32 position
     layer applied to the GPU's own old positions and FP32 deposit displacements (the record of
     an unfused push): plain, shearing (with the shear move and the shearing-periodic y shift of
-    x-face crossings), expanding and leaky boxes, 2D and 3D, with particles started on and
+    x-face crossings), expanding, leaky and combined shearing-expanding boxes, 2D and 3D, with particles started on and
     within one ulp of the cell edges and at the x faces moving out of the box;
   * a shearing box whose face flow moves particles a whole cell in y per step latches
     PIC_DERR_CFL, and the oracle's layer flags the same particles;
@@ -61,7 +61,7 @@ def parts_with_edges(n, dim, ppc, theta, seed):
     return out
 
 
-CASES = [(d, f) for f in ("plain", "shear", "expand", "leaky") for d in (2, 3)]
+CASES = [(d, f) for f in ("plain", "shear", "expand", "leaky", "shear_expand") for d in (2, 3)]
 
 
 @pytest.mark.parametrize("dim,frame", CASES)
@@ -73,7 +73,7 @@ def test_cells_and_offsets_bit_exact_against_the_fp32_layer(dim, frame):
         for _ in range(2):
             c.gpu.step()
         c.box.step = 2  # the oracle's layer takes the step for Delta y_s(t^{n+1})
-        if frame == "shear":
+        if frame in ("shear", "shear_expand"):
             dys = oracle.shear_offset(c.box, 3 * c.box.dt)
             assert 0.02 < dys % 1 < 0.98
         c.gpu.sort()

@@ -9,8 +9,9 @@
     PIC_DERR_CFL, and the oracle's layer flags the same particles;
   * continuity rho(x^{n+1}) - rho(x^n) + dt div J = 0 for the expanding box in primed
     coordinates (the deposit gives l J' directly, Sec. 3.1) and for the leaky box;
-  * the shearing box (Sec. 2.2): the comoving deposit x^n -> x' folded through the shearing-
-    periodic x faces at an integer Delta y_s(t^{n+1/2}) conserves charge; the GPU's current is
+  * the shearing box (Sec. 2.2), and the combined frame in primed coordinates: the comoving
+    deposit x^n -> x' folded through the shearing-periodic x faces at an integer
+    Delta y_s(t^{n+1/2}) conserves charge; the GPU's current is
     read after the J' transport, which the test undoes column by column (its linear-
     interpolation weights are well conditioned for the small shifts used here).
 """
@@ -185,7 +186,10 @@ def _untransport(col, d):
     return np.linalg.solve(A, col)
 
 
-def test_continuity_shearing_box_comoving_deposit_through_the_faces():
+@pytest.mark.parametrize("frame,kw", [("shear", {}),
+                                      ("shear_expand", dict(adot=4e-3, axis_mask=0b011))])
+def test_continuity_shearing_box_comoving_deposit_through_the_faces(frame, kw):
+    """The combined frame with x and y expanding: the same, in primed comoving coordinates."""
     n = (40, 36)
     nx, ny = n
     dt, s = 0.45, 1.5
@@ -205,7 +209,7 @@ def test_continuity_shearing_box_comoving_deposit_through_the_faces():
         u[0, :ma] = np.abs(u[0, :ma]) + 0.2  # group A moves outwards
         parts.append(dict(cell=torch.from_numpy((i + nx * j).astype(np.int32)),
                           off=torch.from_numpy(off), u=torch.from_numpy(u)))
-    c = Case(2, n, "shear", parts=parts, shear_s=s, omega0=sO / s, seed=741)
+    c = Case(2, n, frame, parts=parts, shear_s=s, omega0=sO / s, seed=741, **kw)
     try:
         c.gpu.set_step(2)
         c.box.step = 2

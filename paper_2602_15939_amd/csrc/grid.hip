@@ -760,7 +760,7 @@ void ksb_pass3_kernel(KsbDev K)
     const uint32_t aoff = 4u * (uint32_t)(x0 + tid % PX + G.sy * wrapn(y0 - 2 + tid / PX, ny));
     const int aslot = tid + (W0X - PX) * (tid / PX) + 2;
     // extra F^k position, lanes 0..31 of wave 0 (x-halo columns lx = 0, 1, W0X-2, W0X-1 of
-    // F^k) and of waves 13 and 15 (column col, row r of the XR0 opposite-face rows of side 0 and
+    // F^k) and of waves WO0 and WO1 (column col, row r of the XR0 opposite-face rows of side 0 and
     // side 1).  An image position interpolates two values (shift ydys of F^k): lane l + 32
     // loads the second one for lane l.
     uint32_t xoff = 0;
@@ -807,8 +807,8 @@ void ksb_pass3_kernel(KsbDev K)
     const int bslot = bly * W1X + blx;
     const int bgx = x0 + tid % PX;
     const uint32_t boff = 4u * (uint32_t)(bgx + G.sy * wrapn(y0 - 1 + bly, ny));
-    // extra F^{k+1} position (wave 12: the x-halo columns lx = 0, W1X - 1, rows r >> 1 --
-    // interior, or beyond a face an image of the opposite face's values; wave 14: row r of the
+    // extra F^{k+1} position (wave WXB: the x-halo columns lx = 0, W1X - 1, rows r >> 1 --
+    // interior, or beyond a face an image of the opposite face's values; wave WAUX: row r of the
     // opposite face of side cs, one plane ahead)
     int cslot = 0, cs = 0, crow = 0, cgx = 0;
     bool cop = false, cimg = false, caux = false;
@@ -882,8 +882,8 @@ void ksb_pass3_kernel(KsbDev K)
                 if (xslot >= 0) XA[s][xs][c][xslot] = v;
             }
     };
-    // C (first pass: J) of the F^{k+1} positions into Cd: main ones and wave 12's at plane zm,
-    // wave 14's at za
+    // C (first pass: J) of the F^{k+1} positions into Cd: main ones and wave WXB's at plane zm,
+    // wave WAUX's at za
     auto load_c = [&](float* Cd, int zm, int za) {
         const uint32_t pm = plane_of(zm);
         const uint32_t o = bmain ? boff : coff;

@@ -197,9 +197,9 @@ def serve_bench(args, runs=None, run_steps=None, baseline_runs=None):
 
     from paper_2602_15939_amd import serve
 
-    runs = runs if runs is None else runs
-    run_steps = run_steps if run_steps is None else run_steps
-    baseline_runs = baseline_runs if baseline_runs is None else baseline_runs
+    runs = args.runs if runs is None else runs
+    run_steps = args.run_steps if run_steps is None else run_steps
+    baseline_runs = args.baseline_runs if baseline_runs is None else baseline_runs
     budget = int(args.budget_gb * 2**30)
     tiles = serve.tune_tiles(log=lambda m: print(m, file=sys.stderr, flush=True))
     # warm-up (module loads, allocator pools): a few runs each way, not timed

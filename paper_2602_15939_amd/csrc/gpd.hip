@@ -807,9 +807,11 @@ __device__ __attribute__((always_inline)) inline void gpd_body(const StepDev& P,
 }
 
 // 3D tiles: compact regions (48.4 KB of LDS for 8^3) let three workgroups share a CU, so the
-// register budget is set for 6 waves per SIMD.
+// register budget is set for 6 waves per SIMD.  2D tiles of 16x16 and 8x8 (16 KB and less) fit
+// eight waves per SIMD in 64 VGPRs (a few spilled: 2-4 % faster for the leaky box than at the
+// 81-93 VGPRs of no budget); the larger 2D tiles are bound by their LDS first.
 template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 1)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 8)))
 void gpd_kernel(StepDev P, int fuse)
 {
     gpd_body<DIM, TX, TY, TZ, FRAME, NT>(P, (int)blockIdx.x, (int)gridDim.x, fuse);
@@ -817,7 +819,7 @@ void gpd_kernel(StepDev P, int fuse)
 
 // Many boxes in one launch: the blocks of unit u (one box's tiles) take its descriptor.
 template <int DIM, int TX, int TY, int TZ, int FRAME, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 1)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 8)))
 void gpd_batch(const StepDev* __restrict__ t, UnitMap m)
 {
     const int u = unit_of(m, (int)blockIdx.x);

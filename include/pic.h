@@ -69,10 +69,10 @@ enum pic_leaky_mode { PIC_LEAKY_DISPLACEMENT = 0, PIC_LEAKY_PROBABILISTIC = 1 };
 #define PIC_STEP_GRAPH 2u   /* the batched step as a captured HIP graph, replayed while the box
                                set and its launch shapes stay the same (implies BATCHED) */
 /* pic_tile_sort flags */
-#define PIC_SORT_OVERLAP 1u /* run the sort on a second stream of the box, after the work queued
-                               on the box stream so far (the push that wrote the positions), so
-                               that it overlaps the current fold and the Maxwell step queued
-                               after it; the next call that reads or writes particles or the sort
+#define PIC_SORT_OVERLAP 1u /* run the sort of each species on a stream of its own (the species'
+                               sorts side by side), after the work queued on the box stream so
+                               far (the push that wrote the positions), so that it overlaps the
+                               current fold and the Maxwell step queued after it; the next call that reads or writes particles or the sort
                                (push, deposit, sort, escape compaction, particle and sort copies,
                                pic_box_get, pic_step, pic_autotune, the histogram) first waits for
                                it; pic_shear_remap, pic_maxwell_step and the field and current

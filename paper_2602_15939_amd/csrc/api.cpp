@@ -157,10 +157,11 @@ struct pic_box {
     bool sorted = false;
     bool deposit_pending = false;
     bool record_valid = false;  // the unfused-deposit workspace holds the last push's record
-    // PIC_SORT_OVERLAP: a sort on a second stream of the box, joined by the next call that
-    // touches particles or the sort (default priority, created on first use)
-    hipStream_t side = nullptr;
-    hipEvent_t fork_ev = nullptr, side_ev = nullptr;
+    // PIC_SORT_OVERLAP: the sort of each species on a stream of its own beside the box stream,
+    // joined by the next call that touches particles or the sort (default priority, created
+    // on first use)
+    hipStream_t side[kMaxSpecies] = {};
+    hipEvent_t fork_ev = nullptr, side_ev[kMaxSpecies] = {};
     bool side_pending = false;
     bool track_ids = false;
     bool caller_mem = false;  // created on caller memory (pic_box_mem): never allocates
@@ -183,12 +184,14 @@ constexpr int kRowAlign = 32;  // floats per 128-byte line
 
 int32_t hip_fail(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EDEVICE; }
 
-// make the box stream wait for a sort queued on the side stream (PIC_SORT_OVERLAP)
+// make the box stream wait for the sorts queued on the side streams (PIC_SORT_OVERLAP)
 int32_t side_join(pic_box* b)
 {
     if (!b->side_pending) return PIC_OK;
     b->side_pending = false;
-    return hip_fail(hipStreamWaitEvent(b->st, b->side_ev, 0));
+    for (int s = 0; s < b->nsp; s++)
+        if (hipStreamWaitEvent(b->st, b->side_ev[s], 0) != hipSuccess) return PIC_EDEVICE;
+    return PIC_OK;
 }
 
 // the leaky box's escape rule applies: always in the leaky frame, on request in the others
@@ -470,27 +473,34 @@ int max_tiles(int dim, const int n[3])
     return m;
 }
 
+// the tile sort of species s, queued on stream st (the species' buffers only: the sorts of
+// different species may run at the same time)
+int32_t sort_species(pic_box* b, int s, hipStream_t st)
+{
+    Species& S = b->sp[s];
+    hipError_t e;
+    if (b->mig_ok && S.grouped) {
+        const int nxt = S.toff_cur ^ 1;
+        e = migrate_sort(S.cell[S.cur], S.toff[S.toff_cur], S.n_upper, b->cc, b->tl, b->mg, S.sb,
+                         S.toff[nxt], S.n_live, S.which, b->ctr + 2, S.counts_ready, st);
+        S.toff_cur = nxt;
+        b->n_migrations++;
+    } else {
+        e = tile_sort(S.cell[S.cur], S.n_live, S.n_upper, b->cc, b->tl, S.sb, S.toff[S.toff_cur],
+                      S.n_live, S.which, st);
+    }
+    if (e != hipSuccess) return PIC_EDEVICE;
+    S.grouped = false;
+    S.counts_ready = false;
+    return PIC_OK;
+}
+
 int32_t sort_box(pic_box* b)
 {
     if (b->deposit_pending) return PIC_ESTATE;  // the unfused deposit reads this sort's slots
     if (side_join(b)) return PIC_EDEVICE;
-    for (int s = 0; s < b->nsp; s++) {
-        Species& S = b->sp[s];
-        hipError_t e;
-        if (b->mig_ok && S.grouped) {
-            const int nxt = S.toff_cur ^ 1;
-            e = migrate_sort(S.cell[S.cur], S.toff[S.toff_cur], S.n_upper, b->cc, b->tl, b->mg,
-                             S.sb, S.toff[nxt], S.n_live, S.which, b->ctr + 2, S.counts_ready, b->st);
-            S.toff_cur = nxt;
-            b->n_migrations++;
-        } else {
-            e = tile_sort(S.cell[S.cur], S.n_live, S.n_upper, b->cc, b->tl, S.sb,
-                          S.toff[S.toff_cur], S.n_live, S.which, b->st);
-        }
-        if (e != hipSuccess) return PIC_EDEVICE;
-        S.grouped = false;
-        S.counts_ready = false;
-    }
+    for (int s = 0; s < b->nsp; s++)
+        if (sort_species(b, s, b->st)) return PIC_EDEVICE;
     b->sorted = true;
     return PIC_OK;
 }
@@ -1610,12 +1620,14 @@ int32_t pic_box_destroy(pic_box* b)
 {
     if (!b) return PIC_OK;
     hipStreamSynchronize(b->st);
-    if (b->side) {
-        hipStreamSynchronize(b->side);
-        hipStreamDestroy(b->side);
+    for (int s = 0; s < kMaxSpecies; s++) {
+        if (b->side[s]) {
+            hipStreamSynchronize(b->side[s]);
+            hipStreamDestroy(b->side[s]);
+        }
+        if (b->side_ev[s]) hipEventDestroy(b->side_ev[s]);
     }
     if (b->fork_ev) hipEventDestroy(b->fork_ev);
-    if (b->side_ev) hipEventDestroy(b->side_ev);
     stager_release(b->stager);
     for (auto& a : b->allocs) lib_free(a.first, a.second);
     delete b;
@@ -1866,23 +1878,25 @@ int32_t pic_tile_sort(pic_box* const* boxes, int32_t nb, uint32_t flags)
             r = sort_box(b);
             continue;
         }
-        // fork: the side stream takes over after the work queued so far (the push that wrote
-        // the positions); the sort's kernels run there; the join is left to the next call
-        // that touches particles or the sort
+        // fork: each species' side stream takes over after the work queued so far (the push
+        // that wrote the positions); the species' sorts run there, side by side; the join is
+        // left to the next call that touches particles or the sort
         if (b->deposit_pending) return PIC_ESTATE;
         if (side_join(b)) return PIC_EDEVICE;
         // created on first use (each that is still missing, so a failed creation is retried)
-        if ((!b->side && hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) ||
-            (!b->fork_ev && hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) ||
-            (!b->side_ev && hipEventCreateWithFlags(&b->side_ev, hipEventDisableTiming) != hipSuccess))
+        if (!b->fork_ev && hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess)
             return PIC_EDEVICE;
-        if (hipEventRecord(b->fork_ev, b->st) != hipSuccess || hipStreamWaitEvent(b->side, b->fork_ev, 0) != hipSuccess)
-            return PIC_EDEVICE;
-        hipStream_t main = b->st;
-        b->st = b->side;
-        r = sort_box(b);
-        b->st = main;
-        if (hipEventRecord(b->side_ev, b->side) != hipSuccess) return PIC_EDEVICE;
+        for (int s = 0; s < b->nsp; s++)
+            if ((!b->side[s] && hipStreamCreateWithFlags(&b->side[s], hipStreamNonBlocking) != hipSuccess) ||
+                (!b->side_ev[s] && hipEventCreateWithFlags(&b->side_ev[s], hipEventDisableTiming) != hipSuccess))
+                return PIC_EDEVICE;
+        if (hipEventRecord(b->fork_ev, b->st) != hipSuccess) return PIC_EDEVICE;
+        for (int s = 0; s < b->nsp; s++) {
+            if (hipStreamWaitEvent(b->side[s], b->fork_ev, 0) != hipSuccess ||
+                sort_species(b, s, b->side[s]) != PIC_OK || hipEventRecord(b->side_ev[s], b->side[s]) != hipSuccess)
+                return PIC_EDEVICE;
+        }
+        b->sorted = true;
         b->side_pending = true;
     }
     return r;

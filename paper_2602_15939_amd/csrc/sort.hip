@@ -560,9 +560,10 @@ __device__ __attribute__((always_inline)) inline void scan_small_body(const Scan
 }
 PIC_BATCHED_KERNEL(scan_small, ScanArgs, kBlock)
 
+// the box's count of radix fallbacks (the sorts of two species may add at the same time)
 __global__ void count_fallback_kernel(unsigned long long* ctr, Gate g)
 {
-    if (!g.off()) ctr[0] += 1ull;
+    if (!g.off()) atomicAdd(ctr, 1ull);
 }
 
 hipError_t sort_batch(SortBatchKind k, const void* table, UnitMap m, int blocks, hipStream_t st)

@@ -1,7 +1,8 @@
 """Whole steps against the oracle on grids of more cells than one pass of the capped grid-stride
 launches covers (4096 blocks x 256 threads = 1,048,576 cells), so that their threads loop: the
-shearing box's J' transport and x fold (and its staged Maxwell sweeps, x = 128), and the
-expanding box's Yee updates.  Particles within 2e-6, current and fields within 1e-5 of their
+shearing box's J' transport and x fold (and its staged Maxwell sweeps, x = 128), the
+expanding box's Yee updates, and the combined frame's field scaling around its one-thread-per-
+cell sweeps.  Particles within 2e-6, current and fields within 1e-5 of their
 maximum, as the small-grid parity tests."""
 import numpy as np
 import pytest
@@ -19,7 +20,8 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
 
-@pytest.mark.parametrize("frame,kw", [("shear", dict(omega0=0.004)), ("expand", dict(adot=2e-3, axis_mask=0b011))])
+@pytest.mark.parametrize("frame,kw", [("shear", dict(omega0=0.004)), ("expand", dict(adot=2e-3, axis_mask=0b011)),
+                                      ("shear_expand", dict(omega0=0.004, adot=2e-3, axis_mask=0b011))])
 def test_step_on_a_grid_larger_than_one_stride_pass(frame, kw):
     print(f"[grid-stride] {frame} {N}", flush=True)
     c = Case(3, N, frame, ppc=1, seed=81, maxwell_iters=8, **kw)
